@@ -1,0 +1,168 @@
+"""Seeded synthetic multichannel STFT mixtures for the two-source full-rank
+spatial covariance model (Section 2 of the FastFCA paper): y = x1 + x2 with
+x_j(n,f) ~ CN(0, v_j(n,f) R_j(f)), R_j Hermitian positive definite and v_j > 0.
+
+This module only draws inputs. It holds none of the EM arithmetic and is the
+one piece shared by the CPU oracle tests, the GPU tests and the benchmark.
+All arrays use the layout y[f, n, m], R[j, f, m, m'], v[j, f, n],
+x[j, f, n, m]; complex Gaussian means E[z z^H] = I with z = (a + ib)/sqrt(2).
+
+Workloads
+---------
+* ``random``  : R_j(f) = A A^H + 0.1 I with A an M x M matrix of i.i.d.
+  CN(0,1) entries drawn independently per source and frequency;
+  v_j(n,f) ~ Gamma(shape 0.5, scale 1) i.i.d.; complex128.
+* ``array``   : a uniform linear array (spacing 4 cm, c = 343 m/s,
+  fs = 16 kHz). R_j(f) = a_j(f) a_j(f)^H + 0.1 Gamma(f), with a_j the
+  steering vector of a direction of arrival drawn uniformly in [0, pi)
+  once per source, and Gamma(f) the spherically isotropic (sinc) diffuse
+  coherence. Bin k sits at k * fs / (2 (F - 1)) Hz. y is rounded to
+  complex64 when ``complex64=True``.
+The paper's own data (speech convolved with measured room responses) is not
+available; these draws stand in for it with the paper's STFT shape (F = 513
+bins of a 1024-point frame at 16 kHz).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+FS_HZ = 16000.0
+MIC_SPACING_M = 0.04
+SOUND_SPEED_MPS = 343.0
+
+
+def cn(rng: np.random.Generator, shape) -> np.ndarray:
+    """Standard circular complex Gaussian CN(0, 1) samples."""
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+
+
+@dataclass
+class Mixture:
+    y: np.ndarray        # [F, N, M] complex observed mixture
+    R: np.ndarray        # [2, F, M, M] true spatial covariances
+    v: np.ndarray        # [2, F, N] true source powers
+    x: np.ndarray        # [2, F, N, M] true source images
+    theta: np.ndarray | None = None  # DOAs of the array workload (radians)
+
+    @property
+    def shape(self):
+        F, N, M = self.y.shape
+        return M, F, N
+
+
+def bin_frequencies_hz(F: int, fs: float = FS_HZ) -> np.ndarray:
+    """Centre frequency of STFT bins 0..F-1 (DC .. Nyquist inclusive)."""
+    if F == 1:
+        return np.zeros(1)
+    return np.arange(F) * fs / (2.0 * (F - 1))
+
+
+def steering_vectors(theta: float, M: int, F: int, d: float = MIC_SPACING_M,
+                     c: float = SOUND_SPEED_MPS, fs: float = FS_HZ) -> np.ndarray:
+    """[F, M] far-field ULA steering vectors, microphone 1 as phase reference."""
+    fhz = bin_frequencies_hz(F, fs)
+    m = np.arange(M)
+    return np.exp(-2j * np.pi * fhz[:, None] * m[None, :] * d * np.cos(theta) / c)
+
+
+def diffuse_coherence(M: int, F: int, d: float = MIC_SPACING_M,
+                      c: float = SOUND_SPEED_MPS, fs: float = FS_HZ) -> np.ndarray:
+    """[F, M, M] spherically isotropic coherence sin(x)/x, x = 2 pi f |m-m'| d / c."""
+    fhz = bin_frequencies_hz(F, fs)
+    dist = np.abs(np.arange(M)[:, None] - np.arange(M)[None, :]) * d
+    arg = 2.0 * np.pi * fhz[:, None, None] * dist[None, :, :] / c
+    return np.sinc(arg / np.pi)  # numpy sinc is sin(pi x)/(pi x)
+
+
+def random_covariances(rng: np.random.Generator, M: int, F: int) -> np.ndarray:
+    A = cn(rng, (2, F, M, M))
+    return A @ np.conj(np.swapaxes(A, -1, -2)) + 0.1 * np.eye(M)
+
+
+def array_covariances(theta: np.ndarray, M: int, F: int) -> np.ndarray:
+    G = diffuse_coherence(M, F)
+    R = np.empty((2, F, M, M), dtype=np.complex128)
+    for j in range(2):
+        a = steering_vectors(float(theta[j]), M, F)
+        R[j] = a[:, :, None] * np.conj(a[:, None, :]) + 0.1 * G
+    return R
+
+
+def _sqrt_factor(R: np.ndarray, method: str) -> np.ndarray:
+    """A factor B with B B^H = R (Cholesky, or the PSD eigen square root)."""
+    if method == "chol":
+        return np.linalg.cholesky(R)
+    w, U = np.linalg.eigh(R)
+    return U * np.sqrt(np.clip(w, 0.0, None))[..., None, :]
+
+
+def draw_images(R: np.ndarray, v: np.ndarray, z: np.ndarray, method: str) -> np.ndarray:
+    """x_j(n,f) = sqrt(v_j(n,f)) B_j(f) z_j(n,f) so that E[x x^H] = v_j R_j."""
+    B = _sqrt_factor(R, method)                       # [2, F, M, M]
+    x = np.einsum("jfab,jfnb->jfna", B, z)
+    return x * np.sqrt(v)[..., None]
+
+
+def random_mixture(M: int = 2, F: int = 257, N: int = 200, seed: int = 0) -> Mixture:
+    """The ``random`` workload. Draw order: A, then v, then z."""
+    rng = np.random.default_rng(seed)
+    R = random_covariances(rng, M, F)
+    v = rng.gamma(0.5, 1.0, size=(2, F, N))
+    z = cn(rng, (2, F, N, M))
+    x = draw_images(R, v, z, "chol")
+    return Mixture(y=x[0] + x[1], R=R, v=v, x=x)
+
+
+def array_mixture(M: int = 4, F: int = 513, N: int = 1000, seed: int = 1,
+                  complex64: bool = True, v: np.ndarray | None = None) -> Mixture:
+    """The ``array`` workload. Draw order: both DOAs, then v, then z.
+
+    ``v`` may be supplied (e.g. a temporally correlated draw); it is then
+    used instead of the Gamma draw, and the DOAs and z are drawn as usual.
+    """
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(0.0, np.pi, size=2)
+    R = array_covariances(theta, M, F)
+    vg = rng.gamma(0.5, 1.0, size=(2, F, N))
+    if v is None:
+        v = vg
+    z = cn(rng, (2, F, N, M))
+    x = draw_images(R, v, z, "eig")
+    y = x[0] + x[1]
+    if complex64:
+        y = y.astype(np.complex64)
+    return Mixture(y=y, R=R, v=v, x=x, theta=theta)
+
+
+def ar1_log_powers(rng: np.random.Generator, F: int, N: int, rho: float = 0.9) -> np.ndarray:
+    """[2, F, N] source powers whose logs follow a stationary AR(1) in n with
+    coefficient rho, mean and variance matched to log Gamma(0.5, 1):
+    E[log v] = digamma(0.5), Var[log v] = trigamma(0.5) = pi^2 / 2."""
+    mu = -1.9635100260214235          # digamma(0.5) = -gamma - 2 log 2
+    var = np.pi ** 2 / 2.0
+    sd_e = np.sqrt(var * (1.0 - rho * rho))
+    lv = np.empty((2, F, N))
+    lv[:, :, 0] = mu + np.sqrt(var) * rng.standard_normal((2, F))
+    e = sd_e * rng.standard_normal((2, F, N))
+    for n in range(1, N):
+        lv[:, :, n] = mu + rho * (lv[:, :, n - 1] - mu) + e[:, :, n]
+    return np.exp(lv)
+
+
+def condition_numbers(R: np.ndarray) -> np.ndarray:
+    """[F] max_j cond_2(R_j(f)) of the true covariances (a data property used
+    to decide which bins a finite-precision comparison is meaningful on)."""
+    w = np.linalg.eigvalsh(R)                         # [2, F, M] ascending
+    with np.errstate(divide="ignore"):
+        k = w[..., -1] / np.where(w[..., 0] > 0, w[..., 0], 0.0)
+    return np.max(k, axis=0)
+
+
+def default_initial_covariances(M: int, F: int) -> np.ndarray:
+    """R1 = I and R2 = I + 0.5 e1 e1^H at every bin (the plain start)."""
+    R0 = np.zeros((2, F, M, M), dtype=np.complex128)
+    R0[:] = np.eye(M)
+    R0[1, :, 0, 0] += 0.5
+    return R0
