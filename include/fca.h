@@ -1,0 +1,159 @@
+/*
+ * fca.h -- C ABI of the MI355X (gfx950) FastFCA EM library, libfca.so.
+ *
+ * The library estimates the two-source full-rank spatial covariance model
+ * of Ito, Araki & Nakatani, "FastFCA" (arXiv:1805.06572), Section 2:
+ *     y(n,f) = x1(n,f) + x2(n,f),   x_j(n,f) ~ CN(0, v_j(n,f) R_j(f)),
+ * with R_j(f) Hermitian positive definite (the paper's S_j(f)) and
+ * v_j(n,f) > 0, by the FastFCA EM of Section 3 (Algorithm 1): a per-
+ * frequency generalized eigendecomposition jointly diagonalises R1 and R2,
+ * so every time-frequency bin is updated with scalar arithmetic.
+ *
+ * Conventions for every entry point
+ *  - Every call returns an fca_status; nothing throws across the ABI and
+ *    nothing aborts. Calls are stream-ordered on the stream given at init
+ *    and synchronous on return.
+ *  - Complex numbers are interleaved (real, imaginary): complex128 in
+ *    FCA_FP64 mode, complex64 in FCA_FP32_BULK mode. "prec real" means
+ *    double in FCA_FP64 mode and float in FCA_FP32_BULK mode.
+ *  - Pointers may be host or device memory unless stated otherwise; the
+ *    library tells them apart with hipPointerGetAttributes. Every output
+ *    buffer is allocated and owned by the caller.
+ *  - Matrices are row-major; element (m, m') of an M x M matrix is at
+ *    m * M + m'.
+ *  - A context is not thread-safe. Different contexts are independent.
+ */
+#ifndef FCA_H
+#define FCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fca_ctx fca_ctx;
+
+typedef enum {
+    FCA_OK = 0,
+    FCA_E_ARG = -1,       /* invalid argument; nothing was changed or allocated */
+    FCA_E_NOMEM = -2,     /* a device or pinned-host allocation failed */
+    FCA_E_DEVICE = -3,    /* a HIP runtime call or kernel launch failed */
+    FCA_E_NOT_PD = -4,    /* some frequency lost positive definiteness (see flags) */
+    FCA_E_NONFINITE = -5, /* some frequency produced a non-finite value (see flags) */
+    FCA_E_STATE = -6      /* the context is unusable after an earlier device error */
+} fca_status;
+
+typedef enum {
+    FCA_FP64 = 0,      /* everything in double precision */
+    FCA_FP32_BULK = 1  /* per-bin arithmetic in float; the generalized eigen-
+                          decomposition, every cross-thread sum and the log-
+                          likelihood sums in double */
+} fca_precision;
+
+/* Per-frequency status bits (fca_status_per_freq). A frequency with
+ * FCA_FLAG_NOT_PD or FCA_FLAG_NONFINITE is frozen at its last complete
+ * iterate theta^(l): later iterations leave it unchanged and report the
+ * log-likelihood of that iterate. Other frequencies are unaffected. */
+#define FCA_FLAG_NOT_PD 1    /* a Cholesky pivot of R2 (or its eigenbasis
+                                form) was not positive */
+#define FCA_FLAG_NONFINITE 2 /* a power or covariance entry was non-finite or
+                                a power was not positive */
+#define FCA_FLAG_SWEEPS 4    /* the Jacobi eigen-solver stopped at its sweep
+                                limit (informational; not frozen) */
+
+/* One mixture (Section 2, problem statement).
+ *   M        microphones (the paper's I), 1 <= M <= 8
+ *   F        frequency bins (DC .. Nyquist), F >= 1
+ *   N        frames, 1 <= N <= 2048
+ *   prec     an fca_precision
+ *   y        observed STFT mixture y(n,f), complex (prec), element (f,n,m)
+ *            at y + f*y_stride_f + n*y_stride_n + m*y_stride_m, strides in
+ *            complex elements and >= 0 (torch.stft's [m][f][n] and the
+ *            natural [f][n][m] both fit); copied into the context by
+ *            fca_init, so the caller may free it afterwards.
+ *   R0       optional initial spatial covariances, [2][F][M][M] complex128
+ *            (R_1 then R_2), Hermitian positive definite (only the upper
+ *            triangle is read); NULL selects R1 = I, R2 = I + 0.5 e1 e1^H.
+ *   v0       optional initial powers, [2][F][N] prec real, > 0; NULL selects
+ *            v_j(n,f) = ||y(n,f)||^2 / M for both sources, floored at 1e-12
+ *            times the mean of ||y||^2 / M over all bins (1 if that mean is
+ *            zero). R0 and v0 are copied at init.
+ *   stream   hipStream_t for all work of the context; NULL = null stream. */
+typedef struct {
+    int32_t M, F, N;
+    int32_t prec;
+    const void *y;
+    int64_t y_stride_f, y_stride_n, y_stride_m;
+    const double *R0;
+    const void *v0;
+    void *stream;
+} fca_problem;
+
+/* Create a context for one mixture, copy y, R0, v0 into device memory and
+ * set the initial values (Algorithm 1, step 1): v^(0) and the generalized
+ * eigenvectors P^(0) and eigenvalues Lambda^(0) of (R1^(0), R2^(0)).
+ * Returns FCA_E_ARG (and *out = NULL) for invalid sizes, pointers or an R0
+ * that is not positive definite. */
+fca_status fca_init(const fca_problem *p, fca_ctx **out);
+
+/* As fca_init for B >= 1 mixtures processed together. All mixtures share F,
+ * prec and stream; M and N may differ per mixture. Batch outputs below are
+ * the per-mixture outputs concatenated in mixture order. */
+fca_status fca_init_batch(const fca_problem *p, int32_t B, fca_ctx **out);
+
+/* Set the initial values again from the R0 and v0 given at init (or the
+ * plain start), clearing all per-frequency flags (Algorithm 1, step 1).
+ * Allocates nothing. */
+fca_status fca_reset(fca_ctx *c);
+
+/* Run `iters` >= 0 EM iterations (Algorithm 1, steps 3-9) on every mixture.
+ *   loglik  NULL, or [B][iters] doubles: the log-likelihood (eq. like,
+ *           summed over all bins of the mixture) of theta^(l) at the start
+ *           of iteration l. With iters == 0 nothing is updated and
+ *           loglik[b] receives the log-likelihood of the current parameters.
+ *   R_out   NULL, or [2][F][M][M] complex128 per mixture: R_j(f) of the
+ *           parameters after the call, recovered as R2 = (P P^H)^-1 and
+ *           R1 = P^-H Lambda P^-1 (eq. recoverS).
+ *   v_out   NULL, or [2][F][N] prec real per mixture: v_j(n,f) after the call.
+ * Returns FCA_E_NOT_PD or FCA_E_NONFINITE when some frequency is flagged
+ * (all outputs are still written; see fca_status_per_freq). */
+fca_status fca_em_step(fca_ctx *c, int32_t iters, double *loglik, double *R_out, void *v_out);
+
+/* MMSE source images with the current parameters (eq. MMSE; Algorithm 1,
+ * step 11): x_out is [2][F][N][M] complex (prec) per mixture, x1 then x2,
+ * with x1 = P^-H mu~1 computed in the eigenbasis and x2 = y - x1. */
+fca_status fca_separate(fca_ctx *c, void *x_out);
+
+/* Copy the per-frequency FCA_FLAG_* bits, [B][F] int32, to flags. */
+fca_status fca_status_per_freq(const fca_ctx *c, int32_t *flags);
+
+/* Text of the last error of the context (or of the last failed fca_init when
+ * c is NULL). The string stays valid until the next call on the context. */
+const char *fca_last_error(const fca_ctx *c);
+
+/* Free the context and all its device memory. NULL is accepted. */
+void fca_destroy(fca_ctx *c);
+
+/* Batched generalized eigendecomposition of Hermitian-definite pencils in
+ * FP64 (eq. GEVD and the Appendix theorem): for each of `count` problems,
+ * P^H S2 P = I and P^H S1 P = diag(lambda). S1, S2, P are [count][M][M]
+ * complex128 and lambda [count] x M doubles, all DEVICE pointers; only the
+ * upper triangles of S1 and S2 are read; eigenvalue order is unspecified.
+ * flags [count] int32 device pointer receives FCA_FLAG_* bits (NOT_PD if
+ * S2 is not positive definite). 1 <= M <= 8. stream as in fca_problem. */
+fca_status fca_gevd(int32_t M, int32_t count, const double *S1, const double *S2, double *P,
+                    double *lambda, int32_t *flags, void *stream);
+
+/* Kernel timing of the EM iterations. enable != 0 makes later fca_em_step
+ * calls record HIP events, on the context's stream, around the launches of
+ * the EM-iteration kernel. On return *em_kernel_ms and *em_launches hold the
+ * totals accumulated since the previous fca_timing call (either may be
+ * NULL), and the totals restart from zero. */
+fca_status fca_timing(fca_ctx *c, int32_t enable, double *em_kernel_ms, int64_t *em_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCA_H */

@@ -1,0 +1,586 @@
+// fca_api.hip -- host runtime of libfca: the C ABI declared in include/fca.h.
+//
+// A context owns, in device memory: the mixtures in the EM layout
+// y_int[f][m][n] (complex, row pitch npad = N rounded up to 64), the powers
+// v[j][f][n] (same pitch), the per-frequency state P (M x M complex FP64,
+// stride 64 entries), Lambda (stride 8), log|det P|^2 and status flags, the
+// initial values for fca_reset, and the per-iteration log-likelihood of every
+// (mixture, frequency). The EM problems are sorted into launch groups of equal
+// (M, frames per thread), largest N first, and each group is one launch of
+// the per-frequency EM kernel per chunk of iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fca.h"
+#include "fca_internal.h"
+
+using namespace fca;
+
+namespace {
+
+constexpr int kLChunk = 128;  // iterations per EM launch (log-likelihood buffer depth)
+
+struct MixInfo {
+    int M, N, npad, fpt;
+    int64_t y_base;   // complex elements into y
+    int64_t v_base;   // reals into v (and v_init)
+    int64_t R_base;   // complex128 elements into R_init
+    int64_t out_R;    // complex128 elements into a batch R_out
+    int64_t out_v;    // reals into a batch v_out
+    int64_t out_x;    // complex elements into a batch x_out
+    int pid0;         // first problem index (b * F)
+    bool has_v0;
+};
+
+struct Group {
+    int M, fpt, first, count, max_n;
+};
+
+thread_local std::string g_init_error;
+
+}  // namespace
+
+struct fca_ctx {
+    int B = 0, F = 0;
+    bool fp64 = true;
+    hipStream_t stream = nullptr;
+    size_t esz = 16, rsz = 8;
+    std::vector<MixInfo> mix;
+    std::vector<Group> groups;
+    int nprob = 0;
+
+    void* y = nullptr;
+    void* v = nullptr;
+    void* v_init = nullptr;
+    double2* R_init = nullptr;
+    double2* P = nullptr;
+    double* lam = nullptr;
+    double* logdet = nullptr;
+    int* flags = nullptr;
+    double* ll = nullptr;
+    double* ll_tot = nullptr;
+    double* ll_host = nullptr;  // pinned
+    double* fsum = nullptr;
+    double2* R_stage = nullptr;
+    EmProblem* probs = nullptr;
+    int64_t* x_off = nullptr;
+    std::vector<int> flags_host;
+
+    bool broken = false;
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double em_ms = 0.0;
+    int64_t em_launches = 0;
+    std::string err;
+};
+
+namespace {
+
+void set_err(fca_ctx* c, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_init_error = buf;
+}
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // an unregistered host pointer is not an error here
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged || a.isManaged;
+}
+
+#define FCA_HIP(c, call)                                                                 \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            set_err((c), "%s failed: %s", #call, hipGetErrorString(e_));                 \
+            if (c) (c)->broken = true;                                                   \
+            return FCA_E_DEVICE;                                                         \
+        }                                                                                \
+    } while (0)
+
+template <typename P>
+fca_status dev_alloc(fca_ctx* c, P** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, "hipMalloc of %zu bytes failed", bytes);
+        *p = nullptr;
+        return FCA_E_NOMEM;
+    }
+    return FCA_OK;
+}
+
+void free_ctx_memory(fca_ctx* c) {
+    void* dev[] = {c->y, c->v, c->v_init, c->R_init, c->P, c->lam, c->logdet, c->flags, c->ll,
+                   c->ll_tot, c->fsum, c->R_stage, c->probs, c->x_off};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    if (c->ll_host) (void)hipHostFree(c->ll_host);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+}
+
+int frames_per_thread(int N) {
+    int fpt = 1;
+    while (fpt * kEmThreads < N) fpt *= 2;
+    return fpt;
+}
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+fca_status validate(const fca_problem* p, int b, const fca_problem* p0) {
+    if (!p) { set_err(nullptr, "problem %d is NULL", b); return FCA_E_ARG; }
+    if (p->M < 1 || p->M > kMaxM) { set_err(nullptr, "problem %d: M=%d outside 1..%d", b, p->M, kMaxM); return FCA_E_ARG; }
+    if (p->F < 1) { set_err(nullptr, "problem %d: F=%d < 1", b, p->F); return FCA_E_ARG; }
+    if (p->N < 1 || p->N > kMaxFrames) {
+        set_err(nullptr, "problem %d: N=%d outside 1..%d", b, p->N, kMaxFrames);
+        return FCA_E_ARG;
+    }
+    if (p->prec != FCA_FP64 && p->prec != FCA_FP32_BULK) { set_err(nullptr, "problem %d: bad prec %d", b, p->prec); return FCA_E_ARG; }
+    if (!p->y) { set_err(nullptr, "problem %d: y is NULL", b); return FCA_E_ARG; }
+    if (p->y_stride_f < 0 || p->y_stride_n < 0 || p->y_stride_m < 0) {
+        set_err(nullptr, "problem %d: negative y stride", b);
+        return FCA_E_ARG;
+    }
+    if (p0 && (p->F != p0->F || p->prec != p0->prec || p->stream != p0->stream)) {
+        set_err(nullptr, "problem %d: F, prec and stream must match problem 0", b);
+        return FCA_E_ARG;
+    }
+    return FCA_OK;
+}
+
+// Initial values (Algorithm 1, step 1) for every mixture.
+fca_status do_reset(fca_ctx* c) {
+    const hipStream_t s = c->stream;
+    for (int b = 0; b < c->B; ++b) {
+        const MixInfo& mi = c->mix[b];
+        char* v = static_cast<char*>(c->v) + mi.v_base * c->rsz;
+        if (mi.has_v0) {
+            FCA_HIP(c, hipMemcpyAsync(v, static_cast<char*>(c->v_init) + mi.v_base * c->rsz,
+                                      2ull * c->F * mi.npad * c->rsz, hipMemcpyDeviceToDevice, s));
+        } else {
+            const void* yb = static_cast<char*>(c->y) + mi.y_base * c->esz;
+            FCA_HIP(c, launch_power_sums(c->fp64, yb, mi.M, c->F, mi.N, mi.npad, c->fsum + mi.pid0, s));
+            FCA_HIP(c, launch_default_v(c->fp64, yb, c->fsum + mi.pid0, mi.M, c->F, mi.N, mi.npad, v, s));
+        }
+        const int64_t mm = (int64_t)mi.M * mi.M;
+        const double2* R1 = c->R_init + mi.R_base;
+        const double2* R2 = R1 + (int64_t)c->F * mm;
+        FCA_HIP(c, launch_gevd(mi.M, c->F, R1, R2, mm, mm, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM,
+                               kMaxM * kMaxM, c->lam + (int64_t)mi.pid0 * kMaxM, kMaxM,
+                               c->logdet + mi.pid0, c->flags + mi.pid0, s));
+    }
+    FCA_HIP(c, hipMemcpyAsync(c->flags_host.data(), c->flags, sizeof(int) * c->nprob,
+                              hipMemcpyDeviceToHost, s));
+    FCA_HIP(c, hipStreamSynchronize(s));
+    for (int i = 0; i < c->nprob; ++i) {
+        if (c->flags_host[i] & kFreezeMask) {
+            set_err(c, "initial R2 (or R1) not positive definite at mixture %d, frequency %d",
+                    i / c->F, i % c->F);
+            return FCA_E_NOT_PD;
+        }
+    }
+    // the sweep-limit bit of the initial eigendecomposition is not kept
+    FCA_HIP(c, hipMemsetAsync(c->flags, 0, sizeof(int) * c->nprob, s));
+    FCA_HIP(c, hipStreamSynchronize(s));
+    return FCA_OK;
+}
+
+fca_status check_flags(fca_ctx* c) {
+    const hipStream_t s = c->stream;
+    FCA_HIP(c, hipMemcpyAsync(c->flags_host.data(), c->flags, sizeof(int) * c->nprob,
+                              hipMemcpyDeviceToHost, s));
+    FCA_HIP(c, hipStreamSynchronize(s));
+    fca_status st = FCA_OK;
+    for (int i = 0; i < c->nprob; ++i) {
+        const int f = c->flags_host[i];
+        if (f & kFlagNotPD) {
+            if (st == FCA_OK) set_err(c, "mixture %d, frequency %d lost positive definiteness", i / c->F, i % c->F);
+            st = FCA_E_NOT_PD;
+            break;
+        }
+        if ((f & kFlagNonFinite) && st == FCA_OK) {
+            set_err(c, "mixture %d, frequency %d produced a non-finite value", i / c->F, i % c->F);
+            st = FCA_E_NONFINITE;
+        }
+    }
+    return st;
+}
+
+fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
+    const fca_problem& p0 = probs[0];
+    for (int b = 0; b < B; ++b) {
+        fca_status st = validate(&probs[b], b, b ? &p0 : nullptr);
+        if (st != FCA_OK) return st;
+    }
+    fca_ctx* c = new (std::nothrow) fca_ctx();
+    if (!c) { set_err(nullptr, "out of host memory"); return FCA_E_NOMEM; }
+    c->B = B;
+    c->F = p0.F;
+    c->fp64 = (p0.prec == FCA_FP64);
+    c->stream = static_cast<hipStream_t>(p0.stream);
+    c->esz = c->fp64 ? 16 : 8;
+    c->rsz = c->fp64 ? 8 : 4;
+    c->nprob = B * c->F;
+    c->flags_host.assign(c->nprob, 0);
+
+    int64_t y_tot = 0, v_tot = 0, R_tot = 0, oR = 0, ov = 0, ox = 0;
+    int maxM = 1;
+    bool any_v0 = false;
+    c->mix.resize(B);
+    for (int b = 0; b < B; ++b) {
+        MixInfo& mi = c->mix[b];
+        mi.M = probs[b].M;
+        mi.N = probs[b].N;
+        mi.npad = (int)round_up(mi.N, 64);
+        mi.fpt = frames_per_thread(mi.N);
+        mi.y_base = y_tot;
+        mi.v_base = v_tot;
+        mi.R_base = R_tot;
+        mi.out_R = oR;
+        mi.out_v = ov;
+        mi.out_x = ox;
+        mi.pid0 = b * c->F;
+        mi.has_v0 = probs[b].v0 != nullptr;
+        any_v0 = any_v0 || mi.has_v0;
+        maxM = std::max(maxM, mi.M);
+        y_tot += (int64_t)c->F * mi.M * mi.npad;
+        v_tot += 2LL * c->F * mi.npad;
+        R_tot += 2LL * c->F * mi.M * mi.M;
+        oR += 2LL * c->F * mi.M * mi.M;
+        ov += 2LL * c->F * mi.N;
+        ox += 2LL * c->F * mi.N * mi.M;
+    }
+
+    fca_status st = FCA_OK;
+#define FCA_TRY(x)                                     \
+    do {                                               \
+        st = (x);                                      \
+        if (st != FCA_OK) {                            \
+            g_init_error = c->err.empty() ? g_init_error : c->err; \
+            free_ctx_memory(c);                        \
+            delete c;                                  \
+            return st;                                 \
+        }                                              \
+    } while (0)
+
+    FCA_TRY(dev_alloc(c, &c->y, y_tot * c->esz));
+    FCA_TRY(dev_alloc(c, &c->v, v_tot * c->rsz));
+    if (any_v0) FCA_TRY(dev_alloc(c, &c->v_init, v_tot * c->rsz));
+    FCA_TRY(dev_alloc(c, &c->R_init, R_tot * sizeof(double2)));
+    FCA_TRY(dev_alloc(c, &c->P, (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2)));
+    FCA_TRY(dev_alloc(c, &c->lam, (size_t)c->nprob * kMaxM * sizeof(double)));
+    FCA_TRY(dev_alloc(c, &c->logdet, (size_t)c->nprob * sizeof(double)));
+    FCA_TRY(dev_alloc(c, &c->flags, (size_t)c->nprob * sizeof(int)));
+    FCA_TRY(dev_alloc(c, &c->ll, (size_t)kLChunk * c->nprob * sizeof(double)));
+    FCA_TRY(dev_alloc(c, &c->ll_tot, (size_t)kLChunk * B * sizeof(double)));
+    FCA_TRY(dev_alloc(c, &c->fsum, (size_t)c->nprob * sizeof(double)));
+    FCA_TRY(dev_alloc(c, &c->R_stage, 2ull * c->F * maxM * maxM * sizeof(double2)));
+    FCA_TRY(dev_alloc(c, &c->probs, (size_t)c->nprob * sizeof(EmProblem)));
+    FCA_TRY(dev_alloc(c, &c->x_off, (size_t)c->nprob * 2 * sizeof(int64_t)));
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->ll_host), (size_t)kLChunk * B * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        c->ll_host = nullptr;
+        set_err(c, "hipHostMalloc failed");
+        FCA_TRY(FCA_E_NOMEM);
+    }
+    auto hipcall = [&](hipError_t e, const char* what) -> fca_status {
+        if (e == hipSuccess) return FCA_OK;
+        set_err(c, "%s failed: %s", what, hipGetErrorString(e));
+        return FCA_E_DEVICE;
+    };
+    FCA_TRY(hipcall(hipEventCreate(&c->ev0), "hipEventCreate"));
+    FCA_TRY(hipcall(hipEventCreate(&c->ev1), "hipEventCreate"));
+
+    const hipStream_t s = c->stream;
+    // ---- problem table: groups of equal (M, fpt), larger N first inside a group
+    std::vector<EmProblem> table;
+    std::vector<int64_t> xoff;
+    {
+        std::vector<int> order(B);
+        for (int b = 0; b < B; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const MixInfo &A = c->mix[a], &Bm = c->mix[b];
+            if (A.M != Bm.M) return A.M < Bm.M;
+            if (A.fpt != Bm.fpt) return A.fpt > Bm.fpt;
+            return A.N > Bm.N;
+        });
+        for (int oi = 0; oi < B; ++oi) {
+            const int b = order[oi];
+            const MixInfo& mi = c->mix[b];
+            if (c->groups.empty() || c->groups.back().M != mi.M || c->groups.back().fpt != mi.fpt)
+                c->groups.push_back(Group{mi.M, mi.fpt, (int)table.size(), 0, 0});
+            Group& g = c->groups.back();
+            for (int f = 0; f < c->F; ++f) {
+                EmProblem e;
+                e.y_off = mi.y_base + (int64_t)f * mi.M * mi.npad;
+                e.v_off = mi.v_base + (int64_t)f * mi.npad;
+                e.v2_off = (int64_t)c->F * mi.npad;
+                e.n = mi.N;
+                e.npad = mi.npad;
+                e.pid = mi.pid0 + f;
+                e.m = mi.M;
+                table.push_back(e);
+                xoff.push_back(mi.out_x + (int64_t)f * mi.N * mi.M);
+                xoff.push_back(mi.out_x + ((int64_t)c->F + f) * mi.N * mi.M);
+            }
+            g.count += c->F;
+            g.max_n = std::max(g.max_n, mi.N);
+        }
+    }
+    FCA_TRY(hipcall(hipMemcpyAsync(c->probs, table.data(), table.size() * sizeof(EmProblem),
+                                   hipMemcpyHostToDevice, s), "hipMemcpyAsync(problems)"));
+    FCA_TRY(hipcall(hipMemcpyAsync(c->x_off, xoff.data(), xoff.size() * sizeof(int64_t),
+                                   hipMemcpyHostToDevice, s), "hipMemcpyAsync(x offsets)"));
+
+    // ---- copy y (K0 ingest), R0, v0
+    for (int b = 0; b < B; ++b) {
+        const fca_problem& p = probs[b];
+        const MixInfo& mi = c->mix[b];
+        const int64_t extent = (int64_t)(p.F - 1) * p.y_stride_f + (int64_t)(p.N - 1) * p.y_stride_n +
+                               (int64_t)(p.M - 1) * p.y_stride_m + 1;
+        const void* src = p.y;
+        void* tmp = nullptr;
+        if (!is_device_ptr(p.y)) {
+            FCA_TRY(dev_alloc(c, &tmp, extent * c->esz));
+            fca_status cs = hipcall(hipMemcpyAsync(tmp, p.y, extent * c->esz, hipMemcpyHostToDevice, s),
+                                    "hipMemcpyAsync(y)");
+            if (cs != FCA_OK) { (void)hipFree(tmp); FCA_TRY(cs); }
+            src = tmp;
+        }
+        fca_status ks = hipcall(launch_ingest(c->fp64, src, p.y_stride_f, p.y_stride_n, p.y_stride_m, mi.M,
+                                              c->F, mi.N, mi.npad,
+                                              static_cast<char*>(c->y) + mi.y_base * c->esz, s),
+                                "ingest");
+        if (tmp) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(tmp);
+        }
+        FCA_TRY(ks);
+
+        double2* Rb = c->R_init + mi.R_base;
+        if (p.R0) {
+            FCA_TRY(hipcall(hipMemcpyAsync(Rb, p.R0, 2ull * c->F * mi.M * mi.M * sizeof(double2),
+                                           hipMemcpyDefault, s), "hipMemcpyAsync(R0)"));
+        } else {
+            FCA_TRY(hipcall(launch_default_R(mi.M, c->F, Rb, s), "default R0"));
+        }
+        if (p.v0) {
+            const size_t vbytes = 2ull * c->F * mi.N * c->rsz;
+            const void* vsrc = p.v0;
+            void* vtmp = nullptr;
+            if (!is_device_ptr(p.v0)) {
+                FCA_TRY(dev_alloc(c, &vtmp, vbytes));
+                fca_status cs = hipcall(hipMemcpyAsync(vtmp, p.v0, vbytes, hipMemcpyHostToDevice, s),
+                                        "hipMemcpyAsync(v0)");
+                if (cs != FCA_OK) { (void)hipFree(vtmp); FCA_TRY(cs); }
+                vsrc = vtmp;
+            }
+            fca_status ks2 = hipcall(launch_copy_v_in(c->fp64, vsrc, c->F, mi.N, mi.npad,
+                                                      static_cast<char*>(c->v_init) + mi.v_base * c->rsz, s),
+                                     "copy v0");
+            if (vtmp) {
+                (void)hipStreamSynchronize(s);
+                (void)hipFree(vtmp);
+            }
+            FCA_TRY(ks2);
+        }
+    }
+    FCA_TRY(hipcall(hipStreamSynchronize(s), "hipStreamSynchronize"));
+
+    st = do_reset(c);
+    if (st == FCA_E_NOT_PD) st = FCA_E_ARG;
+    FCA_TRY(st);
+#undef FCA_TRY
+    *out = c;
+    return FCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fca_status fca_init(const fca_problem* p, fca_ctx** out) {
+    if (!out) { set_err(nullptr, "out is NULL"); return FCA_E_ARG; }
+    *out = nullptr;
+    if (!p) { set_err(nullptr, "problem is NULL"); return FCA_E_ARG; }
+    return init_impl(p, 1, out);
+}
+
+fca_status fca_init_batch(const fca_problem* p, int32_t B, fca_ctx** out) {
+    if (!out) { set_err(nullptr, "out is NULL"); return FCA_E_ARG; }
+    *out = nullptr;
+    if (!p || B < 1) { set_err(nullptr, "need B >= 1 problems"); return FCA_E_ARG; }
+    return init_impl(p, B, out);
+}
+
+fca_status fca_reset(fca_ctx* c) {
+    if (!c) return FCA_E_ARG;
+    if (c->broken) return FCA_E_STATE;
+    return do_reset(c);
+}
+
+fca_status fca_em_step(fca_ctx* c, int32_t iters, double* loglik, double* R_out, void* v_out) {
+    if (!c) return FCA_E_ARG;
+    if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
+    if (iters < 0) { set_err(c, "iters < 0"); return FCA_E_ARG; }
+    const hipStream_t s = c->stream;
+    const bool ll_dev = loglik && is_device_ptr(loglik);
+    int done = 0;
+    do {
+        const int chunk = iters == 0 ? 0 : std::min(kLChunk, iters - done);
+        const int rows = chunk > 0 ? chunk : 1;
+        if (c->timing) FCA_HIP(c, hipEventRecord(c->ev0, s));
+        for (const Group& g : c->groups) {
+            FCA_HIP(c, launch_em(g.M, c->fp64, g.fpt, c->probs + g.first, g.count, c->y, c->v, c->P, c->lam,
+                                 c->logdet, c->flags, c->ll, c->nprob, chunk, s));
+        }
+        if (c->timing) FCA_HIP(c, hipEventRecord(c->ev1, s));
+        if (loglik) {
+            FCA_HIP(c, launch_ll_reduce(c->ll, c->nprob, rows, c->B, c->F, c->ll_tot, s));
+            const int total = iters > 0 ? iters : 1;
+            if (ll_dev) {
+                FCA_HIP(c, hipMemcpy2DAsync(loglik + done, total * sizeof(double), c->ll_tot,
+                                            rows * sizeof(double), rows * sizeof(double), c->B,
+                                            hipMemcpyDeviceToDevice, s));
+            } else {
+                FCA_HIP(c, hipMemcpyAsync(c->ll_host, c->ll_tot, (size_t)rows * c->B * sizeof(double),
+                                          hipMemcpyDeviceToHost, s));
+                FCA_HIP(c, hipStreamSynchronize(s));
+                for (int b = 0; b < c->B; ++b)
+                    memcpy(loglik + (size_t)b * total + done, c->ll_host + (size_t)b * rows, rows * sizeof(double));
+            }
+        }
+        if (c->timing) {
+            FCA_HIP(c, hipEventSynchronize(c->ev1));
+            float ms = 0.f;
+            FCA_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+            c->em_ms += ms;
+            c->em_launches += (int64_t)c->groups.size();
+        }
+        done += chunk;
+    } while (done < iters);
+
+    if (R_out) {
+        const bool dev = is_device_ptr(R_out);
+        for (int b = 0; b < c->B; ++b) {
+            const MixInfo& mi = c->mix[b];
+            const int64_t mm = (int64_t)mi.M * mi.M;
+            double2* dst = dev ? reinterpret_cast<double2*>(R_out) + mi.out_R : c->R_stage;
+            FCA_HIP(c, launch_recover_R(mi.M, c->F, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM,
+                                        c->lam + (int64_t)mi.pid0 * kMaxM, dst, dst + (int64_t)c->F * mm, s));
+            if (!dev) {
+                FCA_HIP(c, hipMemcpyAsync(reinterpret_cast<double2*>(R_out) + mi.out_R, c->R_stage,
+                                          2ull * c->F * mm * sizeof(double2), hipMemcpyDeviceToHost, s));
+                FCA_HIP(c, hipStreamSynchronize(s));
+            }
+        }
+    }
+    if (v_out) {
+        for (int b = 0; b < c->B; ++b) {
+            const MixInfo& mi = c->mix[b];
+            FCA_HIP(c, hipMemcpy2DAsync(static_cast<char*>(v_out) + mi.out_v * c->rsz, mi.N * c->rsz,
+                                        static_cast<char*>(c->v) + mi.v_base * c->rsz, mi.npad * c->rsz,
+                                        mi.N * c->rsz, 2 * c->F, hipMemcpyDefault, s));
+        }
+    }
+    return check_flags(c);
+}
+
+fca_status fca_separate(fca_ctx* c, void* x_out) {
+    if (!c || !x_out) { if (c) set_err(c, "x_out is NULL"); return FCA_E_ARG; }
+    if (c->broken) return FCA_E_STATE;
+    const hipStream_t s = c->stream;
+    int64_t total = 0;
+    for (const MixInfo& mi : c->mix) total += 2LL * c->F * mi.N * mi.M;
+    const bool dev = is_device_ptr(x_out);
+    void* dst = x_out;
+    if (!dev) {
+        fca_status st = dev_alloc(c, &dst, total * c->esz);
+        if (st != FCA_OK) return st;
+    }
+    hipError_t e = hipSuccess;
+    for (const Group& g : c->groups) {
+        e = launch_separate(g.M, c->fp64, c->probs + g.first, g.count, g.max_n, c->y, c->v, c->P, c->lam, dst,
+                            c->x_off + 2 * (int64_t)g.first, s);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess && !dev) e = hipMemcpyAsync(x_out, dst, total * c->esz, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (!dev) (void)hipFree(dst);
+    if (e != hipSuccess) {
+        set_err(c, "fca_separate: %s", hipGetErrorString(e));
+        c->broken = true;
+        return FCA_E_DEVICE;
+    }
+    return FCA_OK;
+}
+
+fca_status fca_status_per_freq(const fca_ctx* c, int32_t* flags) {
+    if (!c || !flags) return FCA_E_ARG;
+    fca_ctx* cc = const_cast<fca_ctx*>(c);
+    if (cc->broken) return FCA_E_STATE;
+    FCA_HIP(cc, hipMemcpyAsync(cc->flags_host.data(), cc->flags, sizeof(int) * cc->nprob,
+                               hipMemcpyDeviceToHost, cc->stream));
+    FCA_HIP(cc, hipStreamSynchronize(cc->stream));
+    memcpy(flags, cc->flags_host.data(), sizeof(int) * cc->nprob);
+    return FCA_OK;
+}
+
+const char* fca_last_error(const fca_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+void fca_destroy(fca_ctx* c) {
+    if (!c) return;
+    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    free_ctx_memory(c);
+    delete c;
+}
+
+fca_status fca_gevd(int32_t M, int32_t count, const double* S1, const double* S2, double* P, double* lambda,
+                    int32_t* flags, void* stream) {
+    if (M < 1 || M > kMaxM || count < 0) { set_err(nullptr, "fca_gevd: bad M or count"); return FCA_E_ARG; }
+    if (count == 0) return FCA_OK;
+    if (!is_device_ptr(S1) || !is_device_ptr(S2) || !is_device_ptr(P) || !is_device_ptr(lambda) ||
+        !is_device_ptr(flags)) {
+        set_err(nullptr, "fca_gevd: all arrays must be device pointers");
+        return FCA_E_ARG;
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t mm = (int64_t)M * M;
+    hipError_t e = launch_gevd(M, count, reinterpret_cast<const double2*>(S1), reinterpret_cast<const double2*>(S2),
+                               mm, mm, reinterpret_cast<double2*>(P), mm, lambda, M, nullptr, flags, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        set_err(nullptr, "fca_gevd: %s", hipGetErrorString(e));
+        return FCA_E_DEVICE;
+    }
+    return FCA_OK;
+}
+
+fca_status fca_timing(fca_ctx* c, int32_t enable, double* em_kernel_ms, int64_t* em_launches) {
+    if (!c) return FCA_E_ARG;
+    if (em_kernel_ms) *em_kernel_ms = c->em_ms;
+    if (em_launches) *em_launches = c->em_launches;
+    c->em_ms = 0.0;
+    c->em_launches = 0;
+    c->timing = enable != 0;
+    return FCA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// fca_internal.h -- declarations shared by the kernel translation unit and
+// the host runtime of libfca (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fca {
+
+// Per-frequency status bits (the FCA_FLAG_* values of fca.h).
+constexpr int kFlagNotPD = 1;
+constexpr int kFlagNonFinite = 2;
+constexpr int kFlagSweeps = 4;
+constexpr int kFreezeMask = kFlagNotPD | kFlagNonFinite;
+
+// Largest microphone count; per-frequency state is stored with this stride.
+constexpr int kMaxM = 8;
+
+// Threads per workgroup of the per-frequency EM kernel, and the largest
+// number of frames each thread keeps in registers.
+constexpr int kEmThreads = 256;
+constexpr int kMaxFramesPerThread = 8;
+constexpr int kMaxFrames = kEmThreads * kMaxFramesPerThread;
+
+// One EM problem = one (mixture, frequency) pair. All offsets are element
+// offsets into the context's device arrays.
+struct EmProblem {
+    int64_t y_off;   // complex elements: start of y_int[f][m][0]; rows of npad
+    int64_t v_off;   // prec reals: start of v1[f][0]; v2 follows at +v2_off
+    int64_t v2_off;  // distance (elements) from v1 to v2 of the same bin
+    int32_t n;       // frames
+    int32_t npad;    // row pitch of y_int and v (>= n)
+    int32_t pid;     // problem index into P, lam, logdet, flags, ll
+    int32_t m;       // microphones (checked against the kernel's template M)
+};
+
+// Launchers (defined in fca_kernels.hip). All return hipSuccess or the
+// launch error. Every pointer is a device pointer.
+hipError_t launch_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
+                     void* v, double2* P, double* lam, double* logdet, int* flags, double* ll,
+                     int64_t ll_stride, int iters, hipStream_t s);
+
+hipError_t launch_ingest(bool fp64, const void* src, int64_t sf, int64_t sn, int64_t sm, int M,
+                         int F, int N, int npad, void* dst, hipStream_t s);
+
+hipError_t launch_power_sums(bool fp64, const void* y, int M, int F, int N, int npad,
+                             double* fsum, hipStream_t s);
+
+hipError_t launch_default_v(bool fp64, const void* y, const double* fsum, int M, int F, int N,
+                            int npad, void* v, hipStream_t s);
+
+hipError_t launch_copy_v_in(bool fp64, const void* v0, int F, int N, int npad, void* v,
+                            hipStream_t s);
+
+hipError_t launch_gevd(int M, int count, const double2* A, const double2* B, int64_t stride_a,
+                       int64_t stride_b, double2* P, int64_t stride_p, double* lam, int64_t stride_l,
+                       double* logdet, int* flags, hipStream_t s);
+
+hipError_t launch_default_R(int M, int F, double2* R, hipStream_t s);
+
+hipError_t launch_ll_reduce(const double* ll, int64_t ll_stride, int iters, int B, int F,
+                            double* out, hipStream_t s);
+
+hipError_t launch_recover_R(int M, int count, const double2* P, const double* lam, double2* R1,
+                            double2* R2, hipStream_t s);
+
+hipError_t launch_separate(int M, bool fp64, const EmProblem* probs, int count, int max_n,
+                           const void* y, const void* v, const double2* P, const double* lam,
+                           void* x, const int64_t* x_off, hipStream_t s);
+
+}  // namespace fca

@@ -1,0 +1,783 @@
+// fca_kernels.hip -- gfx950 kernels of the FastFCA EM library.
+//
+// The hot kernel is em_kernel: one workgroup owns one (mixture, frequency)
+// EM problem for all iterations of a call. Its frames stay in registers, so
+// y(n,f) and v_j(n,f) cross HBM once per call, not once per iteration. Each
+// iteration (Algorithm 1, steps 3-9):
+//   per bin (one thread per frame, up to FPT frames per thread):
+//     y~ = P^H y                                   eq. (tildey)
+//     d_i = v1 lam_i + v2, mu~ and the posterior   eqs. (MMSEtilde), (updatePhitildeeff)
+//     v_j' from the diagonal traces                eq. (updateveff)
+//     log-likelihood term of theta^(l)             eq. (like) in the eigenbasis
+//     running sums of Phi~_j / v_j'                eq. (updateStildeeff)
+//   per frequency: FP64 reduction of the sums in a fixed order, then the
+//   FP64 generalized eigendecomposition of (S~1, S~2) and P <- P Q,
+//   Lambda <- Sigma (eqs. GEVDeff5, updatePeff, updateLambdaeff).
+// The log-likelihood of a bin uses v1 R1 + v2 R2 = P^-H diag(d) P^-1 and
+// |det P|^2 = 1 / det R2:
+//   log p(y) = -M log(pi) + log|det P|^2 - sum_i log d_i - sum_i |y~_i|^2 / d_i.
+#include <hip/hip_runtime.h>
+
+#include "fca_device.h"
+#include "fca_internal.h"
+
+namespace fca {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+constexpr double kLogPi = 1.1447298858494002;
+
+// Index of the off-diagonal pair (i < k) of an M x M matrix, row-major over
+// the strict upper triangle.
+__host__ __device__ constexpr int pair_index(int M, int i, int k) {
+    return i * M - i * (i + 1) / 2 + (k - i - 1);
+}
+
+// ============================================================== EM kernel
+template <int M, typename T, int FPT>
+__global__ __launch_bounds__(kEmThreads) void em_kernel(
+    const EmProblem* __restrict__ probs, const typename Vec2<T>::type* __restrict__ y,
+    T* __restrict__ v, double2* __restrict__ Pg, double* __restrict__ lamg,
+    double* __restrict__ logdetg, int* __restrict__ flagsg, double* __restrict__ ll,
+    int64_t ll_stride, int iters) {
+    using T2 = typename Vec2<T>::type;
+    using MT = Math<T>;
+    constexpr int NT = kEmThreads;
+    constexpr int MM = M * M;
+    constexpr int NV = 2 * MM;               // reals accumulated per thread
+    constexpr int CH = NV < 32 ? NV : 32;    // values per reduction chunk
+    constexpr int NCH = (NV + CH - 1) / CH;
+    constexpr int G = NT / 32;               // row groups of stage 2
+    constexpr int NW = NT / 64;
+
+    __shared__ double2 sP[MM];
+    __shared__ double2 sPn[MM];
+    __shared__ double sLam[M];
+    __shared__ double sLamN[M];
+    __shared__ double sLogdet;
+    __shared__ int sFlag;
+    __shared__ int sBad;
+    __shared__ double2 sS[2][MM];
+    __shared__ double sFinal[NV];
+    __shared__ T sRed[NT * (CH + 1)];
+    __shared__ double sRed2[G * CH];
+    __shared__ double sLL[NW];
+
+    const EmProblem pr = probs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int nf = pr.n;
+    const int npad = pr.npad;
+    const int pid = pr.pid;
+    const int64_t pbase = (int64_t)pid * kMaxM * kMaxM;
+
+    if (tid < MM) sP[tid] = Pg[pbase + tid];
+    if (tid < M) sLam[tid] = lamg[(int64_t)pid * kMaxM + tid];
+    if (tid == 0) {
+        sLogdet = logdetg[pid];
+        sFlag = flagsg[pid];
+        sBad = 0;
+    }
+
+    // ---- frames of this thread into registers
+    T yr[FPT][M], yi[FPT][M], v1[FPT], v2[FPT];
+    const T2* __restrict__ yb = y + pr.y_off;
+#pragma unroll
+    for (int k = 0; k < FPT; ++k) {
+        const int n = k * NT + tid;
+        const bool ok = n < nf;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            T2 val;
+            if (ok) val = yb[(int64_t)m * npad + n];
+            else { val.x = T(0); val.y = T(0); }
+            yr[k][m] = val.x;
+            yi[k][m] = val.y;
+        }
+        v1[k] = ok ? v[pr.v_off + n] : T(1);
+        v2[k] = ok ? v[pr.v_off + pr.v2_off + n] : T(1);
+    }
+    __syncthreads();
+    const bool frozen_at_entry = (sFlag & kFreezeMask) != 0;
+    const int passes = (iters > 0 && !frozen_at_entry) ? iters : 1;
+    const int ll_count = iters > 0 ? iters : 1;
+
+    for (int it = 0; it < passes; ++it) {
+        // ---- per-frequency constants in the bulk precision
+        T Pr[M][M], Pi[M][M], lm[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            lm[a] = (T)sLam[a];
+#pragma unroll
+            for (int b = 0; b < M; ++b) {
+                const double2 p = sP[a * M + b];
+                Pr[a][b] = (T)p.x;
+                Pi[a][b] = (T)p.y;
+            }
+        }
+        T acc[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] = T(0);
+        double llacc = 0.0;
+        T v1n[FPT], v2n[FPT];
+        bool bad = false;
+
+#pragma unroll
+        for (int k = 0; k < FPT; ++k) {
+            v1n[k] = v1[k];
+            v2n[k] = v2[k];
+            if (k * NT >= nf) continue;  // uniform: the whole block of frames is padding
+            const bool ok = (k * NT + tid) < nf;
+            const T a1 = v1[k], a2 = v2[k];
+            // eq. (tildey): y~_i = sum_m conj(P_mi) y_m
+            T ytr[M], yti[M], e[M], r[M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                T sr = T(0), si = T(0);
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    sr = fma(Pr[m][i], yr[k][m], fma(Pi[m][i], yi[k][m], sr));
+                    si = fma(Pr[m][i], yi[k][m], fma(-Pi[m][i], yr[k][m], si));
+                }
+                ytr[i] = sr;
+                yti[i] = si;
+                e[i] = fma(sr, sr, si * si);
+            }
+            // d_i = v1 lam_i + v2 and the log-likelihood term of theta^(l)
+            T d[M];
+            T quad = T(0);
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                d[i] = fma(a1, lm[i], a2);
+                r[i] = MT::rcp(d[i]);
+                quad = fma(e[i], r[i], quad);
+            }
+            T logd = T(0);
+#pragma unroll
+            for (int i = 0; i < M; i += 2) {
+                const T pd = (i + 1 < M) ? d[i] * d[i + 1] : d[i];
+                logd += MT::log(pd);
+            }
+            // eq. (updateveff): v1' = (v1/M) sum r_i (v1 lam_i e_i r_i + v2),
+            //                   v2' = (v2/M) sum r_i (v2 e_i r_i + v1 lam_i)
+            T s1 = T(0), s2 = T(0);
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const T er = e[i] * r[i];
+                s1 = fma(r[i], fma(a1 * lm[i], er, a2), s1);
+                s2 = fma(r[i], fma(a2, er, a1 * lm[i]), s2);
+            }
+            const T nv1 = a1 * s1 * (T(1) / T(M));
+            const T nv2 = a2 * s2 * (T(1) / T(M));
+            if (ok) {
+                llacc += (double)(-logd - quad);
+                bad = bad || !(nv1 > T(0)) || !(nv2 > T(0)) || !isfinite(nv1) || !isfinite(nv2);
+                v1n[k] = nv1;
+                v2n[k] = nv2;
+            }
+            // eq. (updateStildeeff): sum_n (mu~_j mu~_j^H + diag(c)) / v_j', with
+            // mu~1_i = v1 lam_i r_i y~_i, mu~2_i = v2 r_i y~_i, c_i = v1 v2 lam_i r_i.
+            // u_j = mu~_j / sqrt(v_j') makes the rank-one term u_j u_j^H.
+            const T w1 = ok ? MT::rsqrt(nv1) : T(0);
+            const T w2 = ok ? MT::rsqrt(nv2) : T(0);
+            const T iv1 = w1 * w1, iv2 = w2 * w2;
+            T u1r[M], u1i[M], u2r[M], u2i[M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const T g1 = a1 * lm[i] * r[i];
+                const T g2 = a2 * r[i];
+                const T c = g1 * a2;
+                const T s1i = g1 * w1, s2i = g2 * w2;
+                u1r[i] = s1i * ytr[i];
+                u1i[i] = s1i * yti[i];
+                u2r[i] = s2i * ytr[i];
+                u2i[i] = s2i * yti[i];
+                acc[i] = fma(s1i * s1i, e[i], fma(c, iv1, acc[i]));
+                acc[MM + i] = fma(s2i * s2i, e[i], fma(c, iv2, acc[MM + i]));
+            }
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+#pragma unroll
+                for (int q = i + 1; q < M; ++q) {
+                    const int o = M + 2 * pair_index(M, i, q);
+                    acc[o] = fma(u1r[i], u1r[q], fma(u1i[i], u1i[q], acc[o]));
+                    acc[o + 1] = fma(u1i[i], u1r[q], fma(-u1r[i], u1i[q], acc[o + 1]));
+                    acc[MM + o] = fma(u2r[i], u2r[q], fma(u2i[i], u2i[q], acc[MM + o]));
+                    acc[MM + o + 1] = fma(u2i[i], u2r[q], fma(-u2r[i], u2i[q], acc[MM + o + 1]));
+                }
+            }
+        }
+        if (bad) sBad = 1;
+
+        // ---- log-likelihood: wave then workgroup, FP64, fixed order
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) llacc += __shfl_xor(llacc, off, 64);
+        if ((tid & 63) == 0) sLL[tid >> 6] = llacc;
+
+        // ---- sums of the accumulators over the workgroup, FP64 across threads
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (ch * CH + c < NV) sRed[tid * (CH + 1) + c] = acc[ch * CH + c];
+            __syncthreads();
+            for (int task = tid; task < CH * G; task += NT) {
+                const int c = task % CH, g = task / CH;
+                double s = 0.0;
+#pragma unroll 8
+                for (int rr = 0; rr < 32; ++rr) s += (double)sRed[(g * 32 + rr) * (CH + 1) + c];
+                sRed2[g * CH + c] = s;
+            }
+            __syncthreads();
+            if (tid < CH && ch * CH + tid < NV) {
+                double s = 0.0;
+#pragma unroll
+                for (int g = 0; g < G; ++g) s += sRed2[g * CH + tid];
+                sFinal[ch * CH + tid] = s;
+            }
+            __syncthreads();
+        }
+
+        // ---- S~_j = sums / N as full Hermitian matrices (FP64)
+        if (tid < NV) {
+            const int j = tid / MM, ent = tid % MM, i = ent / M, q = ent % M;
+            const double invn = 1.0 / (double)nf;
+            const double* f = sFinal + j * MM;
+            double2 val;
+            if (i == q) val = make_double2(f[i] * invn, 0.0);
+            else if (i < q) {
+                const int o = M + 2 * pair_index(M, i, q);
+                val = make_double2(f[o] * invn, f[o + 1] * invn);
+            } else {
+                const int o = M + 2 * pair_index(M, q, i);
+                val = make_double2(f[o] * invn, -f[o + 1] * invn);
+            }
+            sS[j][ent] = val;
+        }
+        __syncthreads();
+
+        // ---- record LL(theta^(it)); GEVD and basis update by one thread
+        if (tid == 0) {
+            double tot = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) tot += sLL[w];
+            tot += (double)nf * (-(double)M * kLogPi + sLogdet);
+            const bool last = (iters == 0) || frozen_at_entry;
+            if (last) {
+                for (int l = it; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
+            } else {
+                ll[(int64_t)it * ll_stride + pid] = tot;
+                int flag = 0;
+                if (sBad) flag = kFlagNonFinite;
+                double dld = 0.0;
+                int sweeps = 0;
+                if (!flag) flag = gevd_update<M>(sS[0], sS[1], sP, sPn, sLamN, &dld, &sweeps);
+                sFlag |= flag;
+                if (flag & kFreezeMask) {
+                    // frozen at theta^(it): its log-likelihood stands for later iterations
+                    for (int l = it + 1; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < MM; ++i) sP[i] = sPn[i];
+#pragma unroll
+                    for (int i = 0; i < M; ++i) sLam[i] = sLamN[i];
+                    sLogdet += dld;
+                }
+            }
+        }
+        __syncthreads();
+        if (iters == 0 || frozen_at_entry || (sFlag & kFreezeMask)) break;
+#pragma unroll
+        for (int k = 0; k < FPT; ++k) {
+            v1[k] = v1n[k];
+            v2[k] = v2n[k];
+        }
+    }
+
+    // ---- write the state back (frames and per-frequency parameters)
+    if (iters > 0 && !frozen_at_entry) {
+#pragma unroll
+        for (int k = 0; k < FPT; ++k) {
+            const int n = k * NT + tid;
+            if (n < nf) {
+                v[pr.v_off + n] = v1[k];
+                v[pr.v_off + pr.v2_off + n] = v2[k];
+            }
+        }
+        if (tid < MM) Pg[pbase + tid] = sP[tid];
+        if (tid < M) lamg[(int64_t)pid * kMaxM + tid] = sLam[tid];
+        if (tid == 0) {
+            logdetg[pid] = sLogdet;
+            flagsg[pid] = sFlag;
+        }
+    }
+}
+
+template <int M, typename T>
+static hipError_t launch_em_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v,
+                                double2* P, double* lam, double* logdet, int* flags, double* ll,
+                                int64_t ll_stride, int iters, hipStream_t s) {
+    using T2 = typename Vec2<T>::type;
+    const dim3 grid(count), block(kEmThreads);
+    const T2* yy = static_cast<const T2*>(y);
+    T* vv = static_cast<T*>(v);
+    switch (fpt) {
+        case 1: em_kernel<M, T, 1><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
+        case 2: em_kernel<M, T, 2><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
+        case 4: em_kernel<M, T, 4><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
+        case 8: em_kernel<M, T, 8><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int M>
+static hipError_t launch_em_m(bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
+                              void* v, double2* P, double* lam, double* logdet, int* flags, double* ll,
+                              int64_t ll_stride, int iters, hipStream_t s) {
+    return fp64 ? launch_em_fpt<M, double>(fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, iters, s)
+                : launch_em_fpt<M, float>(fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, iters, s);
+}
+
+hipError_t launch_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
+                     void* v, double2* P, double* lam, double* logdet, int* flags, double* ll,
+                     int64_t ll_stride, int iters, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    switch (M) {
+        case 1: return launch_em_m<1>(fp64, fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, iters, s);
+        case 2: return launch_em_m<2>(fp64, fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, iters, s);
+        case 3: return launch_em_m<3>(fp64, fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, iters, s);
+        case 4: return launch_em_m<4>(fp64, fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, iters, s);
+        case 5: return launch_em_m<5>(fp64, fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, iters, s);
+        case 6: return launch_em_m<6>(fp64, fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, iters, s);
+        case 7: return launch_em_m<7>(fp64, fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, iters, s);
+        case 8: return launch_em_m<8>(fp64, fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, iters, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ============================================================== ingest
+// dst[f][m][n] (row pitch npad, zero padded) from the caller's strided y.
+template <typename T2>
+__global__ void ingest_kernel(const T2* __restrict__ src, int64_t sf, int64_t sn, int64_t sm, int M,
+                              int F, int N, int npad, T2* __restrict__ dst) {
+    const int64_t total = (int64_t)F * M * npad;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int n = (int)(i % npad);
+        const int64_t fm = i / npad;
+        const int m = (int)(fm % M);
+        const int f = (int)(fm / M);
+        T2 val;
+        if (n < N) val = src[f * sf + n * sn + m * sm];
+        else { val.x = 0; val.y = 0; }
+        dst[i] = val;
+    }
+}
+
+static unsigned grid_for(int64_t total, int block) {
+    int64_t g = (total + block - 1) / block;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+hipError_t launch_ingest(bool fp64, const void* src, int64_t sf, int64_t sn, int64_t sm, int M,
+                         int F, int N, int npad, void* dst, hipStream_t s) {
+    const unsigned g = grid_for((int64_t)F * M * npad, 256);
+    if (fp64)
+        ingest_kernel<double2><<<g, 256, 0, s>>>(static_cast<const double2*>(src), sf, sn, sm, M, F, N, npad, static_cast<double2*>(dst));
+    else
+        ingest_kernel<float2><<<g, 256, 0, s>>>(static_cast<const float2*>(src), sf, sn, sm, M, F, N, npad, static_cast<float2*>(dst));
+    return hipGetLastError();
+}
+
+// ============================================================== plain start of v
+// fsum[f] = sum_n ||y(n,f)||^2 / M (FP64, fixed order: per-thread strided sums,
+// then a tree over the workgroup).
+template <typename T2>
+__global__ void power_sums_kernel(const T2* __restrict__ y, int M, int N, int npad, double* __restrict__ fsum) {
+    __shared__ double red[256];
+    const int f = blockIdx.x;
+    double s = 0.0;
+    for (int n = threadIdx.x; n < N; n += 256) {
+        double p = 0.0;
+        for (int m = 0; m < M; ++m) {
+            const T2 val = y[((int64_t)f * M + m) * npad + n];
+            p += (double)val.x * (double)val.x + (double)val.y * (double)val.y;
+        }
+        s += p / M;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) fsum[f] = red[0];
+}
+
+hipError_t launch_power_sums(bool fp64, const void* y, int M, int F, int N, int npad, double* fsum,
+                             hipStream_t s) {
+    if (fp64)
+        power_sums_kernel<double2><<<F, 256, 0, s>>>(static_cast<const double2*>(y), M, N, npad, fsum);
+    else
+        power_sums_kernel<float2><<<F, 256, 0, s>>>(static_cast<const float2*>(y), M, N, npad, fsum);
+    return hipGetLastError();
+}
+
+// v_j(n,f) = max(||y(n,f)||^2 / M, floor), floor = 1e-12 * mean over bins
+// (1 if the mean is zero); padding frames get 1.
+template <typename T, typename T2>
+__global__ void default_v_kernel(const T2* __restrict__ y, const double* __restrict__ fsum, int M, int F,
+                                 int N, int npad, T* __restrict__ v) {
+    __shared__ double s_floor;
+    const int f = blockIdx.y;
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int g = 0; g < F; ++g) tot += fsum[g];
+        const double mean = tot / ((double)F * (double)N);
+        s_floor = mean > 0.0 ? 1e-12 * mean : 1.0;
+    }
+    __syncthreads();
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= npad) return;
+    double val = 1.0;
+    if (n < N) {
+        double p = 0.0;
+        for (int m = 0; m < M; ++m) {
+            const T2 yy = y[((int64_t)f * M + m) * npad + n];
+            p += (double)yy.x * (double)yy.x + (double)yy.y * (double)yy.y;
+        }
+        val = p / M;
+        if (!(val >= s_floor)) val = s_floor;
+    }
+    v[(int64_t)f * npad + n] = (T)val;
+    v[((int64_t)F + f) * npad + n] = (T)val;
+}
+
+hipError_t launch_default_v(bool fp64, const void* y, const double* fsum, int M, int F, int N, int npad,
+                            void* v, hipStream_t s) {
+    const dim3 grid((npad + 255) / 256, F);
+    if (fp64)
+        default_v_kernel<double, double2><<<grid, 256, 0, s>>>(static_cast<const double2*>(y), fsum, M, F, N, npad, static_cast<double*>(v));
+    else
+        default_v_kernel<float, float2><<<grid, 256, 0, s>>>(static_cast<const float2*>(y), fsum, M, F, N, npad, static_cast<float*>(v));
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void copy_v_in_kernel(const T* __restrict__ v0, int F, int N, int npad, T* __restrict__ v) {
+    const int64_t total = 2LL * F * npad;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int n = (int)(i % npad);
+        const int64_t row = i / npad;
+        v[i] = (n < N) ? v0[row * N + n] : T(1);
+    }
+}
+
+hipError_t launch_copy_v_in(bool fp64, const void* v0, int F, int N, int npad, void* v, hipStream_t s) {
+    const unsigned g = grid_for(2LL * F * npad, 256);
+    if (fp64)
+        copy_v_in_kernel<double><<<g, 256, 0, s>>>(static_cast<const double*>(v0), F, N, npad, static_cast<double*>(v));
+    else
+        copy_v_in_kernel<float><<<g, 256, 0, s>>>(static_cast<const float*>(v0), F, N, npad, static_cast<float*>(v));
+    return hipGetLastError();
+}
+
+// ============================================================== batched GEVD
+// One thread per pencil (A, B) at A + i*stride_a, B + i*stride_b, starting
+// from the identity basis: P + i*stride_p receives Q (M x M), lam +
+// i*stride_l the eigenvalues, logdet[i] = log|det Q|^2 = -log det B (if
+// logdet is not null) and flags[i] the FCA flag bits. On failure P = I and
+// lam = 1.
+template <int M>
+__global__ void gevd_kernel(int count, const double2* __restrict__ A, const double2* __restrict__ B,
+                            int64_t stride_a, int64_t stride_b, double2* __restrict__ P, int64_t stride_p,
+                            double* __restrict__ lam, int64_t stride_l, double* __restrict__ logdet,
+                            int* __restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double2 Id[M * M];
+#pragma unroll
+    for (int a = 0; a < M * M; ++a) Id[a] = make_double2((a % (M + 1)) == 0 ? 1.0 : 0.0, 0.0);
+    double2 Pn[M * M];
+    double ln[M];
+    double dld = 0.0;
+    int sweeps = 0;
+    const int flag = gevd_update<M>(A + i * stride_a, B + i * stride_b, Id, Pn, ln, &dld, &sweeps);
+    if (!(flag & kFreezeMask)) {
+#pragma unroll
+        for (int a = 0; a < M * M; ++a) P[i * stride_p + a] = Pn[a];
+#pragma unroll
+        for (int a = 0; a < M; ++a) lam[i * stride_l + a] = ln[a];
+    } else {
+#pragma unroll
+        for (int a = 0; a < M * M; ++a) P[i * stride_p + a] = Id[a];
+#pragma unroll
+        for (int a = 0; a < M; ++a) lam[i * stride_l + a] = 1.0;
+        dld = 0.0;
+    }
+    if (logdet) logdet[i] = dld;
+    flags[i] = flag;
+}
+
+hipError_t launch_gevd(int M, int count, const double2* A, const double2* B, int64_t stride_a,
+                       int64_t stride_b, double2* P, int64_t stride_p, double* lam, int64_t stride_l,
+                       double* logdet, int* flags, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const unsigned g = (count + 63) / 64;
+    switch (M) {
+#define FCA_GEVD_CASE(MM_)                                                                                     \
+    case MM_:                                                                                                  \
+        gevd_kernel<MM_><<<g, 64, 0, s>>>(count, A, B, stride_a, stride_b, P, stride_p, lam, stride_l, logdet, \
+                                          flags);                                                              \
+        break;
+        FCA_GEVD_CASE(1) FCA_GEVD_CASE(2) FCA_GEVD_CASE(3) FCA_GEVD_CASE(4)
+        FCA_GEVD_CASE(5) FCA_GEVD_CASE(6) FCA_GEVD_CASE(7) FCA_GEVD_CASE(8)
+#undef FCA_GEVD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// R1 = I, R2 = I + 0.5 e1 e1^H at every frequency: R[2][F][M][M].
+__global__ void default_R_kernel(int M, int F, double2* __restrict__ R) {
+    const int64_t total = 2LL * F * M * M;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int ent = (int)(i % (M * M));
+        const int j = (int)(i / ((int64_t)F * M * M));
+        const int a = ent / M, b = ent % M;
+        double re = (a == b) ? 1.0 : 0.0;
+        if (j == 1 && a == 0 && b == 0) re += 0.5;
+        R[i] = make_double2(re, 0.0);
+    }
+}
+
+hipError_t launch_default_R(int M, int F, double2* R, hipStream_t s) {
+    default_R_kernel<<<grid_for(2LL * F * M * M, 256), 256, 0, s>>>(M, F, R);
+    return hipGetLastError();
+}
+
+// ============================================================== log-likelihood totals
+// out[b*iters + it] = sum_f ll[it*ll_stride + b*F + f], FP64, fixed order.
+__global__ void ll_reduce_kernel(const double* __restrict__ ll, int64_t ll_stride, int iters, int F,
+                                 double* __restrict__ out) {
+    __shared__ double red[256];
+    const int it = blockIdx.x, b = blockIdx.y;
+    double s = 0.0;
+    for (int f = threadIdx.x; f < F; f += 256) s += ll[(int64_t)it * ll_stride + (int64_t)b * F + f];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)b * iters + it] = red[0];
+}
+
+hipError_t launch_ll_reduce(const double* ll, int64_t ll_stride, int iters, int B, int F, double* out,
+                            hipStream_t s) {
+    if (iters <= 0 || B <= 0) return hipSuccess;
+    ll_reduce_kernel<<<dim3(iters, B), 256, 0, s>>>(ll, ll_stride, iters, F, out);
+    return hipGetLastError();
+}
+
+// ============================================================== inverse of P
+// Gauss-Jordan elimination with partial pivoting, FP64. Returns false if P is
+// numerically singular.
+template <int M>
+__device__ bool invert(const double2* __restrict__ P, double2 (&X)[M][M]) {
+    double2 A[M][M];
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            A[i][k] = P[i * M + k];
+            X[i][k] = make_double2(i == k ? 1.0 : 0.0, 0.0);
+        }
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        // pivot search among rows c..M-1 (swap by value, indices stay static)
+        double best = cabs2(A[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < M; ++r) {
+            const double mag = cabs2(A[r][c]);
+            if (mag > best) {
+                best = mag;
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    const double2 ta = A[c][k]; A[c][k] = A[r][k]; A[r][k] = ta;
+                    const double2 tx = X[c][k]; X[c][k] = X[r][k]; X[r][k] = tx;
+                }
+            }
+        }
+        if (!(best > 0.0)) ok = false;
+        const double2 piv = A[c][c];
+        const double inv_mag = 1.0 / cabs2(piv);
+        const double2 pinv = make_double2(piv.x * inv_mag, -piv.y * inv_mag);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            A[c][k] = cmul(A[c][k], pinv);
+            X[c][k] = cmul(X[c][k], pinv);
+        }
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            if (r == c) continue;
+            const double2 fct = A[r][c];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                A[r][k] = csub(A[r][k], cmul(fct, A[c][k]));
+                X[r][k] = csub(X[r][k], cmul(fct, X[c][k]));
+            }
+        }
+    }
+    return ok;
+}
+
+// R2 = (P P^H)^-1 = P^-H P^-1 and R1 = P^-H Lambda P^-1 (eq. recoverS with
+// S~1 = Lambda, S~2 = I in the current eigenbasis). One thread per problem.
+template <int M>
+__global__ void recover_R_kernel(int count, const double2* __restrict__ P, const double* __restrict__ lam,
+                                 double2* __restrict__ R1, double2* __restrict__ R2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double2 X[M][M];
+    invert<M>(P + (int64_t)i * kMaxM * kMaxM, X);
+    const double* l = lam + (int64_t)i * kMaxM;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+#pragma unroll
+        for (int b = 0; b < M; ++b) {
+            double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const double2 t = cmulc(X[k][b], X[k][a]);  // conj(X_ka) X_kb
+                s2 = cadd(s2, t);
+                s1 = cadd(s1, cscale(l[k], t));
+            }
+            if (a == b) { s1.y = 0.0; s2.y = 0.0; }
+            R1[(int64_t)i * M * M + a * M + b] = s1;
+            R2[(int64_t)i * M * M + a * M + b] = s2;
+        }
+    }
+}
+
+hipError_t launch_recover_R(int M, int count, const double2* P, const double* lam, double2* R1,
+                            double2* R2, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const unsigned g = (count + 63) / 64;
+    switch (M) {
+#define FCA_REC_CASE(MM_) \
+    case MM_: recover_R_kernel<MM_><<<g, 64, 0, s>>>(count, P, lam, R1, R2); break;
+        FCA_REC_CASE(1) FCA_REC_CASE(2) FCA_REC_CASE(3) FCA_REC_CASE(4)
+        FCA_REC_CASE(5) FCA_REC_CASE(6) FCA_REC_CASE(7) FCA_REC_CASE(8)
+#undef FCA_REC_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ============================================================== MMSE separation
+// x1 = P^-H mu~1 with mu~1_i = v1 lam_i y~_i / d_i (eq. MMSEtilde and
+// Algorithm 1, step 11), x2 = y - x1 (eq. MMSE: mu1 + mu2 = y). Grid
+// (frame blocks, problems); P^-H in FP64 once per workgroup.
+template <int M, typename T>
+__global__ __launch_bounds__(256) void separate_kernel(const EmProblem* __restrict__ probs,
+                                                       const typename Vec2<T>::type* __restrict__ y,
+                                                       const T* __restrict__ v, const double2* __restrict__ Pg,
+                                                       const double* __restrict__ lamg,
+                                                       typename Vec2<T>::type* __restrict__ x,
+                                                       const int64_t* __restrict__ x_off) {
+    using T2 = typename Vec2<T>::type;
+    using MT = Math<T>;
+    __shared__ double2 sP[M * M];
+    __shared__ double2 sQ[M * M];  // P^-H
+    __shared__ double sLam[M];
+    const EmProblem pr = probs[blockIdx.y];
+    if ((int)blockIdx.x * 256 >= pr.n) return;
+    const int tid = threadIdx.x;
+    const int64_t pbase = (int64_t)pr.pid * kMaxM * kMaxM;
+    if (tid < M * M) sP[tid] = Pg[pbase + tid];
+    if (tid < M) sLam[tid] = lamg[(int64_t)pr.pid * kMaxM + tid];
+    __syncthreads();
+    if (tid == 0) {
+        double2 X[M][M];
+        invert<M>(sP, X);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int b = 0; b < M; ++b) sQ[a * M + b] = cconj(X[b][a]);
+    }
+    __syncthreads();
+    const int n = blockIdx.x * 256 + tid;
+    if (n >= pr.n) return;
+    T yr[M], yi[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const T2 val = y[pr.y_off + (int64_t)m * pr.npad + n];
+        yr[m] = val.x;
+        yi[m] = val.y;
+    }
+    const T a1 = v[pr.v_off + n], a2 = v[pr.v_off + pr.v2_off + n];
+    T mr[M], mi[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        T sr = T(0), si = T(0);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const double2 p = sP[m * M + i];
+            sr = fma((T)p.x, yr[m], fma((T)p.y, yi[m], sr));
+            si = fma((T)p.x, yi[m], fma(-(T)p.y, yr[m], si));
+        }
+        const T g = a1 * (T)sLam[i] * MT::rcp(fma(a1, (T)sLam[i], a2));
+        mr[i] = g * sr;
+        mi[i] = g * si;
+    }
+    T2* x1 = x + x_off[2 * blockIdx.y] + (int64_t)n * M;
+    T2* x2 = x + x_off[2 * blockIdx.y + 1] + (int64_t)n * M;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        T sr = T(0), si = T(0);
+#pragma unroll
+        for (int b = 0; b < M; ++b) {
+            const double2 q = sQ[a * M + b];
+            sr = fma((T)q.x, mr[b], fma(-(T)q.y, mi[b], sr));
+            si = fma((T)q.x, mi[b], fma((T)q.y, mr[b], si));
+        }
+        T2 o1, o2;
+        o1.x = sr; o1.y = si;
+        o2.x = yr[a] - sr; o2.y = yi[a] - si;
+        x1[a] = o1;
+        x2[a] = o2;
+    }
+}
+
+hipError_t launch_separate(int M, bool fp64, const EmProblem* probs, int count, int max_n, const void* y,
+                           const void* v, const double2* P, const double* lam, void* x,
+                           const int64_t* x_off, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const dim3 grid((max_n + 255) / 256, count);
+    switch (M) {
+#define FCA_SEP_CASE(MM_)                                                                                        \
+    case MM_:                                                                                                    \
+        if (fp64)                                                                                                \
+            separate_kernel<MM_, double><<<grid, 256, 0, s>>>(probs, static_cast<const double2*>(y),              \
+                static_cast<const double*>(v), P, lam, static_cast<double2*>(x), x_off);                         \
+        else                                                                                                     \
+            separate_kernel<MM_, float><<<grid, 256, 0, s>>>(probs, static_cast<const float2*>(y),                \
+                static_cast<const float*>(v), P, lam, static_cast<float2*>(x), x_off);                           \
+        break;
+        FCA_SEP_CASE(1) FCA_SEP_CASE(2) FCA_SEP_CASE(3) FCA_SEP_CASE(4)
+        FCA_SEP_CASE(5) FCA_SEP_CASE(6) FCA_SEP_CASE(7) FCA_SEP_CASE(8)
+#undef FCA_SEP_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fca

@@ -1,0 +1,262 @@
+"""Thin ctypes binding of libfca.so (include/fca.h), same names as the C ABI.
+
+Argument marshalling only: every step of the EM runs in the library's HIP
+kernels; torch provides device memory and the stream. Inputs are torch
+tensors (device or host) or numpy arrays; outputs are allocated as torch
+tensors on the device of the input mixture. Loading fails loudly if the
+library has not been built (``python -m paper_1805_06572_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfca.so")
+
+FCA_OK = 0
+FCA_E_ARG = -1
+FCA_E_NOMEM = -2
+FCA_E_DEVICE = -3
+FCA_E_NOT_PD = -4
+FCA_E_NONFINITE = -5
+FCA_E_STATE = -6
+FCA_FP64 = 0
+FCA_FP32_BULK = 1
+FCA_FLAG_NOT_PD = 1
+FCA_FLAG_NONFINITE = 2
+FCA_FLAG_SWEEPS = 4
+STATUS_NAMES = {0: "FCA_OK", -1: "FCA_E_ARG", -2: "FCA_E_NOMEM", -3: "FCA_E_DEVICE",
+                -4: "FCA_E_NOT_PD", -5: "FCA_E_NONFINITE", -6: "FCA_E_STATE"}
+
+EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_em_step", "fca_separate",
+            "fca_status_per_freq", "fca_last_error", "fca_destroy", "fca_gevd", "fca_timing"]
+
+
+class fca_problem(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("F", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("y", ctypes.c_void_p), ("y_stride_f", ctypes.c_int64),
+                ("y_stride_n", ctypes.c_int64), ("y_stride_m", ctypes.c_int64),
+                ("R0", ctypes.c_void_p), ("v0", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
+
+
+class FcaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libfca.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                               "`python -m paper_1805_06572_amd.build` (there is no fallback path)")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.fca_init.argtypes = [ctypes.POINTER(fca_problem), ctypes.POINTER(vp)]
+        L.fca_init_batch.argtypes = [ctypes.POINTER(fca_problem), i32, ctypes.POINTER(vp)]
+        L.fca_reset.argtypes = [vp]
+        L.fca_em_step.argtypes = [vp, i32, vp, vp, vp]
+        L.fca_separate.argtypes = [vp, vp]
+        L.fca_status_per_freq.argtypes = [vp, vp]
+        L.fca_last_error.argtypes = [vp]
+        L.fca_last_error.restype = ctypes.c_char_p
+        L.fca_destroy.argtypes = [vp]
+        L.fca_destroy.restype = None
+        L.fca_gevd.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
+        L.fca_timing.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_em_step", "fca_separate",
+                     "fca_status_per_freq", "fca_gevd", "fca_timing"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def fca_last_error(ctx=None) -> str:
+    h = ctx.handle if ctx is not None else None
+    return lib().fca_last_error(h).decode()
+
+
+def _check(status: int, ctx=None, allow=()):
+    if status != FCA_OK and status not in allow:
+        raise FcaError(status, fca_last_error(ctx))
+    return status
+
+
+def _stream_handle(device: torch.device):
+    if device.type == "cuda":
+        return torch.cuda.current_stream(device).cuda_stream
+    return None
+
+
+def _as_tensor(a, dtype=None):
+    if a is None:
+        return None
+    t = torch.from_numpy(np.ascontiguousarray(a)) if isinstance(a, np.ndarray) else a
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return t
+
+
+@dataclass
+class Ctx:
+    """Handle of an fca_ctx plus the shapes needed to size outputs."""
+    handle: int
+    Ms: list
+    Ns: list
+    F: int
+    prec: int
+    device: torch.device
+
+    @property
+    def B(self):
+        return len(self.Ms)
+
+    @property
+    def real_dtype(self):
+        return torch.float64 if self.prec == FCA_FP64 else torch.float32
+
+    @property
+    def complex_dtype(self):
+        return torch.complex128 if self.prec == FCA_FP64 else torch.complex64
+
+
+def _problem(y, R0, v0, prec, stream):
+    """fca_problem for y[f, n, m] (any strides); keeps the tensors alive via the return."""
+    cdt = torch.complex128 if prec == FCA_FP64 else torch.complex64
+    rdt = torch.float64 if prec == FCA_FP64 else torch.float32
+    y = _as_tensor(y, cdt)
+    if y.dim() != 3:
+        raise ValueError("y must be [F, N, M]")
+    F, N, M = y.shape
+    R0 = _as_tensor(R0, torch.complex128)
+    v0 = _as_tensor(v0, rdt)
+    if R0 is not None:
+        R0 = R0.contiguous()
+        if tuple(R0.shape) != (2, F, M, M):
+            raise ValueError("R0 must be [2, F, M, M]")
+    if v0 is not None:
+        v0 = v0.contiguous()
+        if tuple(v0.shape) != (2, F, N):
+            raise ValueError("v0 must be [2, F, N]")
+    p = fca_problem(M=M, F=F, N=N, prec=prec, y=y.data_ptr(), y_stride_f=y.stride(0),
+                    y_stride_n=y.stride(1), y_stride_m=y.stride(2),
+                    R0=R0.data_ptr() if R0 is not None else None,
+                    v0=v0.data_ptr() if v0 is not None else None, stream=stream)
+    return p, (y, R0, v0), (M, F, N)
+
+
+def fca_init(y, R0=None, v0=None, prec=FCA_FP32_BULK) -> Ctx:
+    """Create a context for one mixture y[f, n, m] (torch or numpy)."""
+    return fca_init_batch([y], None if R0 is None else [R0], None if v0 is None else [v0], prec)
+
+
+def fca_init_batch(ys, R0s=None, v0s=None, prec=FCA_FP32_BULK) -> Ctx:
+    ys = [_as_tensor(y) for y in ys]
+    device = ys[0].device if isinstance(ys[0], torch.Tensor) else torch.device("cpu")
+    if device.type != "cuda":
+        device = torch.device("cuda", torch.cuda.current_device())
+    stream = _stream_handle(device)
+    R0s = R0s or [None] * len(ys)
+    v0s = v0s or [None] * len(ys)
+    probs, keep, shapes = [], [], []
+    for y, R0, v0 in zip(ys, R0s, v0s):
+        p, k, s = _problem(y, R0, v0, prec, stream)
+        probs.append(p)
+        keep.append(k)
+        shapes.append(s)
+    arr = (fca_problem * len(probs))(*probs)
+    h = ctypes.c_void_p()
+    _check(lib().fca_init_batch(arr, len(probs), ctypes.byref(h)))
+    del keep
+    return Ctx(handle=h.value, Ms=[s[0] for s in shapes], Ns=[s[2] for s in shapes], F=shapes[0][1],
+               prec=prec, device=device)
+
+
+def fca_reset(ctx: Ctx):
+    _check(lib().fca_reset(ctx.handle), ctx)
+
+
+def fca_em_step(ctx: Ctx, iters: int, want_loglik=True, want_R=True, want_v=True, allow_flags=False):
+    """Run `iters` EM iterations. Returns (loglik [B, max(iters,1)] float64,
+    R list of [2, F, M, M] complex128, v list of [2, F, N]) on the context's
+    device (entries not requested are None)."""
+    B, F = ctx.B, ctx.F
+    dev = ctx.device
+    ll = torch.empty((B, max(iters, 1)), dtype=torch.float64, device=dev) if want_loglik else None
+    nR = sum(2 * F * m * m for m in ctx.Ms)
+    nv = sum(2 * F * n for n in ctx.Ns)
+    R = torch.empty(nR, dtype=torch.complex128, device=dev) if want_R else None
+    v = torch.empty(nv, dtype=ctx.real_dtype, device=dev) if want_v else None
+    allow = (FCA_E_NOT_PD, FCA_E_NONFINITE) if allow_flags else ()
+    _check(lib().fca_em_step(ctx.handle, iters, ll.data_ptr() if ll is not None else None,
+                             R.data_ptr() if R is not None else None,
+                             v.data_ptr() if v is not None else None), ctx, allow)
+    Rs = vs = None
+    if want_R:
+        Rs, o = [], 0
+        for m in ctx.Ms:
+            Rs.append(R[o:o + 2 * F * m * m].view(2, F, m, m))
+            o += 2 * F * m * m
+    if want_v:
+        vs, o = [], 0
+        for n in ctx.Ns:
+            vs.append(v[o:o + 2 * F * n].view(2, F, n))
+            o += 2 * F * n
+    return ll, Rs, vs
+
+
+def fca_separate(ctx: Ctx):
+    """MMSE source images, list of [2, F, N, M] complex tensors (one per mixture)."""
+    tot = sum(2 * ctx.F * n * m for n, m in zip(ctx.Ns, ctx.Ms))
+    x = torch.empty(tot, dtype=ctx.complex_dtype, device=ctx.device)
+    _check(lib().fca_separate(ctx.handle, x.data_ptr()), ctx)
+    out, o = [], 0
+    for n, m in zip(ctx.Ns, ctx.Ms):
+        out.append(x[o:o + 2 * ctx.F * n * m].view(2, ctx.F, n, m))
+        o += 2 * ctx.F * n * m
+    return out
+
+
+def fca_status_per_freq(ctx: Ctx) -> np.ndarray:
+    flags = np.zeros((ctx.B, ctx.F), np.int32)
+    _check(lib().fca_status_per_freq(ctx.handle, flags.ctypes.data), ctx)
+    return flags
+
+
+def fca_destroy(ctx: Ctx):
+    if ctx is not None and ctx.handle:
+        lib().fca_destroy(ctx.handle)
+        ctx.handle = None
+
+
+def fca_gevd(S1: torch.Tensor, S2: torch.Tensor):
+    """Batched FP64 GEVD of device tensors S1, S2 [count, M, M] complex128.
+    Returns (P [count, M, M], lam [count, M], flags [count])."""
+    if S1.dtype != torch.complex128 or S2.dtype != torch.complex128:
+        raise TypeError("S1 and S2 must be complex128")
+    S1 = S1.contiguous()
+    S2 = S2.contiguous()
+    count, M, _ = S1.shape
+    P = torch.empty_like(S1)
+    lam = torch.empty((count, M), dtype=torch.float64, device=S1.device)
+    flags = torch.empty((count,), dtype=torch.int32, device=S1.device)
+    _check(lib().fca_gevd(M, count, S1.data_ptr(), S2.data_ptr(), P.data_ptr(), lam.data_ptr(),
+                          flags.data_ptr(), _stream_handle(S1.device)))
+    return P, lam, flags
+
+
+def fca_timing(ctx: Ctx, enable: bool):
+    """(EM-kernel milliseconds, launches) since the last call; sets timing on/off."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().fca_timing(ctx.handle, 1 if enable else 0, ctypes.byref(ms), ctypes.byref(n)), ctx)
+    return ms.value, n.value
