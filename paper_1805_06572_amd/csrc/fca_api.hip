@@ -175,8 +175,9 @@ fca_status do_reset(fca_ctx* c) {
                                       2ull * c->F * mi.npad * c->rsz, hipMemcpyDeviceToDevice, s));
         } else {
             const void* yb = static_cast<char*>(c->y) + mi.y_base * c->esz;
-            FCA_HIP(c, launch_power_sums(c->fp64, yb, mi.M, c->F, mi.N, mi.npad, c->fsum + mi.pid0, s));
-            FCA_HIP(c, launch_default_v(c->fp64, yb, c->fsum + mi.pid0, mi.M, c->F, mi.N, mi.npad, v, s));
+            double* fs = c->fsum + (int64_t)b * (c->F + 1);
+            FCA_HIP(c, launch_power_sums(c->fp64, yb, mi.M, c->F, mi.N, mi.npad, fs, s));
+            FCA_HIP(c, launch_default_v(c->fp64, yb, fs, mi.M, c->F, mi.N, mi.npad, v, s));
         }
         const int64_t mm = (int64_t)mi.M * mi.M;
         const double2* R1 = c->R_init + mi.R_base;
@@ -289,7 +290,7 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     FCA_TRY(dev_alloc(c, &c->flags, (size_t)c->nprob * sizeof(int)));
     FCA_TRY(dev_alloc(c, &c->ll, (size_t)kLChunk * c->nprob * sizeof(double)));
     FCA_TRY(dev_alloc(c, &c->ll_tot, (size_t)kLChunk * B * sizeof(double)));
-    FCA_TRY(dev_alloc(c, &c->fsum, (size_t)c->nprob * sizeof(double)));
+    FCA_TRY(dev_alloc(c, &c->fsum, (size_t)B * (c->F + 1) * sizeof(double)));
     FCA_TRY(dev_alloc(c, &c->R_stage, 2ull * c->F * maxM * maxM * sizeof(double2)));
     FCA_TRY(dev_alloc(c, &c->probs, (size_t)c->nprob * sizeof(EmProblem)));
     FCA_TRY(dev_alloc(c, &c->x_off, (size_t)c->nprob * 2 * sizeof(int64_t)));

@@ -65,60 +65,102 @@ template <> struct Math<double> {
     static __device__ __forceinline__ double log(double x) { return ::log(x); }
 };
 
+// ---------------------------------------------------------------- FP64 helpers
+// Hardware reciprocal / reciprocal square root refined by two Newton steps
+// (full double precision for normal positive inputs).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    r = r * fma(-h * r, r, 1.5);
+    return r * fma(-h * r, r, 1.5);
+}
+
+// Orders the LDS accesses of one wavefront: a wave executes its LDS
+// instructions in issue order, so after this point every lane sees what the
+// other lanes of the same wave stored before it. Also a compiler barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- GEVD (FP64)
-// Generalized eigendecomposition of the pencil (A, B), A Hermitian, B
-// Hermitian positive definite, folded into a basis update: on return
-// Pnew = Pold * Q with Q^H B Q = I and Q^H A Q = diag(lam), and
-// *dlogdet = -log det B (= log |det Q|^2). One thread; every array index is a
-// compile-time constant after unrolling so the working matrices live in
-// registers. A, B and Pold are full M x M row-major (Hermitian inputs: the
-// upper triangle is used). Returns FCA flag bits (0 on success).
+// Working storage of one wave-parallel eigendecomposition (in LDS).
+struct GevdScratch {
+    double2 W[kMaxM * kMaxM];   // L^-1 (row-major, stride M)
+    double2 T[kMaxM * kMaxM];   // L^-1 A (stride MP)
+    double2 C[kMaxM * kMaxM];   // working Hermitian matrix (stride MP)
+    double2 V[kMaxM * kMaxM];   // accumulated basis (stride MP)
+    double4 prm[kMaxM];         // rotation of the pair containing index k: (c, g.re, g.im, t|h|)
+};
+
+template <int M> struct GevdShape {
+    static constexpr int MP = M <= 1 ? 1 : M <= 2 ? 2 : M <= 4 ? 4 : 8;  // padded order
+    static constexpr int LG = MP == 1 ? 0 : MP == 2 ? 1 : MP == 4 ? 2 : 3;
+};
+
+// Generalized eigendecomposition of the Hermitian-definite pencil (A, B),
+// folded into a basis update: Pnew = Pold Q with Q^H B Q = I and
+// Q^H A Q = diag(lam); *dlogdet = -log det B = log|det Q|^2. This is the
+// per-frequency step of the FastFCA iteration (eqs. GEVDeff5, updatePeff,
+// updateLambdaeff); the Appendix theorem guarantees Q exists when B is
+// positive definite.
 //
-// Method: B = L L^H (Cholesky); C = L^-1 A L^-H; cyclic complex Jacobi
-// rotations diagonalise C = W diag(lam) W^H and are applied to the columns
-// of V = Pold L^-H, so V ends as Pold L^-H W = Pold Q. (The Appendix proof
-// whitens with the eigendecomposition of B instead; any factor of B gives
-// the same pencil eigenvalues and a valid Q.)
+// Called by all 64 lanes of ONE wavefront (uniform control flow). A, B, Pold
+// are full M x M row-major in LDS (Hermitian inputs; the upper triangle of B
+// is what the factorisation reads). Pnew and lam may be LDS or global.
+// Returns FCA flag bits (0 on success); on failure nothing is written.
+//
+// Method: B = L L^H by Cholesky (computed redundantly by every lane, so it is
+// uniform), W = L^-1; lane (i,k) of the MP x MP grid (M padded to a power of
+// two with zero rows/columns) then holds C_ik of C = W A W^H and V_ik of
+// V = Pold W^H. Jacobi rounds x = 1..MP-1 pair every index k with k XOR x;
+// the MP/2 disjoint rotations of a round are applied together, so each
+// sweep rotates every pair once. The rotation of (p,q), p < q, is
+// G_pp = G_qq = c, G_pq = g = s e, G_qp = -conj(g), e = C_pq/|C_pq|,
+// t = s/c = sign(tau)/(|tau| + sqrt(1+tau^2)), tau = (C_qq - C_pp)/(2|C_pq|):
+// it zeroes C_pq and moves C_pp -= t|C_pq|, C_qq += t|C_pq|. Rotations are
+// skipped when |C_pq|^2 <= eps2 |C_pp C_qq|, and sweeps stop once every
+// off-diagonal entry passes that test. At the end C = diag(lam), V = Pold Q.
+// (The Appendix proof whitens B by its eigendecomposition; a Cholesky factor
+// gives the same eigenvalues and an equally valid Q.)
 template <int M>
-__host__ __device__ int gevd_update(const double2* __restrict__ A, const double2* __restrict__ B,
-                           const double2* __restrict__ Pold, double2* __restrict__ Pnew,
-                           double* __restrict__ lam, double* __restrict__ dlogdet, int* sweeps_used) {
-    // ---- Cholesky B = L L^H; W = L^-1 (both lower triangular)
+__device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold, GevdScratch& ws,
+                         double2* Pnew, double* lam, double* dlogdet, double eps2) {
+    constexpr int MP = GevdShape<M>::MP;
+    constexpr int LG = GevdShape<M>::LG;
+    const int lane = threadIdx.x & 63;
+    const int i = lane >> LG, k = lane & (MP - 1);
+    const bool act = lane < MP * MP;
+    const bool in = act && i < M && k < M;
+
+    // ---- Cholesky B = L L^H and W = L^-1, uniform across lanes
     double2 L[M][M];
     double pivprod = 1.0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         double d = B[j * M + j].x;
 #pragma unroll
-        for (int k = 0; k < j; ++k) d -= cabs2(L[j][k]);
+        for (int q = 0; q < j; ++q) d -= cabs2(L[j][q]);
         if (!(d > 0.0) || !__builtin_isfinite(d)) return kFlagNotPD;
         pivprod *= d;
-        const double ljj = sqrt(d);
-        const double inv = 1.0 / ljj;
-        L[j][j] = make_double2(ljj, 0.0);
+        const double inv = rsqrt_nr(d);
+        L[j][j] = make_double2(d * inv, 0.0);
 #pragma unroll
-        for (int i = j + 1; i < M; ++i) {
-            // B is Hermitian: B[i][j] = conj(B[j][i]) from the upper triangle
-            double2 s = cconj(B[j * M + i]);
+        for (int r = j + 1; r < M; ++r) {
+            double2 s = cconj(B[j * M + r]);
 #pragma unroll
-            for (int k = 0; k < j; ++k) s = csub(s, cmulc(L[i][k], L[j][k]));
-            L[i][j] = cscale(inv, s);
+            for (int q = 0; q < j; ++q) s = csub(s, cmulc(L[r][q], L[j][q]));
+            L[r][j] = cscale(inv, s);
         }
     }
-    double2 W[M][M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) W[j][j] = make_double2(1.0 / L[j][j].x, 0.0);
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-#pragma unroll
-        for (int i = j + 1; i < M; ++i) {
-            double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int k = j; k < i; ++k) s = cfma(L[i][k], W[k][j], s);
-            W[i][j] = cscale(-W[i][i].x, s);
-        }
-    }
-    // log det B = log prod_j L_jj^2; fall back to a sum of logs on range trouble
     double ld;
     if (pivprod > 1e-300 && pivprod < 1e300) {
         ld = ::log(pivprod);
@@ -127,116 +169,134 @@ __host__ __device__ int gevd_update(const double2* __restrict__ A, const double2
 #pragma unroll
         for (int j = 0; j < M; ++j) ld += 2.0 * ::log(L[j][j].x);
     }
-    *dlogdet = -ld;
-
-    // ---- C = W A W^H (Hermitian; upper triangle kept, diagonal real)
-    double2 T[M][M];  // T = W A
+    if (lane == 0) {
+        double2 Wr[M][M];
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
+        for (int j = 0; j < M; ++j) Wr[j][j] = make_double2(rcp_nr(L[j][j].x), 0.0);
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            double2 s = make_double2(0.0, 0.0);
+        for (int j = 0; j < M; ++j) {
 #pragma unroll
-            for (int a = 0; a <= i; ++a) {
-                const double2 Aak = (a <= k) ? A[a * M + k] : cconj(A[k * M + a]);
-                s = cfma(W[i][a], (a == k) ? make_double2(Aak.x, 0.0) : Aak, s);
+            for (int r = j + 1; r < M; ++r) {
+                double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int q = j; q < r; ++q) s = cfma(L[r][q], Wr[q][j], s);
+                Wr[r][j] = cscale(-Wr[r][r].x, s);
             }
-            T[i][k] = s;
         }
+#pragma unroll
+        for (int r = 0; r < M; ++r)
+#pragma unroll
+            for (int j = 0; j <= r; ++j) ws.W[r * M + j] = Wr[r][j];
     }
-    double2 C[M][M];
+    wave_lds_sync();
+
+    // ---- T = W A (row i of lane), then C = T W^H and V = Pold W^H
+    if (in) {
+        double2 t = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-#pragma unroll
-        for (int k = i; k < M; ++k) {
-            double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int b = 0; b <= k; ++b) s = cfmac(T[i][b], W[k][b], s);
-            C[i][k] = s;
-        }
-        C[i][i].y = 0.0;
+        for (int a = 0; a < M; ++a)
+            if (a <= i) t = cfma(ws.W[i * M + a], A[a * M + k], t);
+        ws.T[i * MP + k] = t;
     }
-    // ---- V = Pold W^H
-    double2 V[M][M];
+    wave_lds_sync();
+    double2 c = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
+    if (in) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int b = 0; b <= k; ++b) s = cfmac(Pold[i * M + b], W[k][b], s);
-            V[i][k] = s;
+        for (int b = 0; b < M; ++b) {
+            if (b <= k) {
+                const double2 w = ws.W[k * M + b];
+                c = cfmac(ws.T[i * MP + b], w, c);
+                v = cfmac(Pold[i * M + b], w, v);
+            }
         }
+        if (i == k) c.y = 0.0;
     }
 
-    // ---- cyclic Jacobi on C (upper triangle), rotations applied to V.
-    // Rotation of the (p,q) plane: G_pp = G_qq = c, G_pq = s e, G_qp = -s conj(e)
-    // with e = C_pq / |C_pq|, t = s / c = sign(tau) / (|tau| + sqrt(1 + tau^2)),
-    // tau = (C_qq - C_pp) / (2 |C_pq|). Then (G^H C G)_pq = 0,
-    // C_pp -= t |C_pq|, C_qq += t |C_pq|. A rotation is skipped when
-    // |C_pq|^2 <= eps^2 |C_pp C_qq| (relative threshold, eps = 1e-15).
+    // ---- Jacobi sweeps
     int flag = 0;
     int sweep = 0;
-    for (; sweep < kJacobiMaxSweeps; ++sweep) {
-        bool rotated = false;
-#pragma unroll
-        for (int p = 0; p < M - 1; ++p) {
-#pragma unroll
-            for (int q = p + 1; q < M; ++q) {
-                const double2 h = C[p][q];
+    for (;; ++sweep) {
+        // convergence test on the current matrix
+        if (act) ws.C[lane] = c;
+        wave_lds_sync();
+        bool open = false;
+        if (in && i < k) {
+            const double a = ws.C[i * MP + i].x, b = ws.C[k * MP + k].x;
+            const double hh = cabs2(c);
+            open = hh > eps2 * fabs(a * b) && hh > 1e-300;
+        }
+        if (!__any(open)) break;
+        if (sweep == kJacobiMaxSweeps) {
+            flag |= kFlagSweeps;
+            break;
+        }
+#pragma unroll 1
+        for (int x = 1; x < MP; ++x) {
+            const int k2 = k ^ x, i2 = i ^ x;
+            if (act) {
+                ws.C[lane] = c;
+                ws.V[lane] = v;
+            }
+            wave_lds_sync();
+            double cc = 1.0, th = 0.0;
+            double2 g = make_double2(0.0, 0.0);
+            double2 cik2 = c, ci2k = c, ci2k2 = c, vik2 = v;
+            if (act) {
+                const int p = k < k2 ? k : k2, q = k ^ k2 ^ p;
+                const double a = ws.C[p * MP + p].x, b = ws.C[q * MP + q].x;
+                const double2 h = ws.C[p * MP + q];
+                cik2 = ws.C[i * MP + k2];
+                ci2k = ws.C[i2 * MP + k];
+                ci2k2 = ws.C[i2 * MP + k2];
+                vik2 = ws.V[i * MP + k2];
                 const double hh = cabs2(h);
-                const double a = C[p][p].x, b = C[q][q].x;
-                if (hh > 1e-30 * fabs(a * b) && hh > 1e-300) {
-                    rotated = true;
-                    const double habs = sqrt(hh);
-                    const double rh = 1.0 / habs;
+                if (hh > eps2 * fabs(a * b) && hh > 1e-300) {
+                    const double rh = rsqrt_nr(hh);
+                    const double habs = hh * rh;
                     const double tau = 0.5 * (b - a) * rh;
-                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(fma(tau, tau, 1.0)));
-                    const double c = 1.0 / sqrt(fma(t, t, 1.0));
-                    const double s = t * c;
-                    const double2 e = cscale(rh, h);
-                    const double2 se = cscale(s, e);           // s e
-                    const double2 sec = cconj(se);             // s conj(e)
-                    C[p][p].x = a - t * habs;
-                    C[q][q].x = b + t * habs;
-                    C[p][q] = make_double2(0.0, 0.0);
-#pragma unroll
-                    for (int k = 0; k < M; ++k) {
-                        if (k == p || k == q) continue;
-                        // column entries C_kp, C_kq from the stored upper triangle
-                        const double2 ckp = (k < p) ? C[k][p] : cconj(C[p][k]);
-                        const double2 ckq = (k < q) ? C[k][q] : cconj(C[q][k]);
-                        const double2 nkp = csub(cscale(c, ckp), cmul(sec, ckq));
-                        const double2 nkq = cadd(cmul(se, ckp), cscale(c, ckq));
-                        if (k < p) C[k][p] = nkp; else C[p][k] = cconj(nkp);
-                        if (k < q) C[k][q] = nkq; else C[q][k] = cconj(nkq);
+                    const double at = fabs(tau);
+                    // sqrt(1 + tau^2) without overflow for large |tau|
+                    double root;
+                    if (at > 1.0) {
+                        const double u = rcp_nr(at);
+                        const double w2 = fma(u, u, 1.0);
+                        root = at * (w2 * rsqrt_nr(w2));
+                    } else {
+                        const double w2 = fma(tau, tau, 1.0);
+                        root = w2 * rsqrt_nr(w2);
                     }
-#pragma unroll
-                    for (int i = 0; i < M; ++i) {
-                        const double2 vp = V[i][p], vq = V[i][q];
-                        V[i][p] = csub(cscale(c, vp), cmul(sec, vq));
-                        V[i][q] = cadd(cmul(se, vp), cscale(c, vq));
-                    }
+                    const double t = copysign(rcp_nr(at + root), tau);
+                    cc = rsqrt_nr(fma(t, t, 1.0));
+                    const double s = t * cc;
+                    g = make_double2(s * h.x * rh, s * h.y * rh);
+                    th = t * habs;
                 }
+                if (i == 0) ws.prm[k] = make_double4(cc, g.x, g.y, th);
+            }
+            wave_lds_sync();
+            if (act) {
+                const double4 pr = ws.prm[i];
+                // column factor G_{k2,k} and conjugated row factor conj(G_{i2,i})
+                const double2 gk = (k < k2) ? make_double2(-g.x, g.y) : g;
+                const double2 gi = (i < i2) ? make_double2(-pr.y, -pr.z) : make_double2(pr.y, -pr.z);
+                const double ci = pr.x;
+                double2 cn = cadd(cscale(ci, cadd(cscale(cc, c), cmul(gk, cik2))),
+                                  cmul(gi, cadd(cscale(cc, ci2k), cmul(gk, ci2k2))));
+                if (k == i) cn = make_double2(c.x + ((i < i2) ? -th : th), 0.0);
+                else if (k == i2 && th != 0.0) cn = make_double2(0.0, 0.0);
+                v = cadd(cscale(cc, v), cmul(gk, vik2));
+                c = cn;
             }
         }
-        if (!rotated) break;
     }
-    if (sweep == kJacobiMaxSweeps) flag |= kFlagSweeps;
-    *sweeps_used = sweep;
 
-    bool finite = true;
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-        lam[i] = C[i][i].x;
-        finite = finite && __builtin_isfinite(lam[i]);
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            Pnew[i * M + k] = V[i][k];
-            finite = finite && cfinite(V[i][k]);
-        }
+    bool finite = !in || (cfinite(v) && (i != k || __builtin_isfinite(c.x)));
+    if (in) {
+        Pnew[i * M + k] = v;
+        if (i == k) lam[i] = c.x;
     }
-    if (!finite || !__builtin_isfinite(*dlogdet)) flag |= kFlagNonFinite;
+    if (!__all(finite) || !__builtin_isfinite(ld)) flag |= kFlagNonFinite;
+    *dlogdet = -ld;
     return flag;
 }
 

@@ -46,7 +46,8 @@ hipError_t launch_ingest(bool fp64, const void* src, int64_t sf, int64_t sn, int
 hipError_t launch_power_sums(bool fp64, const void* y, int M, int F, int N, int npad,
                              double* fsum, hipStream_t s);
 
-hipError_t launch_default_v(bool fp64, const void* y, const double* fsum, int M, int F, int N,
+// fsum holds F per-frequency power sums followed by one slot for the floor.
+hipError_t launch_default_v(bool fp64, const void* y, double* fsum, int M, int F, int N,
                             int npad, void* v, hipStream_t s);
 
 hipError_t launch_copy_v_in(bool fp64, const void* v0, int F, int N, int npad, void* v,

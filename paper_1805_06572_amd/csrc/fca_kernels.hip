@@ -29,6 +29,13 @@ template <> struct Vec2<double> { using type = double2; };
 
 constexpr double kLogPi = 1.1447298858494002;
 
+template <typename T> __device__ __forceinline__ typename Vec2<T>::type make_vec2(T x, T y) {
+    typename Vec2<T>::type r;
+    r.x = x;
+    r.y = y;
+    return r;
+}
+
 // Index of the off-diagonal pair (i < k) of an M x M matrix, row-major over
 // the strict upper triangle.
 __host__ __device__ constexpr int pair_index(int M, int i, int k) {
@@ -37,11 +44,11 @@ __host__ __device__ constexpr int pair_index(int M, int i, int k) {
 
 // ============================================================== EM kernel
 template <int M, typename T, int FPT>
-__global__ __launch_bounds__(kEmThreads) void em_kernel(
+__global__ __launch_bounds__(kEmThreads) __attribute__((amdgpu_waves_per_eu(3))) void em_kernel(
     const EmProblem* __restrict__ probs, const typename Vec2<T>::type* __restrict__ y,
     T* __restrict__ v, double2* __restrict__ Pg, double* __restrict__ lamg,
     double* __restrict__ logdetg, int* __restrict__ flagsg, double* __restrict__ ll,
-    int64_t ll_stride, int iters) {
+    int64_t ll_stride, int iters, double eps2) {
     using T2 = typename Vec2<T>::type;
     using MT = Math<T>;
     constexpr int NT = kEmThreads;
@@ -54,6 +61,8 @@ __global__ __launch_bounds__(kEmThreads) void em_kernel(
 
     __shared__ double2 sP[MM];
     __shared__ double2 sPn[MM];
+    __shared__ T2 sPt[MM];
+    __shared__ T sLamT[M];
     __shared__ double sLam[M];
     __shared__ double sLamN[M];
     __shared__ double sLogdet;
@@ -64,6 +73,7 @@ __global__ __launch_bounds__(kEmThreads) void em_kernel(
     __shared__ T sRed[NT * (CH + 1)];
     __shared__ double sRed2[G * CH];
     __shared__ double sLL[NW];
+    __shared__ GevdScratch sWs;
 
     const EmProblem pr = probs[blockIdx.x];
     const int tid = threadIdx.x;
@@ -104,18 +114,16 @@ __global__ __launch_bounds__(kEmThreads) void em_kernel(
     const int ll_count = iters > 0 ? iters : 1;
 
     for (int it = 0; it < passes; ++it) {
-        // ---- per-frequency constants in the bulk precision
-        T Pr[M][M], Pi[M][M], lm[M];
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-            lm[a] = (T)sLam[a];
-#pragma unroll
-            for (int b = 0; b < M; ++b) {
-                const double2 p = sP[a * M + b];
-                Pr[a][b] = (T)p.x;
-                Pi[a][b] = (T)p.y;
-            }
+        // ---- per-frequency constants in the bulk precision (LDS copy)
+        if (tid < MM) {
+            const double2 p = sP[tid];
+            sPt[tid] = make_vec2<T>((T)p.x, (T)p.y);
         }
+        if (tid < M) sLamT[tid] = (T)sLam[tid];
+        __syncthreads();
+        T lm[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) lm[a] = sLamT[a];
         T acc[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) acc[i] = T(0);
@@ -130,6 +138,12 @@ __global__ __launch_bounds__(kEmThreads) void em_kernel(
             if (k * NT >= nf) continue;  // uniform: the whole block of frames is padding
             const bool ok = (k * NT + tid) < nf;
             const T a1 = v1[k], a2 = v2[k];
+            // P is re-read from LDS for every frame (a broadcast read) rather
+            // than held in registers across the frame loop, and frames are not
+            // interleaved by the scheduler: both keep the register count low
+            // enough for three workgroups per CU.
+            __asm__ volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
             // eq. (tildey): y~_i = sum_m conj(P_mi) y_m
             T ytr[M], yti[M], e[M], r[M];
 #pragma unroll
@@ -137,8 +151,9 @@ __global__ __launch_bounds__(kEmThreads) void em_kernel(
                 T sr = T(0), si = T(0);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
-                    sr = fma(Pr[m][i], yr[k][m], fma(Pi[m][i], yi[k][m], sr));
-                    si = fma(Pr[m][i], yi[k][m], fma(-Pi[m][i], yr[k][m], si));
+                    const T2 pmi = sPt[m * M + i];
+                    sr = fma(pmi.x, yr[k][m], fma(pmi.y, yi[k][m], sr));
+                    si = fma(pmi.x, yi[k][m], fma(-pmi.y, yr[k][m], si));
                 }
                 ytr[i] = sr;
                 yti[i] = si;
@@ -257,33 +272,32 @@ __global__ __launch_bounds__(kEmThreads) void em_kernel(
         }
         __syncthreads();
 
-        // ---- record LL(theta^(it)); GEVD and basis update by one thread
-        if (tid == 0) {
+        // ---- record LL(theta^(it)); GEVD and basis update by wave 0
+        if (tid < 64) {
+            const bool last = (iters == 0) || frozen_at_entry;
             double tot = 0.0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) tot += sLL[w];
             tot += (double)nf * (-(double)M * kLogPi + sLogdet);
-            const bool last = (iters == 0) || frozen_at_entry;
             if (last) {
-                for (int l = it; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
+                if (tid == 0)
+                    for (int l = it; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
             } else {
-                ll[(int64_t)it * ll_stride + pid] = tot;
-                int flag = 0;
-                if (sBad) flag = kFlagNonFinite;
+                if (tid == 0) ll[(int64_t)it * ll_stride + pid] = tot;
+                int flag = sBad ? kFlagNonFinite : 0;
                 double dld = 0.0;
-                int sweeps = 0;
-                if (!flag) flag = gevd_update<M>(sS[0], sS[1], sP, sPn, sLamN, &dld, &sweeps);
-                sFlag |= flag;
+                if (!flag) flag = gevd_wave<M>(sS[0], sS[1], sP, sWs, sPn, sLamN, &dld, eps2);
+                wave_lds_sync();
                 if (flag & kFreezeMask) {
                     // frozen at theta^(it): its log-likelihood stands for later iterations
-                    for (int l = it + 1; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
+                    if (tid == 0)
+                        for (int l = it + 1; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
                 } else {
-#pragma unroll
-                    for (int i = 0; i < MM; ++i) sP[i] = sPn[i];
-#pragma unroll
-                    for (int i = 0; i < M; ++i) sLam[i] = sLamN[i];
-                    sLogdet += dld;
+                    if (tid < MM) sP[tid] = sPn[tid];
+                    if (tid < M) sLam[tid] = sLamN[tid];
+                    if (tid == 0) sLogdet += dld;
                 }
+                if (tid == 0) sFlag |= flag;
             }
         }
         __syncthreads();
@@ -314,19 +328,26 @@ __global__ __launch_bounds__(kEmThreads) void em_kernel(
     }
 }
 
+// Jacobi stopping threshold (squared, relative): full double precision in
+// FP64 mode; 1e-8 in the float bulk mode, where the per-bin arithmetic is
+// itself only float-accurate (the eigendecomposition still runs in double).
+constexpr double kEps2Fp64 = 1e-30;
+constexpr double kEps2Fp32Bulk = 1e-16;
+
 template <int M, typename T>
 static hipError_t launch_em_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v,
                                 double2* P, double* lam, double* logdet, int* flags, double* ll,
                                 int64_t ll_stride, int iters, hipStream_t s) {
     using T2 = typename Vec2<T>::type;
+    const double eps2 = sizeof(T) == 8 ? kEps2Fp64 : kEps2Fp32Bulk;
     const dim3 grid(count), block(kEmThreads);
     const T2* yy = static_cast<const T2*>(y);
     T* vv = static_cast<T*>(v);
     switch (fpt) {
-        case 1: em_kernel<M, T, 1><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
-        case 2: em_kernel<M, T, 2><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
-        case 4: em_kernel<M, T, 4><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
-        case 8: em_kernel<M, T, 8><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
+        case 1: em_kernel<M, T, 1><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, eps2); break;
+        case 2: em_kernel<M, T, 2><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, eps2); break;
+        case 4: em_kernel<M, T, 4><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, eps2); break;
+        case 8: em_kernel<M, T, 8><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, eps2); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -427,22 +448,32 @@ hipError_t launch_power_sums(bool fp64, const void* y, int M, int F, int N, int 
     return hipGetLastError();
 }
 
-// v_j(n,f) = max(||y(n,f)||^2 / M, floor), floor = 1e-12 * mean over bins
-// (1 if the mean is zero); padding frames get 1.
+// floor = 1e-12 * mean over bins of ||y||^2 / M (1 if that mean is zero),
+// from the per-frequency sums in a fixed order; stored at fsum[F].
+__global__ void power_floor_kernel(double* __restrict__ fsum, int F, int N) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int g = threadIdx.x; g < F; g += 256) s += fsum[g];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mean = red[0] / ((double)F * (double)N);
+        fsum[F] = mean > 0.0 ? 1e-12 * mean : 1.0;
+    }
+}
+
+// v_j(n,f) = max(||y(n,f)||^2 / M, floor) for both sources; padding frames get 1.
 template <typename T, typename T2>
 __global__ void default_v_kernel(const T2* __restrict__ y, const double* __restrict__ fsum, int M, int F,
                                  int N, int npad, T* __restrict__ v) {
-    __shared__ double s_floor;
     const int f = blockIdx.y;
-    if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int g = 0; g < F; ++g) tot += fsum[g];
-        const double mean = tot / ((double)F * (double)N);
-        s_floor = mean > 0.0 ? 1e-12 * mean : 1.0;
-    }
-    __syncthreads();
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= npad) return;
+    const double vfloor = fsum[F];
     double val = 1.0;
     if (n < N) {
         double p = 0.0;
@@ -451,14 +482,15 @@ __global__ void default_v_kernel(const T2* __restrict__ y, const double* __restr
             p += (double)yy.x * (double)yy.x + (double)yy.y * (double)yy.y;
         }
         val = p / M;
-        if (!(val >= s_floor)) val = s_floor;
+        if (!(val >= vfloor)) val = vfloor;
     }
     v[(int64_t)f * npad + n] = (T)val;
     v[((int64_t)F + f) * npad + n] = (T)val;
 }
 
-hipError_t launch_default_v(bool fp64, const void* y, const double* fsum, int M, int F, int N, int npad,
+hipError_t launch_default_v(bool fp64, const void* y, double* fsum, int M, int F, int N, int npad,
                             void* v, hipStream_t s) {
+    power_floor_kernel<<<1, 256, 0, s>>>(fsum, F, N);
     const dim3 grid((npad + 255) / 256, F);
     if (fp64)
         default_v_kernel<double, double2><<<grid, 256, 0, s>>>(static_cast<const double2*>(y), fsum, M, F, N, npad, static_cast<double*>(v));
@@ -488,52 +520,53 @@ hipError_t launch_copy_v_in(bool fp64, const void* v0, int F, int N, int npad, v
 }
 
 // ============================================================== batched GEVD
-// One thread per pencil (A, B) at A + i*stride_a, B + i*stride_b, starting
+// One wavefront per pencil (A, B) at A + i*stride_a, B + i*stride_b, starting
 // from the identity basis: P + i*stride_p receives Q (M x M), lam +
 // i*stride_l the eigenvalues, logdet[i] = log|det Q|^2 = -log det B (if
 // logdet is not null) and flags[i] the FCA flag bits. On failure P = I and
 // lam = 1.
 template <int M>
-__global__ void gevd_kernel(int count, const double2* __restrict__ A, const double2* __restrict__ B,
-                            int64_t stride_a, int64_t stride_b, double2* __restrict__ P, int64_t stride_p,
-                            double* __restrict__ lam, int64_t stride_l, double* __restrict__ logdet,
-                            int* __restrict__ flags) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    double2 Id[M * M];
-#pragma unroll
-    for (int a = 0; a < M * M; ++a) Id[a] = make_double2((a % (M + 1)) == 0 ? 1.0 : 0.0, 0.0);
-    double2 Pn[M * M];
-    double ln[M];
-    double dld = 0.0;
-    int sweeps = 0;
-    const int flag = gevd_update<M>(A + i * stride_a, B + i * stride_b, Id, Pn, ln, &dld, &sweeps);
-    if (!(flag & kFreezeMask)) {
-#pragma unroll
-        for (int a = 0; a < M * M; ++a) P[i * stride_p + a] = Pn[a];
-#pragma unroll
-        for (int a = 0; a < M; ++a) lam[i * stride_l + a] = ln[a];
-    } else {
-#pragma unroll
-        for (int a = 0; a < M * M; ++a) P[i * stride_p + a] = Id[a];
-#pragma unroll
-        for (int a = 0; a < M; ++a) lam[i * stride_l + a] = 1.0;
-        dld = 0.0;
+__global__ __launch_bounds__(64) void gevd_kernel(const double2* __restrict__ A, const double2* __restrict__ B,
+                                                  int64_t stride_a, int64_t stride_b, double2* __restrict__ P,
+                                                  int64_t stride_p, double* __restrict__ lam, int64_t stride_l,
+                                                  double* __restrict__ logdet, int* __restrict__ flags) {
+    constexpr int MM = M * M;
+    __shared__ double2 sA[MM], sB[MM], sId[MM], sPn[MM];
+    __shared__ double sLam[M];
+    __shared__ GevdScratch sWs;
+    const int64_t i = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tid < MM) {
+        const int r = tid / M, c = tid % M;
+        // Hermitian inputs: build the full matrices from the upper triangles
+        const double2 a = (r <= c) ? A[i * stride_a + r * M + c] : cconj(A[i * stride_a + c * M + r]);
+        const double2 b = (r <= c) ? B[i * stride_b + r * M + c] : cconj(B[i * stride_b + c * M + r]);
+        sA[tid] = (r == c) ? make_double2(a.x, 0.0) : a;
+        sB[tid] = (r == c) ? make_double2(b.x, 0.0) : b;
+        sId[tid] = make_double2(r == c ? 1.0 : 0.0, 0.0);
     }
-    if (logdet) logdet[i] = dld;
-    flags[i] = flag;
+    __syncthreads();
+    double dld = 0.0;
+    const int flag = gevd_wave<M>(sA, sB, sId, sWs, sPn, sLam, &dld, 1e-30);
+    wave_lds_sync();
+    const bool ok = !(flag & kFreezeMask);
+    if (tid < MM) P[i * stride_p + tid] = ok ? sPn[tid] : sId[tid];
+    if (tid < M) lam[i * stride_l + tid] = ok ? sLam[tid] : 1.0;
+    if (tid == 0) {
+        if (logdet) logdet[i] = ok ? dld : 0.0;
+        flags[i] = flag;
+    }
 }
 
 hipError_t launch_gevd(int M, int count, const double2* A, const double2* B, int64_t stride_a,
                        int64_t stride_b, double2* P, int64_t stride_p, double* lam, int64_t stride_l,
                        double* logdet, int* flags, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    const unsigned g = (count + 63) / 64;
     switch (M) {
-#define FCA_GEVD_CASE(MM_)                                                                                     \
-    case MM_:                                                                                                  \
-        gevd_kernel<MM_><<<g, 64, 0, s>>>(count, A, B, stride_a, stride_b, P, stride_p, lam, stride_l, logdet, \
-                                          flags);                                                              \
+#define FCA_GEVD_CASE(MM_)                                                                                  \
+    case MM_:                                                                                               \
+        gevd_kernel<MM_><<<count, 64, 0, s>>>(A, B, stride_a, stride_b, P, stride_p, lam, stride_l, logdet, \
+                                              flags);                                                       \
         break;
         FCA_GEVD_CASE(1) FCA_GEVD_CASE(2) FCA_GEVD_CASE(3) FCA_GEVD_CASE(4)
         FCA_GEVD_CASE(5) FCA_GEVD_CASE(6) FCA_GEVD_CASE(7) FCA_GEVD_CASE(8)
