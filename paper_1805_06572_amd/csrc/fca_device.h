@@ -81,6 +81,17 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
     r = r * fma(-h * r, r, 1.5);
     return r * fma(-h * r, r, 1.5);
 }
+// One Newton step only: for quantities whose rounding does not matter beyond
+// single precision (a Jacobi rotation angle may be slightly off; only its
+// cosine/sine pair must be exactly consistent).
+__device__ __forceinline__ double rcp_nr1(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsqrt_nr1(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    return r * fma(-0.5 * x * r, r, 1.5);
+}
 
 // Orders the LDS accesses of one wavefront: a wave executes its LDS
 // instructions in issue order, so after this point every lane sees what the
@@ -251,24 +262,18 @@ __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold
                 vik2 = ws.V[i * MP + k2];
                 const double hh = cabs2(h);
                 if (hh > eps2 * fabs(a * b) && hh > 1e-300) {
-                    const double rh = rsqrt_nr(hh);
+                    // t = sign(tau) / (|tau| + sqrt(1 + tau^2)) written without the
+                    // division by |h|: t = sign(d) 2|h| / (|d| + sqrt(d^2 + 4|h|^2)),
+                    // d = C_qq - C_pp (no overflow, no branch).
+                    const double rh = rsqrt_nr(hh);          // 1/|h|, exact to rounding (|e| = 1)
                     const double habs = hh * rh;
-                    const double tau = 0.5 * (b - a) * rh;
-                    const double at = fabs(tau);
-                    // sqrt(1 + tau^2) without overflow for large |tau|
-                    double root;
-                    if (at > 1.0) {
-                        const double u = rcp_nr(at);
-                        const double w2 = fma(u, u, 1.0);
-                        root = at * (w2 * rsqrt_nr(w2));
-                    } else {
-                        const double w2 = fma(tau, tau, 1.0);
-                        root = w2 * rsqrt_nr(w2);
-                    }
-                    const double t = copysign(rcp_nr(at + root), tau);
-                    cc = rsqrt_nr(fma(t, t, 1.0));
-                    const double s = t * cc;
-                    g = make_double2(s * h.x * rh, s * h.y * rh);
+                    const double d = b - a;
+                    const double w2 = fma(d, d, 4.0 * hh);
+                    const double root = w2 * rsqrt_nr1(w2);
+                    const double t = copysign(2.0 * habs * rcp_nr1(fabs(d) + root), d);
+                    cc = rsqrt_nr(fma(t, t, 1.0));             // c^2 + s^2 = 1 to rounding
+                    const double s = t * cc * rh;
+                    g = make_double2(s * h.x, s * h.y);
                     th = t * habs;
                 }
                 if (i == 0) ws.prm[k] = make_double4(cc, g.x, g.y, th);

@@ -286,7 +286,11 @@ __global__ __launch_bounds__(kEmThreads) __attribute__((amdgpu_waves_per_eu(3)))
                 if (tid == 0) ll[(int64_t)it * ll_stride + pid] = tot;
                 int flag = sBad ? kFlagNonFinite : 0;
                 double dld = 0.0;
+                // the eigendecomposition is this workgroup's critical path: give its
+                // wave issue priority over co-resident waves streaming frames
+                __builtin_amdgcn_s_setprio(3);
                 if (!flag) flag = gevd_wave<M>(sS[0], sS[1], sP, sWs, sPn, sLamN, &dld, eps2);
+                __builtin_amdgcn_s_setprio(0);
                 wave_lds_sync();
                 if (flag & kFreezeMask) {
                     // frozen at theta^(it): its log-likelihood stands for later iterations
