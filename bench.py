@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--N", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-freqs", type=int, default=513)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device-to-device copy (3 times) so that "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE can be scaled to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -120,6 +123,14 @@ def main():
         st = lib.fca_separate(ctx.handle, x.data_ptr())
         assert st == fca.FCA_OK, fca.fca_last_error(ctx)
 
+    if args.copy_calibration:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
