@@ -65,7 +65,8 @@ typedef enum {
 /* One mixture (Section 2, problem statement).
  *   M        microphones (the paper's I), 1 <= M <= 8
  *   F        frequency bins (DC .. Nyquist), F >= 1
- *   N        frames, 1 <= N <= 2048
+ *   N        frames, 1 <= N <= 16777216 (up to 2048 frames stay in registers for
+ *            all iterations; longer mixtures are re-read from memory every pass)
  *   prec     an fca_precision
  *   y        observed STFT mixture y(n,f), complex (prec), element (f,n,m)
  *            at y + f*y_stride_f + n*y_stride_n + m*y_stride_m, strides in

@@ -54,6 +54,7 @@ struct fca_ctx {
     std::vector<MixInfo> mix;
     std::vector<Group> groups;
     int nprob = 0;
+    int64_t v_alt = 0;  // element offset of the second power buffer (streaming problems)
 
     void* y = nullptr;
     void* v = nullptr;
@@ -135,7 +136,10 @@ void free_ctx_memory(fca_ctx* c) {
     if (c->ev1) (void)hipEventDestroy(c->ev1);
 }
 
+// Frames per thread of the resident EM kernel, or 0 (streaming kernel) when
+// the frames do not fit in registers.
 int frames_per_thread(int N) {
+    if (N > kMaxFrames) return 0;
     int fpt = 1;
     while (fpt * kEmThreads < N) fpt *= 2;
     return fpt;
@@ -147,8 +151,8 @@ fca_status validate(const fca_problem* p, int b, const fca_problem* p0) {
     if (!p) { set_err(nullptr, "problem %d is NULL", b); return FCA_E_ARG; }
     if (p->M < 1 || p->M > kMaxM) { set_err(nullptr, "problem %d: M=%d outside 1..%d", b, p->M, kMaxM); return FCA_E_ARG; }
     if (p->F < 1) { set_err(nullptr, "problem %d: F=%d < 1", b, p->F); return FCA_E_ARG; }
-    if (p->N < 1 || p->N > kMaxFrames) {
-        set_err(nullptr, "problem %d: N=%d outside 1..%d", b, p->N, kMaxFrames);
+    if (p->N < 1 || p->N > kMaxFramesStream) {
+        set_err(nullptr, "problem %d: N=%d outside 1..%d", b, p->N, kMaxFramesStream);
         return FCA_E_ARG;
     }
     if (p->prec != FCA_FP64 && p->prec != FCA_FP32_BULK) { set_err(nullptr, "problem %d: bad prec %d", b, p->prec); return FCA_E_ARG; }
@@ -281,7 +285,10 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     } while (0)
 
     FCA_TRY(dev_alloc(c, &c->y, y_tot * c->esz));
-    FCA_TRY(dev_alloc(c, &c->v, v_tot * c->rsz));
+    bool any_stream = false;
+    for (const MixInfo& mi : c->mix) any_stream = any_stream || mi.fpt == 0;
+    c->v_alt = any_stream ? v_tot : 0;
+    FCA_TRY(dev_alloc(c, &c->v, (any_stream ? 2 : 1) * v_tot * c->rsz));
     if (any_v0) FCA_TRY(dev_alloc(c, &c->v_init, v_tot * c->rsz));
     FCA_TRY(dev_alloc(c, &c->R_init, R_tot * sizeof(double2)));
     FCA_TRY(dev_alloc(c, &c->P, (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2)));
@@ -449,8 +456,8 @@ fca_status fca_em_step(fca_ctx* c, int32_t iters, double* loglik, double* R_out,
         const int rows = chunk > 0 ? chunk : 1;
         if (c->timing) FCA_HIP(c, hipEventRecord(c->ev0, s));
         for (const Group& g : c->groups) {
-            FCA_HIP(c, launch_em(g.M, c->fp64, g.fpt, c->probs + g.first, g.count, c->y, c->v, c->P, c->lam,
-                                 c->logdet, c->flags, c->ll, c->nprob, chunk, s));
+            FCA_HIP(c, launch_em(g.M, c->fp64, g.fpt, c->probs + g.first, g.count, c->y, c->v, c->v_alt, c->P,
+                                 c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, s));
         }
         if (c->timing) FCA_HIP(c, hipEventRecord(c->ev1, s));
         if (loglik) {

@@ -20,7 +20,12 @@ constexpr int kMaxM = 8;
 // number of frames each thread keeps in registers.
 constexpr int kEmThreads = 256;
 constexpr int kMaxFramesPerThread = 8;
-constexpr int kMaxFrames = kEmThreads * kMaxFramesPerThread;
+constexpr int kMaxFrames = kEmThreads * kMaxFramesPerThread;  // resident limit
+// Frames per thread per chunk of the streaming EM kernel (more frames than
+// kMaxFrames); such problems use frames-per-thread code 0 in a launch group.
+constexpr int kStreamFramesPerThread = 2;
+// Largest frame count accepted.
+constexpr int kMaxFramesStream = 1 << 24;
 
 // One EM problem = one (mixture, frequency) pair. All offsets are element
 // offsets into the context's device arrays.
@@ -36,9 +41,11 @@ struct EmProblem {
 
 // Launchers (defined in fca_kernels.hip). All return hipSuccess or the
 // launch error. Every pointer is a device pointer.
+// fpt: frames per thread of the resident kernel (1, 2, 4, 8), or 0 for the
+// streaming kernel, whose second power buffer starts at v + v_alt elements.
 hipError_t launch_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
-                     void* v, double2* P, double* lam, double* logdet, int* flags, double* ll,
-                     int64_t ll_stride, int iters, hipStream_t s);
+                     void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags,
+                     double* ll, int64_t ll_stride, int iters, hipStream_t s);
 
 hipError_t launch_ingest(bool fp64, const void* src, int64_t sf, int64_t sn, int64_t sm, int M,
                          int F, int N, int npad, void* dst, hipStream_t s);

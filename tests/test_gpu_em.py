@@ -86,6 +86,9 @@ def test_fp64_random_workload_all_bins(fca):
     (6, 2, 300, 4),
     (7, 2, 90, 3),
     (8, 3, 600, 4),
+    (2, 3, 2049, 4),    # first size beyond the register-resident limit (streamed)
+    (3, 2, 4500, 3),    # streamed, several chunks and a ragged tail
+    (8, 2, 2600, 3),    # streamed at the largest microphone count
 ])
 def test_fp64_shapes(fca, M, F, N, iters):
     mx = synth.random_mixture(M, F, N, 100 + M + N)
@@ -188,6 +191,42 @@ def test_iterations_split_across_calls(fca):
     np.testing.assert_array_equal(v2[0].cpu().numpy(), v)
 
 
+def test_streamed_iterations_split_across_calls(fca):
+    """Streamed problems (N > 2048) keep their powers in a double buffer:
+    7 iterations in one call equal 3 + 4 (odd split) in two calls."""
+    mx = synth.random_mixture(2, 3, 2500, 18)
+    ctx = fca.fca_init(torch.from_numpy(mx.y).to(DEV), prec=fca.FCA_FP64)
+    try:
+        ll1, _, _ = fca.fca_em_step(ctx, 3, want_R=False, want_v=False)
+        ll2, R2, v2 = fca.fca_em_step(ctx, 4)
+        x2 = fca.fca_separate(ctx)[0]
+    finally:
+        fca.fca_destroy(ctx)
+    ll, R, v, _, x = run_gpu(fca, mx.y, fca.FCA_FP64, 7)
+    np.testing.assert_array_equal(np.r_[ll1.cpu().numpy()[0], ll2.cpu().numpy()[0]], ll)
+    np.testing.assert_array_equal(v2[0].cpu().numpy(), v)
+    np.testing.assert_array_equal(R2[0].cpu().numpy(), R)
+    np.testing.assert_array_equal(x2.cpu().numpy(), x)
+
+
+def test_streamed_nonfinite_bin_freezes_only_its_frequency(fca):
+    mx = synth.random_mixture(2, 4, 2300, 19)
+    S0, v0 = oracle.default_init(mx.y)
+    y = mx.y.copy()
+    y[1, 2200, 0] = np.inf
+    clean = run_gpu(fca, mx.y, fca.FCA_FP64, 4, R0=S0, v0=v0, separate=False)
+    ctx = fca.fca_init(torch.from_numpy(y).to(DEV), R0=S0, v0=v0, prec=fca.FCA_FP64)
+    try:
+        _, R, v = fca.fca_em_step(ctx, 4, allow_flags=True)
+        flags = fca.fca_status_per_freq(ctx)[0]
+    finally:
+        fca.fca_destroy(ctx)
+    assert flags[1] & (fca.FCA_FLAG_NONFINITE | fca.FCA_FLAG_NOT_PD)
+    assert not flags[[0, 2, 3]].any()
+    np.testing.assert_array_equal(v[0].cpu().numpy()[:, [0, 2, 3]], clean[2][:, [0, 2, 3]])
+    np.testing.assert_array_equal(v[0].cpu().numpy()[:, 1], v0[:, 1])   # frozen at the start
+
+
 def test_layouts_and_host_input(fca):
     """y as a strided [m][f][n] device view and as host memory give the same result."""
     mx = synth.random_mixture(3, 6, 140, 31)
@@ -210,7 +249,8 @@ def test_layouts_and_host_input(fca):
 
 def test_batch_equals_single_runs(fca):
     mixes = [synth.array_mixture(2, 21, 300, 40), synth.array_mixture(4, 21, 700, 41),
-             synth.array_mixture(2, 21, 64, 42), synth.array_mixture(3, 21, 1500, 43)]
+             synth.array_mixture(2, 21, 64, 42), synth.array_mixture(3, 21, 1500, 43),
+             synth.array_mixture(2, 21, 2300, 44)]
     ctx = fca.fca_init_batch([torch.from_numpy(m.y).to(DEV) for m in mixes], prec=fca.FCA_FP32_BULK)
     try:
         ll, R, v = fca.fca_em_step(ctx, 6, allow_flags=True)
