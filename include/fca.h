@@ -121,6 +121,16 @@ fca_status fca_reset(fca_ctx *c);
  * (all outputs are still written; see fca_status_per_freq). */
 fca_status fca_em_step(fca_ctx *c, int32_t iters, double *loglik, double *R_out, void *v_out);
 
+/* The same L iterations computed by the conventional frame-wise EM of
+ * Section 2 (eqs. MMSE, postquadexp, vupdate, Supdate: per bin a Cholesky
+ * factorisation of v1 R1 + v2 R2, its solves and matrix products, no
+ * eigendecomposition), on the same context and with the same arguments,
+ * outputs and failure semantics as fca_em_step. The paper states the two
+ * algorithms produce identical iterates; this entry point is the in-run
+ * baseline of that comparison. Requires N <= 2048 for every mixture
+ * (FCA_E_ARG otherwise). */
+fca_status fca_conv_em_step(fca_ctx *c, int32_t iters, double *loglik, double *R_out, void *v_out);
+
 /* MMSE source images with the current parameters (eq. MMSE; Algorithm 1,
  * step 11): x_out is [2][F][N][M] complex (prec) per mixture, x1 then x2,
  * with x1 = P^-H mu~1 computed in the eigenbasis and x2 = y - x1. */

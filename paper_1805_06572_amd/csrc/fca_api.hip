@@ -444,10 +444,24 @@ fca_status fca_reset(fca_ctx* c) {
     return do_reset(c);
 }
 
-fca_status fca_em_step(fca_ctx* c, int32_t iters, double* loglik, double* R_out, void* v_out) {
+}  // extern "C"
+
+namespace {
+
+// Shared driver of fca_em_step (FastFCA kernels) and fca_conv_em_step
+// (conventional frame-wise EM kernel): chunks of at most kLChunk iterations,
+// log-likelihood totals per mixture, then R and v out.
+fca_status em_step_impl(fca_ctx* c, int32_t iters, double* loglik, double* R_out, void* v_out, bool conventional) {
     if (!c) return FCA_E_ARG;
     if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
     if (iters < 0) { set_err(c, "iters < 0"); return FCA_E_ARG; }
+    if (conventional) {
+        for (const Group& g : c->groups)
+            if (g.fpt == 0) {
+                set_err(c, "the conventional EM kernel keeps frames in registers: N <= %d", kMaxFrames);
+                return FCA_E_ARG;
+            }
+    }
     const hipStream_t s = c->stream;
     const bool ll_dev = loglik && is_device_ptr(loglik);
     int done = 0;
@@ -456,8 +470,12 @@ fca_status fca_em_step(fca_ctx* c, int32_t iters, double* loglik, double* R_out,
         const int rows = chunk > 0 ? chunk : 1;
         if (c->timing) FCA_HIP(c, hipEventRecord(c->ev0, s));
         for (const Group& g : c->groups) {
-            FCA_HIP(c, launch_em(g.M, c->fp64, g.fpt, c->probs + g.first, g.count, c->y, c->v, c->v_alt, c->P,
-                                 c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, s));
+            if (conventional)
+                FCA_HIP(c, launch_conv_em(g.M, c->fp64, g.fpt, c->probs + g.first, g.count, c->y, c->v, c->P,
+                                          c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, s));
+            else
+                FCA_HIP(c, launch_em(g.M, c->fp64, g.fpt, c->probs + g.first, g.count, c->y, c->v, c->v_alt, c->P,
+                                     c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, s));
         }
         if (c->timing) FCA_HIP(c, hipEventRecord(c->ev1, s));
         if (loglik) {
@@ -509,6 +527,18 @@ fca_status fca_em_step(fca_ctx* c, int32_t iters, double* loglik, double* R_out,
         }
     }
     return check_flags(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+fca_status fca_em_step(fca_ctx* c, int32_t iters, double* loglik, double* R_out, void* v_out) {
+    return em_step_impl(c, iters, loglik, R_out, v_out, false);
+}
+
+fca_status fca_conv_em_step(fca_ctx* c, int32_t iters, double* loglik, double* R_out, void* v_out) {
+    return em_step_impl(c, iters, loglik, R_out, v_out, true);
 }
 
 fca_status fca_separate(fca_ctx* c, void* x_out) {

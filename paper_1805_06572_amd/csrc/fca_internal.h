@@ -47,6 +47,11 @@ hipError_t launch_em(int M, bool fp64, int fpt, const EmProblem* probs, int coun
                      void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags,
                      double* ll, int64_t ll_stride, int iters, hipStream_t s);
 
+// The conventional frame-wise EM (resident frames only, fpt in 1, 2, 4, 8).
+hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
+                          void* v, double2* P, double* lam, double* logdet, int* flags, double* ll,
+                          int64_t ll_stride, int iters, hipStream_t s);
+
 hipError_t launch_ingest(bool fp64, const void* src, int64_t sf, int64_t sn, int64_t sm, int M,
                          int F, int N, int npad, void* dst, hipStream_t s);
 

@@ -24,25 +24,6 @@
 
 namespace fca {
 
-template <typename T> struct Vec2;
-template <> struct Vec2<float> { using type = float2; };
-template <> struct Vec2<double> { using type = double2; };
-
-constexpr double kLogPi = 1.1447298858494002;
-
-template <typename T> __device__ __forceinline__ typename Vec2<T>::type make_vec2(T x, T y) {
-    typename Vec2<T>::type r;
-    r.x = x;
-    r.y = y;
-    return r;
-}
-
-// Index of the off-diagonal pair (i < k) of an M x M matrix, row-major over
-// the strict upper triangle.
-__host__ __device__ constexpr int pair_index(int M, int i, int k) {
-    return i * M - i * (i + 1) / 2 + (k - i - 1);
-}
-
 // ============================================================== EM iteration pieces
 // LDS state of one (mixture, frequency) problem inside an EM workgroup.
 template <int M, typename T> struct EmShared {
@@ -208,52 +189,10 @@ __device__ __forceinline__ bool em_finish(EmShared<M, T>& sh, const T (&acc)[2 *
                                           bool bad, int it, int iters, bool frozen_at_entry, int nf,
                                           double* __restrict__ ll, int64_t ll_stride, int pid, double eps2,
                                           int tid) {
-    using S = EmShared<M, T>;
-    constexpr int MM = S::MM, NV = S::NV, CH = S::CH, NCH = S::NCH, G = S::G, NW = S::NW;
-    constexpr int NT = kEmThreads;
+    constexpr int MM = M * M, NW = kEmThreads / 64;
     const int ll_count = iters > 0 ? iters : 1;
     if (bad) sh.bad = 1;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) llacc += __shfl_xor(llacc, off, 64);
-    if ((tid & 63) == 0) sh.LL[tid >> 6] = llacc;
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-#pragma unroll
-        for (int c = 0; c < CH; ++c)
-            if (ch * CH + c < NV) sh.red[tid * (CH + 1) + c] = acc[ch * CH + c];
-        __syncthreads();
-        for (int task = tid; task < CH * G; task += NT) {
-            const int c = task % CH, g = task / CH;
-            double s = 0.0;
-#pragma unroll 8
-            for (int rr = 0; rr < 32; ++rr) s += (double)sh.red[(g * 32 + rr) * (CH + 1) + c];
-            sh.red2[g * CH + c] = s;
-        }
-        __syncthreads();
-        if (tid < CH && ch * CH + tid < NV) {
-            double s = 0.0;
-#pragma unroll
-            for (int g = 0; g < G; ++g) s += sh.red2[g * CH + tid];
-            sh.fin[ch * CH + tid] = s;
-        }
-        __syncthreads();
-    }
-    if (tid < NV) {
-        const int j = tid / MM, ent = tid % MM, i = ent / M, q = ent % M;
-        const double invn = 1.0 / (double)nf;
-        const double* f = sh.fin + j * MM;
-        double2 val;
-        if (i == q) val = make_double2(f[i] * invn, 0.0);
-        else if (i < q) {
-            const int o = M + 2 * pair_index(M, i, q);
-            val = make_double2(f[o] * invn, f[o + 1] * invn);
-        } else {
-            const int o = M + 2 * pair_index(M, q, i);
-            val = make_double2(f[o] * invn, -f[o + 1] * invn);
-        }
-        sh.S[j][ent] = val;
-    }
-    __syncthreads();
+    wg_reduce_sums<M>(sh, acc, llacc, nf, tid);
     if (tid < 64) {
         const bool last = (iters == 0) || frozen_at_entry;
         double tot = 0.0;
@@ -755,59 +694,6 @@ hipError_t launch_ll_reduce(const double* ll, int64_t ll_stride, int iters, int 
     if (iters <= 0 || B <= 0) return hipSuccess;
     ll_reduce_kernel<<<dim3(iters, B), 256, 0, s>>>(ll, ll_stride, iters, F, out);
     return hipGetLastError();
-}
-
-// ============================================================== inverse of P
-// Gauss-Jordan elimination with partial pivoting, FP64. Returns false if P is
-// numerically singular.
-template <int M>
-__device__ bool invert(const double2* __restrict__ P, double2 (&X)[M][M]) {
-    double2 A[M][M];
-#pragma unroll
-    for (int i = 0; i < M; ++i)
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            A[i][k] = P[i * M + k];
-            X[i][k] = make_double2(i == k ? 1.0 : 0.0, 0.0);
-        }
-    bool ok = true;
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        // pivot search among rows c..M-1 (swap by value, indices stay static)
-        double best = cabs2(A[c][c]);
-#pragma unroll
-        for (int r = c + 1; r < M; ++r) {
-            const double mag = cabs2(A[r][c]);
-            if (mag > best) {
-                best = mag;
-#pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    const double2 ta = A[c][k]; A[c][k] = A[r][k]; A[r][k] = ta;
-                    const double2 tx = X[c][k]; X[c][k] = X[r][k]; X[r][k] = tx;
-                }
-            }
-        }
-        if (!(best > 0.0)) ok = false;
-        const double2 piv = A[c][c];
-        const double inv_mag = 1.0 / cabs2(piv);
-        const double2 pinv = make_double2(piv.x * inv_mag, -piv.y * inv_mag);
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            A[c][k] = cmul(A[c][k], pinv);
-            X[c][k] = cmul(X[c][k], pinv);
-        }
-#pragma unroll
-        for (int r = 0; r < M; ++r) {
-            if (r == c) continue;
-            const double2 fct = A[r][c];
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                A[r][k] = csub(A[r][k], cmul(fct, A[c][k]));
-                X[r][k] = csub(X[r][k], cmul(fct, X[c][k]));
-            }
-        }
-    }
-    return ok;
 }
 
 // R2 = (P P^H)^-1 = P^-H P^-1 and R1 = P^-H Lambda P^-1 (eq. recoverS with

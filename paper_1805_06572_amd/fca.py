@@ -32,7 +32,7 @@ FCA_FLAG_SWEEPS = 4
 STATUS_NAMES = {0: "FCA_OK", -1: "FCA_E_ARG", -2: "FCA_E_NOMEM", -3: "FCA_E_DEVICE",
                 -4: "FCA_E_NOT_PD", -5: "FCA_E_NONFINITE", -6: "FCA_E_STATE"}
 
-EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_em_step", "fca_separate",
+EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_em_step", "fca_conv_em_step", "fca_separate",
             "fca_status_per_freq", "fca_last_error", "fca_destroy", "fca_gevd", "fca_timing"]
 
 
@@ -65,6 +65,7 @@ def lib() -> ctypes.CDLL:
         L.fca_init_batch.argtypes = [ctypes.POINTER(fca_problem), i32, ctypes.POINTER(vp)]
         L.fca_reset.argtypes = [vp]
         L.fca_em_step.argtypes = [vp, i32, vp, vp, vp]
+        L.fca_conv_em_step.argtypes = [vp, i32, vp, vp, vp]
         L.fca_separate.argtypes = [vp, vp]
         L.fca_status_per_freq.argtypes = [vp, vp]
         L.fca_last_error.argtypes = [vp]
@@ -73,7 +74,7 @@ def lib() -> ctypes.CDLL:
         L.fca_destroy.restype = None
         L.fca_gevd.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
         L.fca_timing.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
-        for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_em_step", "fca_separate",
+        for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_em_step", "fca_conv_em_step", "fca_separate",
                      "fca_status_per_freq", "fca_gevd", "fca_timing"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -185,7 +186,8 @@ def fca_reset(ctx: Ctx):
     _check(lib().fca_reset(ctx.handle), ctx)
 
 
-def fca_em_step(ctx: Ctx, iters: int, want_loglik=True, want_R=True, want_v=True, allow_flags=False):
+def fca_em_step(ctx: Ctx, iters: int, want_loglik=True, want_R=True, want_v=True, allow_flags=False,
+                _entry="fca_em_step"):
     """Run `iters` EM iterations. Returns (loglik [B, max(iters,1)] float64,
     R list of [2, F, M, M] complex128, v list of [2, F, N]) on the context's
     device (entries not requested are None)."""
@@ -197,7 +199,7 @@ def fca_em_step(ctx: Ctx, iters: int, want_loglik=True, want_R=True, want_v=True
     R = torch.empty(nR, dtype=torch.complex128, device=dev) if want_R else None
     v = torch.empty(nv, dtype=ctx.real_dtype, device=dev) if want_v else None
     allow = (FCA_E_NOT_PD, FCA_E_NONFINITE) if allow_flags else ()
-    _check(lib().fca_em_step(ctx.handle, iters, ll.data_ptr() if ll is not None else None,
+    _check(getattr(lib(), _entry)(ctx.handle, iters, ll.data_ptr() if ll is not None else None,
                              R.data_ptr() if R is not None else None,
                              v.data_ptr() if v is not None else None), ctx, allow)
     Rs = vs = None
@@ -212,6 +214,11 @@ def fca_em_step(ctx: Ctx, iters: int, want_loglik=True, want_R=True, want_v=True
             vs.append(v[o:o + 2 * F * n].view(2, F, n))
             o += 2 * F * n
     return ll, Rs, vs
+
+
+def fca_conv_em_step(ctx: Ctx, iters: int, want_loglik=True, want_R=True, want_v=True, allow_flags=False):
+    """As fca_em_step, computed by the conventional frame-wise EM kernel."""
+    return fca_em_step(ctx, iters, want_loglik, want_R, want_v, allow_flags, _entry="fca_conv_em_step")
 
 
 def fca_separate(ctx: Ctx):

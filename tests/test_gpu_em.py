@@ -349,3 +349,67 @@ def test_gevd_rejects_non_pd(fca):
     S2 = np.diag([1.0, -2.0, 1.0]).astype(np.complex128)[None]
     _, _, flags = fca.fca_gevd(torch.from_numpy(S1).to(DEV), torch.from_numpy(S2).to(DEV))
     assert flags.cpu().numpy()[0] & fca.FCA_FLAG_NOT_PD
+
+
+# ------------------------------------------------------------------ conventional EM kernel (in-run baseline)
+@pytest.mark.parametrize("M,F,N,iters", [(2, 20, 200, 10), (3, 5, 300, 6), (4, 3, 700, 5), (1, 4, 90, 4),
+                                         (8, 2, 150, 3)])
+def test_conventional_kernel_matches_oracle(fca, M, F, N, iters):
+    mx = synth.random_mixture(M, F, N, 300 + M)
+    S0, v0 = oracle.default_init(mx.y)
+    S, v, ll, flags = oracle.em(mx.y, S0, v0, iters, threads=8)
+    ctx = fca.fca_init(torch.from_numpy(mx.y).to(DEV), prec=fca.FCA_FP64)
+    try:
+        gll, gR, gv = fca.fca_conv_em_step(ctx, iters)
+        x = fca.fca_separate(ctx)[0].cpu().numpy()
+    finally:
+        fca.fca_destroy(ctx)
+    assert per_freq_rel(gv[0].cpu().numpy(), v, (-1,)).max() < 1e-9
+    assert per_freq_rel(gR[0].cpu().numpy(), S, (-2, -1)).max() < 1e-9
+    np.testing.assert_allclose(gll.cpu().numpy()[0], ll[:iters].sum(1), rtol=1e-10)
+    assert per_freq_rel(x, oracle.mmse(mx.y, S, v), (-2, -1)).max() < 1e-9
+
+
+def test_fastfca_and_conventional_kernels_interleave(fca):
+    """The paper's equivalence on the GPU: 3 FastFCA + 3 conventional + 2
+    FastFCA iterations on one context equal 8 oracle iterations."""
+    mx = synth.random_mixture(3, 6, 400, 77)
+    S0, v0 = oracle.default_init(mx.y)
+    S, v, ll, _ = oracle.em(mx.y, S0, v0, 8, threads=8)
+    ctx = fca.fca_init(torch.from_numpy(mx.y).to(DEV), prec=fca.FCA_FP64)
+    try:
+        l1, _, _ = fca.fca_em_step(ctx, 3, want_R=False, want_v=False)
+        l2, _, _ = fca.fca_conv_em_step(ctx, 3, want_R=False, want_v=False)
+        l3, gR, gv = fca.fca_em_step(ctx, 2)
+    finally:
+        fca.fca_destroy(ctx)
+    gll = np.r_[l1.cpu().numpy()[0], l2.cpu().numpy()[0], l3.cpu().numpy()[0]]
+    np.testing.assert_allclose(gll, ll[:8].sum(1), rtol=1e-10)
+    assert per_freq_rel(gv[0].cpu().numpy(), v, (-1,)).max() < 1e-9
+    assert per_freq_rel(gR[0].cpu().numpy(), S, (-2, -1)).max() < 1e-9
+
+
+def test_conventional_kernel_fp32_array_workload(fca, array_workload):
+    mx, S, v, ll, oflags = array_workload
+    kappa = synth.condition_numbers(mx.R)
+    ctx = fca.fca_init(torch.from_numpy(mx.y).to(DEV), prec=fca.FCA_FP32_BULK)
+    try:
+        gll, gR, gv = fca.fca_conv_em_step(ctx, 50, allow_flags=True)
+        gflags = fca.fca_status_per_freq(ctx)[0]
+    finally:
+        fca.fca_destroy(ctx)
+    gate = (kappa <= 1e3) & (oflags == 0) & (gflags == 0)
+    assert gate.sum() > 300
+    err_v = per_freq_rel(gv[0].cpu().numpy().astype(np.float64), v, (-1,))
+    assert err_v[:, gate].max() < 1e-4
+
+
+def test_conventional_kernel_rejects_streamed_mixtures(fca):
+    mx = synth.random_mixture(2, 2, 2100, 5)
+    ctx = fca.fca_init(torch.from_numpy(mx.y).to(DEV), prec=fca.FCA_FP64)
+    try:
+        with pytest.raises(fca.FcaError) as ei:
+            fca.fca_conv_em_step(ctx, 1)
+        assert ei.value.status == fca.FCA_E_ARG
+    finally:
+        fca.fca_destroy(ctx)
