@@ -163,6 +163,47 @@ fca_status fca_gevd(int32_t M, int32_t count, const double *S1, const double *S2
  * NULL), and the totals restart from zero. */
 fca_status fca_timing(fca_ctx *c, int32_t enable, double *em_kernel_ms, int64_t *em_launches);
 
+/* ------------------------------------------------------------------
+ * Learned initial powers (optional; not part of the paper's method).
+ * A per-bin MLP predicts r = v1 / (v1 + v2) from features of y(n,f):
+ * log(|y_m|^2 + 1e-20) for each microphone, cos and sin of the phase of y_m
+ * relative to microphone 1 (m = 2..M), and f / (F - 1) (IN = 3M - 1 values,
+ * zero-padded to 32). Three hidden layers of width 256 with GELU (erf form),
+ * one sigmoid output; BF16 weights and activations into MFMA, FP32
+ * accumulation, FP32 master weights, AdamW; loss = mean binary cross-
+ * entropy against soft targets. The learned start is
+ * v_j^(0) = (r, 1 - r) * 2 ||y||^2 / M (r = 1/2 gives the plain start) and
+ * reaches the EM only through fca_problem.v0.
+ * Parameter vector (fp32, flat): for each hidden layer l = 1..3 its weight
+ * [256][in_l] (in_1 = 32, the padded input; in_2 = in_3 = 256) then its bias
+ * [256]; then the output weight [256] and bias [1].
+ * Every array argument below is a DEVICE pointer unless marked host; y of
+ * fca_mlp_forward/backward is [n][M] complex64, fpos/target/r are [n] float.
+ * ------------------------------------------------------------------ */
+typedef struct fca_mlp fca_mlp;
+
+/* max_batch: largest n of one forward/backward call, a multiple of 64.
+ * 2 <= M <= 8. Weights are initialised from seed. */
+fca_status fca_mlp_create(int32_t M, uint64_t seed, int32_t max_batch, void *stream, fca_mlp **out);
+void fca_mlp_destroy(fca_mlp *m);
+int64_t fca_mlp_num_params(const fca_mlp *m);
+const char *fca_mlp_last_error(const fca_mlp *m);
+/* host params [num_params] */
+fca_status fca_mlp_get_params(fca_mlp *m, float *params);
+fca_status fca_mlp_set_params(fca_mlp *m, const float *params);
+/* r_out[b] = sigmoid(network(features(y[b], fpos[b]))), 1 <= n <= max_batch */
+fca_status fca_mlp_forward(fca_mlp *m, const float *y, const float *fpos, int32_t n, float *r_out);
+/* forward + backward of the mean loss; keeps the gradient for fca_mlp_adamw;
+ * loss (host, may be NULL) and grads_out (host [num_params], may be NULL).
+ * n a multiple of 64, 64 <= n <= max_batch. */
+fca_status fca_mlp_backward(fca_mlp *m, const float *y, const float *fpos, const float *target, int32_t n,
+                            double *loss, float *grads_out);
+/* one AdamW step with the last gradient (bias-corrected moments) */
+fca_status fca_mlp_adamw(fca_mlp *m, float lr, float beta1, float beta2, float eps, float weight_decay);
+/* learned start for a mixture y [F][N][M] complex64 (contiguous, device):
+ * v0_out [2][F][N] float (device), usable as fca_problem.v0 */
+fca_status fca_mlp_init_powers(fca_mlp *m, const float *y, int32_t F, int32_t N, float *v0_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,106 @@
+"""FP64 reference of the learned-initialisation network -- TEST INFRASTRUCTURE.
+
+Only tests may import this module. It restates, in plain numpy, the network
+that the library's MLP kernels compute (the library's header documents it):
+features of a bin y in C^M, three hidden layers of width 256 with the erf
+form of GELU, a sigmoid output r, and the mean binary cross-entropy against
+soft targets, with its gradient by reverse-mode differentiation. Parameters
+use the library's flat layout (per hidden layer: weight [256][in] then bias
+[256], in = 32 padded inputs for the first layer; then output weight [256]
+and bias [1]).
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import erf
+
+HIDDEN = 256
+KP = 32
+
+
+def unpack(params: np.ndarray):
+    p = np.asarray(params, dtype=np.float64)
+    Ws, bs, o = [], [], 0
+    for l in range(3):
+        fan = KP if l == 0 else HIDDEN
+        Ws.append(p[o:o + HIDDEN * fan].reshape(HIDDEN, fan))
+        o += HIDDEN * fan
+        bs.append(p[o:o + HIDDEN])
+        o += HIDDEN
+    w4 = p[o:o + HIDDEN]
+    o += HIDDEN
+    b4 = p[o]
+    return Ws, bs, w4, b4
+
+
+def features(y: np.ndarray, fpos: np.ndarray) -> np.ndarray:
+    """[n, 32]: log(|y_m|^2 + 1e-20); cos, sin of angle(y_m) - angle(y_1); f/(F-1); zeros."""
+    y = np.asarray(y, dtype=np.complex128)
+    n, M = y.shape
+    X = np.zeros((n, KP))
+    X[:, :M] = np.log(np.abs(y) ** 2 + 1e-20)
+    rel = y[:, 1:] * np.conj(y[:, :1])
+    mag = np.abs(rel)
+    ok = mag > 0
+    X[:, M:M + 2 * (M - 1):2] = np.where(ok, rel.real / np.where(ok, mag, 1), 0)
+    X[:, M + 1:M + 2 * (M - 1):2] = np.where(ok, rel.imag / np.where(ok, mag, 1), 0)
+    X[:, 3 * M - 2] = fpos
+    return X
+
+
+def gelu(x):
+    return 0.5 * x * (1.0 + erf(x / np.sqrt(2.0)))
+
+
+def gelu_grad(x):
+    return 0.5 * (1.0 + erf(x / np.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / np.sqrt(2.0 * np.pi)
+
+
+def forward(params, X):
+    """(r [n], cache) for features X [n, 32]."""
+    Ws, bs, w4, b4 = unpack(params)
+    h, pres, hs = X, [], [X]
+    for W, b in zip(Ws, bs):
+        a = h @ W.T + b
+        pres.append(a)
+        h = gelu(a)
+        hs.append(h)
+    z = h @ w4 + b4
+    r = 1.0 / (1.0 + np.exp(-z))
+    return r, (pres, hs, z)
+
+
+def loss(params, X, t):
+    r, (_, _, z) = forward(params, X)
+    sp_neg = np.logaddexp(0.0, -z)   # -log r
+    sp_pos = np.logaddexp(0.0, z)    # -log(1 - r)
+    return float(np.mean(t * sp_neg + (1.0 - t) * sp_pos))
+
+
+def loss_and_grad(params, X, t):
+    """Mean binary cross-entropy and its gradient (flat, same layout)."""
+    Ws, bs, w4, b4 = unpack(params)
+    r, (pres, hs, z) = forward(params, X)
+    n = X.shape[0]
+    dz = (r - t) / n
+    g_w4 = hs[-1].T @ dz
+    g_b4 = dz.sum()
+    d = np.outer(dz, w4) * gelu_grad(pres[-1])
+    gW, gb = [None] * 3, [None] * 3
+    for l in (2, 1, 0):
+        gW[l] = d.T @ hs[l]
+        gb[l] = d.sum(0)
+        if l > 0:
+            d = (d @ Ws[l]) * gelu_grad(pres[l - 1])
+    parts = []
+    for l in range(3):
+        parts += [gW[l].ravel(), gb[l]]
+    parts += [g_w4, np.array([g_b4])]
+    return loss(params, X, t), np.concatenate(parts)
+
+
+def bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round float32 values to bfloat16 (nearest even) and back."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32)

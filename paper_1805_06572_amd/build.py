@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfca.so")
-SOURCES = ["fca_kernels.hip", "fca_conv.hip", "fca_api.hip"]
+SOURCES = ["fca_kernels.hip", "fca_conv.hip", "fca_mlp.hip", "fca_api.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

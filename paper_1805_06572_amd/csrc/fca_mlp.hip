@@ -1,0 +1,588 @@
+// fca_mlp.hip -- learned initial powers for the EM: a per-bin MLP that
+// predicts r = v1 / (v1 + v2) from features of y(n,f), trained and run by the
+// kernels below (BF16 MFMA GEMMs with FP32 accumulation, FP32 master weights,
+// AdamW). v_j^(0) = (r, 1 - r) * 2 ||y||^2 / M, so r = 1/2 is the plain start
+// v_j = ||y||^2 / M. Not part of the paper; the EM entry points see it only
+// through the v0 argument of fca_init.
+//
+// Network: x (IN = 3M - 1 features, zero-padded to KP = 32) -> 3 hidden
+// layers of width 256 with GELU (erf form) -> 1 logit -> sigmoid.
+// Features: log(|y_m|^2 + 1e-20) for each microphone, cos and sin of the
+// phase of y_m relative to microphone 1 (m = 2..M), and f / (F - 1).
+// Loss: mean binary cross-entropy with soft targets.
+//
+// Layouts: activations row-major [n][256] (bf16 copies also transposed
+// [256][n] for the weight-gradient GEMMs); weights like a linear layer,
+// W[out][in] (bf16 copies W and W^T). GEMM: C[m][c] = sum_k A[m][k] B[c][k]
+// with both operands K-contiguous.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "fca.h"
+#include "fca_internal.h"
+
+namespace {
+
+constexpr int kHidden = 256;
+constexpr int kKP = 32;        // padded input width
+constexpr int kLayers = 3;     // hidden layers
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// ------------------------------------------------------------------ features
+__global__ void mlp_features_kernel(const float2* __restrict__ y, const float* __restrict__ fpos, int n, int M,
+                                    bf16* __restrict__ X, bf16* __restrict__ XT, int ldt) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    float feat[kKP];
+    for (int j = 0; j < kKP; ++j) feat[j] = 0.0f;
+    const float2* yb = y + (int64_t)b * M;
+    const float2 y0 = yb[0];
+    const float p0 = y0.x * y0.x + y0.y * y0.y;
+    for (int m = 0; m < M; ++m) {
+        const float2 ym = yb[m];
+        const float pm = ym.x * ym.x + ym.y * ym.y;
+        feat[m] = logf(pm + 1e-20f);
+        if (m > 0) {
+            // y_m conj(y_0) / (|y_m| |y_0|)
+            const float den = sqrtf(pm * p0);
+            const float cr = ym.x * y0.x + ym.y * y0.y, ci = ym.y * y0.x - ym.x * y0.y;
+            const bool okd = den > 0.0f;
+            feat[M + 2 * (m - 1)] = okd ? cr / den : 0.0f;
+            feat[M + 2 * (m - 1) + 1] = okd ? ci / den : 0.0f;
+        }
+    }
+    feat[3 * M - 2] = fpos[b];
+    for (int j = 0; j < kKP; ++j) {
+        const bf16 h = (bf16)feat[j];
+        X[(int64_t)b * kKP + j] = h;
+        XT[(int64_t)j * ldt + b] = h;
+    }
+}
+
+// ------------------------------------------------------------------ GEMM (BF16 MFMA, FP32 accumulate)
+// C[m][c] = sum_k A[m][k] B[c][k]; A is rows x K (row pitch lda), B is
+// cols x K (row pitch ldb).
+// One workgroup = 4 waves = a 64 x 64 tile; each wave 32 x 32 = 2 x 2 MFMA
+// 16x16x32 tiles. Operand lanes: lane l supplies row (l % 16) and the 8
+// consecutive k starting at 8 (l / 16) of a 16 x 32 block, for A and B alike
+// (the products pair the same k); the result tile gives lane l the rows
+// 4 (l / 16) + r, r = 0..3, of column l % 16. K must be a multiple of 32.
+enum Epi { kEpiFwd = 0, kEpiBwdGelu = 1, kEpiStore = 2 };
+
+struct GemmArgs {
+    const bf16* A;
+    const bf16* B;
+    int rows, cols, K;
+    int lda, ldb;       // row pitches of A and B (elements, multiples of 8)
+    const float* bias;  // kEpiFwd: [cols]
+    const float* pre;   // kEpiBwdGelu: pre-activation [rows][cols] of the layer below
+    float* out_f32;     // kEpiFwd: pre-activation; kEpiStore: result [rows][cols]
+    bf16* out_bf;       // bf16 [rows][cols]: GELU(pre) (fwd) or dpre (bwd)
+    bf16* out_bfT;      // bf16 [cols][ldt]: the same, transposed
+    int ldt;
+};
+
+template <int EPI>
+__global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * 64 + (w >> 1) * 32;
+    const int c0 = blockIdx.x * 64 + (w & 1) * 32;
+    const int li = lane & 15, lk = (lane >> 4) * 8;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero8 = (bf16x8){(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
+    for (int k0 = 0; k0 < g.K; k0 += 32) {
+        bf16x8 av[2], bv[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int r = r0 + 16 * t + li;
+            const int c = c0 + 16 * t + li;
+            av[t] = (r < g.rows) ? *reinterpret_cast<const bf16x8*>(g.A + (int64_t)r * g.lda + k0 + lk) : zero8;
+            bv[t] = (c < g.cols) ? *reinterpret_cast<const bf16x8*>(g.B + (int64_t)c * g.ldb + k0 + lk) : zero8;
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 16 * a + (lane >> 4) * 4 + q;
+                const int c = c0 + 16 * b + li;
+                if (r >= g.rows || c >= g.cols) continue;
+                const int64_t e = (int64_t)r * g.cols + c;
+                float val = acc[a][b][q];
+                if (EPI == kEpiFwd) {
+                    val += g.bias[c];
+                    g.out_f32[e] = val;
+                    const bf16 h = (bf16)gelu(val);
+                    g.out_bf[e] = h;
+                    g.out_bfT[(int64_t)c * g.ldt + r] = h;
+                } else if (EPI == kEpiBwdGelu) {
+                    const bf16 d = (bf16)(val * gelu_grad(g.pre[e]));
+                    g.out_bf[e] = d;
+                    g.out_bfT[(int64_t)c * g.ldt + r] = d;
+                } else {
+                    g.out_f32[e] = val;
+                }
+            }
+}
+
+// ------------------------------------------------------------------ output layer, loss, its backward
+// z = GELU(pre3) . w4 + b4, r = sigmoid(z); with targets: loss terms and
+// dz = (r - t) / n. One wave per row.
+__global__ void mlp_out_kernel(const float* __restrict__ pre3, const float* __restrict__ w4, const float* __restrict__ b4,
+                               int n, float* __restrict__ r_out, const float* __restrict__ target,
+                               float* __restrict__ dz, double* __restrict__ loss_terms) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    float s = 0.0f;
+    for (int o = lane; o < kHidden; o += 64) s += gelu(pre3[(int64_t)row * kHidden + o]) * w4[o];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        const float z = s + b4[0];
+        const float r = 1.0f / (1.0f + expf(-z));
+        if (r_out) r_out[row] = r;
+        if (target) {
+            const float t = target[row];
+            // -[t log r + (1 - t) log(1 - r)] with log r = -softplus(-z)
+            const double sp_neg = (z > 0) ? log1p(exp(-(double)z)) : -(double)z + log1p(exp((double)z));
+            const double sp_pos = sp_neg + (double)z;
+            loss_terms[row] = t * sp_neg + (1.0 - t) * sp_pos;
+            dz[row] = (r - t) / (float)n;
+        }
+    }
+}
+
+// dpre3[b][o] = dz[b] w4[o] GELU'(pre3[b][o]) (bf16, both layouts)
+__global__ void mlp_out_back_kernel(const float* __restrict__ pre3, const float* __restrict__ w4,
+                                    const float* __restrict__ dz, int n, bf16* __restrict__ d3, bf16* __restrict__ d3T,
+                                    int ldt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * kHidden) return;
+    const int b = (int)(i / kHidden), o = (int)(i % kHidden);
+    const bf16 d = (bf16)(dz[b] * w4[o] * gelu_grad(pre3[i]));
+    d3[i] = d;
+    d3T[(int64_t)o * ldt + b] = d;
+}
+
+// grad of w4 and b4: dw4[o] = sum_b dz[b] GELU(pre3[b][o]); db4 = sum_b dz[b].
+// Fixed-order per-thread sums, one block.
+__global__ void mlp_out_grad_kernel(const float* __restrict__ pre3, const float* __restrict__ dz, int n,
+                                    float* __restrict__ gw4, float* __restrict__ gb4) {
+    const int o = threadIdx.x;  // 256 threads
+    float s = 0.0f;
+    for (int b = 0; b < n; ++b) s += dz[b] * gelu(pre3[(int64_t)b * kHidden + o]);
+    gw4[o] = s;
+    if (o == 0) {
+        float t = 0.0f;
+        for (int b = 0; b < n; ++b) t += dz[b];
+        gb4[0] = t;
+    }
+}
+
+// bias gradients: gb[o] = sum_b d[o][b] from the transposed bf16 layout [256][ldt]
+__global__ void mlp_bias_grad_kernel(const bf16* __restrict__ dT, int n, int ldt, float* __restrict__ gb) {
+    __shared__ float red[256];
+    const int o = blockIdx.x;
+    float s = 0.0f;
+    for (int b = threadIdx.x; b < n; b += 256) s += (float)dT[(int64_t)o * ldt + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gb[o] = red[0];
+}
+
+// ------------------------------------------------------------------ optimiser and weight copies
+__global__ void mlp_adamw_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
+                                 float* __restrict__ m2, int64_t count, float lr, float b1, float b2, float eps,
+                                 float wd, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float a = b1 * m1[i] + (1.0f - b1) * gi;
+    const float v = b2 * m2[i] + (1.0f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = v;
+    p[i] -= lr * ((a / c1) / (sqrtf(v / c2) + eps) + wd * p[i]);
+}
+
+// bf16 copies of a [rows][cols] fp32 weight: W and W^T
+__global__ void mlp_weight_copy_kernel(const float* __restrict__ W, int rows, int cols, bf16* __restrict__ Wb,
+                                       bf16* __restrict__ WTb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)rows * cols) return;
+    const int r = (int)(i / cols), c = (int)(i % cols);
+    const bf16 h = (bf16)W[i];
+    Wb[i] = h;
+    WTb[(int64_t)c * rows + r] = h;
+}
+
+// ------------------------------------------------------------------ learned start of the powers
+// bins of y[F][N][M] (contiguous) in order f * N + n; v0[j][f][n].
+__global__ void mlp_gather_bins_kernel(const float2* __restrict__ y, int F, int N, int M, int64_t first, int count,
+                                       float2* __restrict__ ybins, float* __restrict__ fpos) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t bin = first + i;
+    const int f = (int)(bin / N);
+    for (int m = 0; m < M; ++m) ybins[(int64_t)i * M + m] = y[bin * M + m];
+    fpos[i] = F > 1 ? (float)f / (float)(F - 1) : 0.0f;
+}
+
+__global__ void mlp_powers_kernel(const float2* __restrict__ ybins, const float* __restrict__ r, int M, int64_t first,
+                                  int count, int64_t FN, float* __restrict__ v0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float p = 0.0f;
+    for (int m = 0; m < M; ++m) {
+        const float2 ym = ybins[(int64_t)i * M + m];
+        p += ym.x * ym.x + ym.y * ym.y;
+    }
+    const float s = fmaxf(2.0f * p / (float)M, 1e-30f);
+    const float ri = fminf(fmaxf(r[i], 1e-6f), 1.0f - 1e-6f);
+    v0[first + i] = ri * s;
+    v0[FN + first + i] = (1.0f - ri) * s;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+struct fca_mlp {
+    int M = 0, in_dim = 0, max_batch = 0, ldt = 0;
+    hipStream_t stream = nullptr;
+    int64_t nparam = 0;
+    // fp32 master parameters, gradients, Adam moments (one allocation each, flat)
+    float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;
+    int64_t off_W[kLayers + 1] = {}, off_b[kLayers + 1] = {};
+    bf16 *Wb[kLayers] = {}, *WTb[kLayers] = {};
+    // activations
+    bf16 *X = nullptr, *XT = nullptr;
+    float* pre[kLayers] = {};
+    bf16 *H[kLayers] = {}, *HT[kLayers] = {};
+    bf16 *D = nullptr, *DT = nullptr, *D2 = nullptr, *D2T = nullptr;
+    float *dz = nullptr, *r = nullptr;
+    double* loss_terms = nullptr;
+    float2* ybins = nullptr;
+    float* fpos = nullptr;
+    int64_t step = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_mlp_error;
+
+template <typename P>
+bool mlp_alloc(P** p, size_t bytes) {
+    if (hipMalloc(reinterpret_cast<void**>(p), bytes ? bytes : 16) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return false;
+    }
+    return true;
+}
+
+void mlp_free(fca_mlp* m) {
+    void* ptrs[] = {m->p, m->g, m->m1, m->m2, m->X, m->XT, m->D, m->DT, m->D2, m->D2T, m->dz, m->r,
+                    m->loss_terms, m->ybins, m->fpos};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    for (int l = 0; l < kLayers; ++l) {
+        if (m->Wb[l]) (void)hipFree(m->Wb[l]);
+        if (m->WTb[l]) (void)hipFree(m->WTb[l]);
+        if (m->pre[l]) (void)hipFree(m->pre[l]);
+        if (m->H[l]) (void)hipFree(m->H[l]);
+        if (m->HT[l]) (void)hipFree(m->HT[l]);
+    }
+}
+
+int layer_in(int l) { return l == 0 ? kKP : kHidden; }
+
+hipError_t refresh_weights(fca_mlp* m) {
+    for (int l = 0; l < kLayers; ++l) {
+        const int64_t cnt = (int64_t)kHidden * layer_in(l);
+        mlp_weight_copy_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, m->stream>>>(m->p + m->off_W[l], kHidden,
+                                                                                      layer_in(l), m->Wb[l], m->WTb[l]);
+    }
+    return hipGetLastError();
+}
+
+template <int EPI>
+hipError_t gemm(hipStream_t s, const GemmArgs& a) {
+    const dim3 grid((a.cols + 63) / 64, (a.rows + 63) / 64);
+    mlp_gemm_kernel<EPI><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// forward of n <= max_batch bins already gathered in ybins/fpos (or given)
+hipError_t forward(fca_mlp* m, const float2* y, const float* fpos, int n) {
+    mlp_features_kernel<<<(n + 255) / 256, 256, 0, m->stream>>>(y, fpos, n, m->M, m->X, m->XT, m->ldt);
+    const bf16* in = m->X;
+    for (int l = 0; l < kLayers; ++l) {
+        GemmArgs a{};
+        a.A = in;
+        a.B = m->Wb[l];
+        a.rows = n;
+        a.cols = kHidden;
+        a.K = layer_in(l);
+        a.lda = layer_in(l);
+        a.ldb = layer_in(l);
+        a.bias = m->p + m->off_b[l];
+        a.out_f32 = m->pre[l];
+        a.out_bf = m->H[l];
+        a.out_bfT = m->HT[l];
+        a.ldt = m->ldt;
+        hipError_t e = gemm<kEpiFwd>(m->stream, a);
+        if (e != hipSuccess) return e;
+        in = m->H[l];
+    }
+    return hipSuccess;
+}
+
+#define MLP_HIP(m, call)                                                            \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            (m)->err = std::string(#call) + ": " + hipGetErrorString(e_);           \
+            return FCA_E_DEVICE;                                                    \
+        }                                                                           \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+fca_status fca_mlp_create(int32_t M, uint64_t seed, int32_t max_batch, void* stream, fca_mlp** out) {
+    if (!out) return FCA_E_ARG;
+    *out = nullptr;
+    if (M < 2 || M > fca::kMaxM || max_batch < 64 || max_batch % 64 != 0) {
+        g_mlp_error = "fca_mlp_create: need 2 <= M <= 8 and max_batch a positive multiple of 64";
+        return FCA_E_ARG;
+    }
+    fca_mlp* m = new (std::nothrow) fca_mlp();
+    if (!m) return FCA_E_NOMEM;
+    m->M = M;
+    m->in_dim = 3 * M - 1;
+    m->max_batch = max_batch;
+    m->ldt = max_batch;
+    m->stream = static_cast<hipStream_t>(stream);
+    int64_t o = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        m->off_W[l] = o;
+        o += (int64_t)kHidden * layer_in(l);
+        m->off_b[l] = o;
+        o += kHidden;
+    }
+    m->off_W[kLayers] = o;
+    o += kHidden;
+    m->off_b[kLayers] = o;
+    o += 1;
+    m->nparam = o;
+    bool ok = mlp_alloc(&m->p, o * 4) && mlp_alloc(&m->g, o * 4) && mlp_alloc(&m->m1, o * 4) &&
+              mlp_alloc(&m->m2, o * 4);
+    for (int l = 0; l < kLayers && ok; ++l)
+        ok = mlp_alloc(&m->Wb[l], (size_t)kHidden * layer_in(l) * 2) &&
+             mlp_alloc(&m->WTb[l], (size_t)kHidden * layer_in(l) * 2) &&
+             mlp_alloc(&m->pre[l], (size_t)max_batch * kHidden * 4) &&
+             mlp_alloc(&m->H[l], (size_t)max_batch * kHidden * 2) && mlp_alloc(&m->HT[l], (size_t)max_batch * kHidden * 2);
+    ok = ok && mlp_alloc(&m->X, (size_t)max_batch * kKP * 2) && mlp_alloc(&m->XT, (size_t)max_batch * kKP * 2) &&
+         mlp_alloc(&m->D, (size_t)max_batch * kHidden * 2) && mlp_alloc(&m->DT, (size_t)max_batch * kHidden * 2) &&
+         mlp_alloc(&m->D2, (size_t)max_batch * kHidden * 2) && mlp_alloc(&m->D2T, (size_t)max_batch * kHidden * 2) &&
+         mlp_alloc(&m->dz, (size_t)max_batch * 4) && mlp_alloc(&m->r, (size_t)max_batch * 4) &&
+         mlp_alloc(&m->loss_terms, (size_t)max_batch * 8) && mlp_alloc(&m->ybins, (size_t)max_batch * M * 8) &&
+         mlp_alloc(&m->fpos, (size_t)max_batch * 4);
+    if (!ok) {
+        mlp_free(m);
+        delete m;
+        g_mlp_error = "fca_mlp_create: device allocation failed";
+        return FCA_E_NOMEM;
+    }
+    // He-style initialisation (deterministic in the seed); padded inputs and
+    // biases start at zero.
+    std::vector<float> h(o, 0.0f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<float> nd(0.0f, 1.0f);
+    for (int l = 0; l < kLayers; ++l) {
+        const int fan_in = l == 0 ? m->in_dim : kHidden;
+        const float sd = std::sqrt(2.0f / fan_in);
+        for (int r = 0; r < kHidden; ++r)
+            for (int c = 0; c < layer_in(l); ++c)
+                h[m->off_W[l] + (int64_t)r * layer_in(l) + c] = (c < fan_in) ? sd * nd(rng) : 0.0f;
+    }
+    for (int c = 0; c < kHidden; ++c) h[m->off_W[kLayers] + c] = std::sqrt(1.0f / kHidden) * nd(rng);
+    if (hipMemcpy(m->p, h.data(), o * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(m->m1, 0, o * 4) != hipSuccess || hipMemset(m->m2, 0, o * 4) != hipSuccess ||
+        hipMemset(m->g, 0, o * 4) != hipSuccess || refresh_weights(m) != hipSuccess ||
+        hipStreamSynchronize(m->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        mlp_free(m);
+        delete m;
+        g_mlp_error = "fca_mlp_create: device initialisation failed";
+        return FCA_E_DEVICE;
+    }
+    *out = m;
+    return FCA_OK;
+}
+
+void fca_mlp_destroy(fca_mlp* m) {
+    if (!m) return;
+    (void)hipStreamSynchronize(m->stream);
+    mlp_free(m);
+    delete m;
+}
+
+int64_t fca_mlp_num_params(const fca_mlp* m) { return m ? m->nparam : 0; }
+
+const char* fca_mlp_last_error(const fca_mlp* m) { return m ? m->err.c_str() : g_mlp_error.c_str(); }
+
+fca_status fca_mlp_get_params(fca_mlp* m, float* params) {
+    if (!m || !params) return FCA_E_ARG;
+    MLP_HIP(m, hipMemcpyAsync(params, m->p, m->nparam * 4, hipMemcpyDeviceToHost, m->stream));
+    MLP_HIP(m, hipStreamSynchronize(m->stream));
+    return FCA_OK;
+}
+
+fca_status fca_mlp_set_params(fca_mlp* m, const float* params) {
+    if (!m || !params) return FCA_E_ARG;
+    MLP_HIP(m, hipMemcpyAsync(m->p, params, m->nparam * 4, hipMemcpyHostToDevice, m->stream));
+    MLP_HIP(m, refresh_weights(m));
+    MLP_HIP(m, hipStreamSynchronize(m->stream));
+    return FCA_OK;
+}
+
+fca_status fca_mlp_forward(fca_mlp* m, const float* y, const float* fpos, int32_t n, float* r_out) {
+    if (!m || !y || !fpos || !r_out || n < 1 || n > m->max_batch) {
+        if (m) m->err = "fca_mlp_forward: bad arguments";
+        return FCA_E_ARG;
+    }
+    MLP_HIP(m, forward(m, reinterpret_cast<const float2*>(y), fpos, n));
+    mlp_out_kernel<<<(n + 3) / 4, 256, 0, m->stream>>>(m->pre[kLayers - 1], m->p + m->off_W[kLayers],
+                                                      m->p + m->off_b[kLayers], n, r_out, nullptr, nullptr, nullptr);
+    MLP_HIP(m, hipGetLastError());
+    MLP_HIP(m, hipStreamSynchronize(m->stream));
+    return FCA_OK;
+}
+
+fca_status fca_mlp_backward(fca_mlp* m, const float* y, const float* fpos, const float* target, int32_t n,
+                            double* loss, float* grads_out) {
+    if (!m || !y || !fpos || !target || n < 64 || n > m->max_batch || n % 64 != 0) {
+        if (m) m->err = "fca_mlp_backward: need 64 <= n <= max_batch, n a multiple of 64";
+        return FCA_E_ARG;
+    }
+    const hipStream_t s = m->stream;
+    MLP_HIP(m, forward(m, reinterpret_cast<const float2*>(y), fpos, n));
+    const float* w4 = m->p + m->off_W[kLayers];
+    mlp_out_kernel<<<(n + 3) / 4, 256, 0, s>>>(m->pre[kLayers - 1], w4, m->p + m->off_b[kLayers], n, m->r, target,
+                                               m->dz, m->loss_terms);
+    mlp_out_grad_kernel<<<1, 256, 0, s>>>(m->pre[kLayers - 1], m->dz, n, m->g + m->off_W[kLayers],
+                                          m->g + m->off_b[kLayers]);
+    mlp_out_back_kernel<<<(unsigned)(((int64_t)n * kHidden + 255) / 256), 256, 0, s>>>(m->pre[kLayers - 1], w4, m->dz,
+                                                                                      n, m->D, m->DT, m->ldt);
+    MLP_HIP(m, hipGetLastError());
+    bf16 *dcur = m->D, *dcurT = m->DT, *dnext = m->D2, *dnextT = m->D2T;
+    for (int l = kLayers - 1; l >= 0; --l) {
+        // weight gradient: gW[o][k] = sum_b d[b][o] in[b][k]  (A = d^T, B = in^T, K = n)
+        GemmArgs gw{};
+        gw.A = dcurT;
+        gw.B = l > 0 ? m->HT[l - 1] : m->XT;
+        gw.rows = kHidden;
+        gw.cols = layer_in(l);
+        gw.K = n;
+        gw.lda = m->ldt;
+        gw.ldb = m->ldt;
+        gw.out_f32 = m->g + m->off_W[l];
+        MLP_HIP(m, gemm<kEpiStore>(s, gw));
+        mlp_bias_grad_kernel<<<kHidden, 256, 0, s>>>(dcurT, n, m->ldt, m->g + m->off_b[l]);
+        MLP_HIP(m, hipGetLastError());
+        if (l > 0) {
+            // d_prev[b][i] = (sum_o d[b][o] W[o][i]) GELU'(pre_prev[b][i])  (B = W^T)
+            GemmArgs gd{};
+            gd.A = dcur;
+            gd.B = m->WTb[l];
+            gd.rows = n;
+            gd.cols = layer_in(l);
+            gd.K = kHidden;
+            gd.lda = kHidden;
+            gd.ldb = kHidden;
+            gd.pre = m->pre[l - 1];
+            gd.out_bf = dnext;
+            gd.out_bfT = dnextT;
+            gd.ldt = m->ldt;
+            MLP_HIP(m, gemm<kEpiBwdGelu>(s, gd));
+            std::swap(dcur, dnext);
+            std::swap(dcurT, dnextT);
+        }
+    }
+    if (loss) {
+        std::vector<double> lt(n);
+        MLP_HIP(m, hipMemcpyAsync(lt.data(), m->loss_terms, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+        MLP_HIP(m, hipStreamSynchronize(s));
+        double t = 0.0;
+        for (int i = 0; i < n; ++i) t += lt[i];
+        *loss = t / n;
+    }
+    if (grads_out) MLP_HIP(m, hipMemcpyAsync(grads_out, m->g, m->nparam * 4, hipMemcpyDeviceToHost, s));
+    MLP_HIP(m, hipStreamSynchronize(s));
+    return FCA_OK;
+}
+
+fca_status fca_mlp_adamw(fca_mlp* m, float lr, float beta1, float beta2, float eps, float weight_decay) {
+    if (!m) return FCA_E_ARG;
+    m->step += 1;
+    const float c1 = 1.0f - std::pow(beta1, (float)m->step), c2 = 1.0f - std::pow(beta2, (float)m->step);
+    mlp_adamw_kernel<<<(unsigned)((m->nparam + 255) / 256), 256, 0, m->stream>>>(m->p, m->g, m->m1, m->m2, m->nparam, lr,
+                                                                                  beta1, beta2, eps, weight_decay, c1, c2);
+    MLP_HIP(m, hipGetLastError());
+    MLP_HIP(m, refresh_weights(m));
+    MLP_HIP(m, hipStreamSynchronize(m->stream));
+    return FCA_OK;
+}
+
+fca_status fca_mlp_init_powers(fca_mlp* m, const float* y, int32_t F, int32_t N, float* v0_out) {
+    if (!m || !y || !v0_out || F < 1 || N < 1) return FCA_E_ARG;
+    const hipStream_t s = m->stream;
+    const int64_t FN = (int64_t)F * N;
+    for (int64_t first = 0; first < FN; first += m->max_batch) {
+        const int cnt = (int)std::min<int64_t>(m->max_batch, FN - first);
+        mlp_gather_bins_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(reinterpret_cast<const float2*>(y), F, N, m->M, first,
+                                                                cnt, m->ybins, m->fpos);
+        MLP_HIP(m, hipGetLastError());
+        MLP_HIP(m, forward(m, m->ybins, m->fpos, cnt));
+        mlp_out_kernel<<<(cnt + 3) / 4, 256, 0, s>>>(m->pre[kLayers - 1], m->p + m->off_W[kLayers],
+                                                    m->p + m->off_b[kLayers], cnt, m->r, nullptr, nullptr, nullptr);
+        mlp_powers_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(m->ybins, m->r, m->M, first, cnt, FN, v0_out);
+        MLP_HIP(m, hipGetLastError());
+    }
+    MLP_HIP(m, hipStreamSynchronize(s));
+    return FCA_OK;
+}
+
+}  // extern "C"

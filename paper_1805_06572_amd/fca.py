@@ -33,7 +33,10 @@ STATUS_NAMES = {0: "FCA_OK", -1: "FCA_E_ARG", -2: "FCA_E_NOMEM", -3: "FCA_E_DEVI
                 -4: "FCA_E_NOT_PD", -5: "FCA_E_NONFINITE", -6: "FCA_E_STATE"}
 
 EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_em_step", "fca_conv_em_step", "fca_separate",
-            "fca_status_per_freq", "fca_last_error", "fca_destroy", "fca_gevd", "fca_timing"]
+            "fca_status_per_freq", "fca_last_error", "fca_destroy", "fca_gevd", "fca_timing",
+            "fca_mlp_create", "fca_mlp_destroy", "fca_mlp_num_params", "fca_mlp_last_error",
+            "fca_mlp_get_params", "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward",
+            "fca_mlp_adamw", "fca_mlp_init_powers"]
 
 
 class fca_problem(ctypes.Structure):
@@ -74,8 +77,24 @@ def lib() -> ctypes.CDLL:
         L.fca_destroy.restype = None
         L.fca_gevd.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
         L.fca_timing.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        L.fca_mlp_create.argtypes = [i32, ctypes.c_uint64, i32, vp, ctypes.POINTER(vp)]
+        L.fca_mlp_destroy.argtypes = [vp]
+        L.fca_mlp_destroy.restype = None
+        L.fca_mlp_num_params.argtypes = [vp]
+        L.fca_mlp_num_params.restype = i64
+        L.fca_mlp_last_error.argtypes = [vp]
+        L.fca_mlp_last_error.restype = ctypes.c_char_p
+        L.fca_mlp_get_params.argtypes = [vp, vp]
+        L.fca_mlp_set_params.argtypes = [vp, vp]
+        L.fca_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
+        L.fca_mlp_backward.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), vp]
+        L.fca_mlp_adamw.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float]
+        L.fca_mlp_init_powers.argtypes = [vp, vp, i32, i32, vp]
         for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_em_step", "fca_conv_em_step", "fca_separate",
-                     "fca_status_per_freq", "fca_gevd", "fca_timing"):
+                     "fca_status_per_freq", "fca_gevd", "fca_timing", "fca_mlp_create", "fca_mlp_get_params",
+                     "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward", "fca_mlp_adamw",
+                     "fca_mlp_init_powers"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -267,3 +286,102 @@ def fca_timing(ctx: Ctx, enable: bool):
     n = ctypes.c_int64()
     _check(lib().fca_timing(ctx.handle, 1 if enable else 0, ctypes.byref(ms), ctypes.byref(n)), ctx)
     return ms.value, n.value
+
+
+# ---------------------------------------------------------------------- learned initial powers (MLP)
+class Mlp:
+    """Handle of an fca_mlp (per-bin network predicting v1 / (v1 + v2))."""
+
+    def __init__(self, M: int, seed: int = 0, max_batch: int = 8192, device=None):
+        self.device = torch.device(device or "cuda:0")
+        self.M = M
+        self.max_batch = max_batch
+        h = ctypes.c_void_p()
+        st = lib().fca_mlp_create(M, seed, max_batch, _stream_handle(self.device), ctypes.byref(h))
+        if st != FCA_OK:
+            raise FcaError(st, lib().fca_mlp_last_error(None).decode())
+        self.handle = h.value
+        self.num_params = int(lib().fca_mlp_num_params(self.handle))
+
+    def _check(self, st):
+        if st != FCA_OK:
+            raise FcaError(st, lib().fca_mlp_last_error(self.handle).decode())
+
+    def close(self):
+        if self.handle:
+            lib().fca_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fca_mlp_create(M: int, seed: int = 0, max_batch: int = 8192) -> Mlp:
+    return Mlp(M, seed, max_batch)
+
+
+def fca_mlp_destroy(m: Mlp):
+    m.close()
+
+
+def fca_mlp_num_params(m: Mlp) -> int:
+    return m.num_params
+
+
+def fca_mlp_last_error(m: Mlp = None) -> str:
+    return lib().fca_mlp_last_error(m.handle if m is not None else None).decode()
+
+
+def fca_mlp_get_params(m: Mlp) -> np.ndarray:
+    out = np.zeros(m.num_params, np.float32)
+    m._check(lib().fca_mlp_get_params(m.handle, out.ctypes.data))
+    return out
+
+
+def fca_mlp_set_params(m: Mlp, params: np.ndarray):
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    assert params.shape == (m.num_params,)
+    m._check(lib().fca_mlp_set_params(m.handle, params.ctypes.data))
+
+
+def _dev(t, dtype):
+    t = _as_tensor(t, dtype)
+    return t.to("cuda").contiguous() if t.device.type != "cuda" else t.contiguous()
+
+
+def fca_mlp_forward(m: Mlp, y, fpos) -> torch.Tensor:
+    """r for bins y [n, M] complex64 with positions fpos [n] (device tensors or numpy)."""
+    y = _dev(y, torch.complex64)
+    fpos = _dev(fpos, torch.float32)
+    n = y.shape[0]
+    r = torch.empty(n, dtype=torch.float32, device=y.device)
+    m._check(lib().fca_mlp_forward(m.handle, y.data_ptr(), fpos.data_ptr(), n, r.data_ptr()))
+    return r
+
+
+def fca_mlp_backward(m: Mlp, y, fpos, target, want_grads=False):
+    """(loss, grads or None) of the mean binary cross-entropy on one batch."""
+    y = _dev(y, torch.complex64)
+    fpos = _dev(fpos, torch.float32)
+    target = _dev(target, torch.float32)
+    loss = ctypes.c_double()
+    g = np.zeros(m.num_params, np.float32) if want_grads else None
+    m._check(lib().fca_mlp_backward(m.handle, y.data_ptr(), fpos.data_ptr(), target.data_ptr(), y.shape[0],
+                                    ctypes.byref(loss), g.ctypes.data if g is not None else None))
+    return loss.value, g
+
+
+def fca_mlp_adamw(m: Mlp, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4):
+    m._check(lib().fca_mlp_adamw(m.handle, lr, beta1, beta2, eps, weight_decay))
+
+
+def fca_mlp_init_powers(m: Mlp, y) -> torch.Tensor:
+    """Learned start v0 [2, F, N] (float32, device) for y [F, N, M] complex64."""
+    y = _dev(y, torch.complex64)
+    F, N, M = y.shape
+    v0 = torch.empty((2, F, N), dtype=torch.float32, device=y.device)
+    m._check(lib().fca_mlp_init_powers(m.handle, y.data_ptr(), F, N, v0.data_ptr()))
+    return v0

@@ -1,0 +1,69 @@
+"""Learned initial powers for the EM (optional; not part of the paper).
+
+Trains the library's per-bin network (fca_mlp_*, hand-written HIP kernels)
+on independent bins of the array workload, and produces the learned start
+v_j^(0) = (r, 1 - r) 2 ||y||^2 / M for a mixture. The plain start stays the
+fallback: `choose_start` evaluates the log-likelihood of both starts with the
+EM itself (an evaluation-only fca_em_step) and keeps the better one.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import fca, synth
+
+
+def train(M: int = 4, F: int = 513, steps: int = 400, batch: int = 8192, lr: float = 1e-3,
+          weight_decay: float = 1e-4, seed: int = 0, chunk_steps: int = 50, log=None):
+    """Train a network for M microphones; returns (Mlp, list of batch losses)."""
+    net = fca.Mlp(M, seed=seed, max_batch=batch)
+    rng = np.random.default_rng(10_000 + seed)
+    losses = []
+    step = 0
+    while step < steps:
+        k = min(chunk_steps, steps - step)
+        y, fpos, r = synth.array_bins(k * batch, M, F, rng)
+        yt = torch.from_numpy(y).cuda()
+        ft = torch.from_numpy(fpos).cuda()
+        rt = torch.from_numpy(r).cuda()
+        for i in range(k):
+            sl = slice(i * batch, (i + 1) * batch)
+            loss, _ = fca.fca_mlp_backward(net, yt[sl], ft[sl], rt[sl])
+            fca.fca_mlp_adamw(net, lr=lr, weight_decay=weight_decay)
+            losses.append(loss)
+        step += k
+        if log:
+            log(f"step {step}: loss {np.mean(losses[-k:]):.5f}")
+    return net, losses
+
+
+def evaluate(net, n: int = 65536, M: int = 4, F: int = 513, seed: int = 99):
+    """(network loss, loss of the best constant predictor) on held-out bins."""
+    from .fca import fca_mlp_forward
+    rng = np.random.default_rng(20_000 + seed)
+    y, fpos, r = synth.array_bins(n, M, F, rng)
+    yt, ft = torch.from_numpy(y).cuda(), torch.from_numpy(fpos).cuda()
+    pred = np.concatenate([fca_mlp_forward(net, yt[i:i + net.max_batch], ft[i:i + net.max_batch]).cpu().numpy()
+                           for i in range(0, n, net.max_batch)])
+    pred = np.clip(pred.astype(np.float64), 1e-7, 1 - 1e-7)
+    t = r.astype(np.float64)
+    bce = float(np.mean(-(t * np.log(pred) + (1 - t) * np.log(1 - pred))))
+    c = t.mean()
+    bce_const = float(np.mean(-(t * np.log(c) + (1 - t) * np.log(1 - c))))
+    return bce, bce_const
+
+
+def choose_start(net, y: torch.Tensor):
+    """(v0 or None, ll_plain, ll_learned): the learned start if the EM rates it
+    higher than the plain start at iteration 0, else None (plain start)."""
+    v0 = fca.fca_mlp_init_powers(net, y)
+    lls = []
+    for start in (None, v0):
+        ctx = fca.fca_init(y, v0=start, prec=fca.FCA_FP32_BULK)
+        try:
+            ll, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False, allow_flags=True)
+        finally:
+            fca.fca_destroy(ctx)
+        lls.append(float(ll.cpu().numpy()[0, 0]))
+    return (v0 if lls[1] > lls[0] else None), lls[0], lls[1]

@@ -151,6 +151,38 @@ def ar1_log_powers(rng: np.random.Generator, F: int, N: int, rho: float = 0.9) -
     return np.exp(lv)
 
 
+def array_bins(n: int, M: int, F: int, rng: np.random.Generator):
+    """n independent time-frequency bins of the array workload, for training
+    the learned initialisation. Each bin draws its own two DOAs (source 1 is
+    the one with the smaller angle), its frequency bin uniformly in 0..F-1
+    and its powers from the stationary marginal of the AR(1) log-power model
+    (log-normal with the moments of log Gamma(0.5, 1)). The bins of one
+    mixture share DOAs and are correlated in time; a per-bin network only sees
+    one bin, whose marginal distribution is the same.
+    Returns y [n, M] complex64, fpos [n] = f/(F-1) float32, r [n] = v1/(v1+v2)
+    float32."""
+    theta = np.sort(rng.uniform(0.0, np.pi, size=(n, 2)), axis=1)
+    k = rng.integers(0, F, size=n)
+    fhz = bin_frequencies_hz(F)[k]
+    mu, var = -1.9635100260214235, np.pi ** 2 / 2.0
+    v = np.exp(mu + np.sqrt(var) * rng.standard_normal((n, 2)))
+    m = np.arange(M)
+    dist = np.abs(m[:, None] - m[None, :]) * MIC_SPACING_M
+    G = np.sinc(2.0 * fhz[:, None, None] * dist[None] / SOUND_SPEED_MPS)   # sin(x)/x, x = 2 pi f d / c
+    z = cn(rng, (n, 2, M))
+    y = np.zeros((n, M), np.complex128)
+    for j in range(2):
+        a = np.exp(-2j * np.pi * fhz[:, None] * m[None, :] * MIC_SPACING_M * np.cos(theta[:, j:j + 1])
+                   / SOUND_SPEED_MPS)
+        R = a[:, :, None] * np.conj(a[:, None, :]) + 0.1 * G
+        w, U = np.linalg.eigh(R)
+        B = U * np.sqrt(np.clip(w, 0.0, None))[:, None, :]
+        y += np.sqrt(v[:, j])[:, None] * np.einsum("nab,nb->na", B, z[:, j])
+    fpos = (k / max(F - 1, 1)).astype(np.float32)
+    r = (v[:, 0] / (v[:, 0] + v[:, 1])).astype(np.float32)
+    return y.astype(np.complex64), fpos, r
+
+
 def condition_numbers(R: np.ndarray) -> np.ndarray:
     """[F] max_j cond_2(R_j(f)) of the true covariances (a data property used
     to decide which bins a finite-precision comparison is meaningful on)."""

@@ -1,0 +1,102 @@
+"""GPU checks of the learned-initialisation network kernels against the FP64
+reference (oracle/mlp.py) on the same BF16-rounded weights. Tolerances follow
+from BF16 storage of weights and activations (8-bit significand, relative
+rounding 2^-9 per value, a few roundings per path): 2e-2 on r, 5e-2 on the
+relative norm of each gradient block."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+from paper_1805_06572_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_06572_amd import fca as mod
+    mod.lib()
+    return mod
+
+
+def blocks(p):
+    """Split a flat parameter vector into its named blocks."""
+    out, o = {}, 0
+    for l in range(3):
+        fan = 32 if l == 0 else 256
+        out[f"W{l + 1}"] = p[o:o + 256 * fan]
+        o += 256 * fan
+        out[f"b{l + 1}"] = p[o:o + 256]
+        o += 256
+    out["w4"] = p[o:o + 256]
+    out["b4"] = p[o + 256:o + 257]
+    return out
+
+
+@pytest.mark.parametrize("M", [2, 4, 8])
+def test_forward_matches_reference(fca, M):
+    net = fca.Mlp(M, seed=3, max_batch=1024)
+    rng = np.random.default_rng(M)
+    y, fpos, r = synth.array_bins(1000, M, 513, rng)
+    got = fca.fca_mlp_forward(net, y, fpos).cpu().numpy()
+    p = ref.bf16_round(fca.fca_mlp_get_params(net))
+    want, _ = ref.forward(p, ref.features(y, fpos))
+    np.testing.assert_allclose(got, want, atol=2e-2)
+    assert np.corrcoef(got, want)[0, 1] > 0.99
+
+
+def test_backward_matches_reference(fca):
+    M = 4
+    net = fca.Mlp(M, seed=5, max_batch=2048)
+    rng = np.random.default_rng(11)
+    y, fpos, r = synth.array_bins(1024, M, 513, rng)
+    loss, g = fca.fca_mlp_backward(net, y, fpos, r, want_grads=True)
+    p = ref.bf16_round(fca.fca_mlp_get_params(net))
+    want_loss, want_g = ref.loss_and_grad(p, ref.features(y, fpos), r.astype(np.float64))
+    assert abs(loss - want_loss) < 1e-2 * abs(want_loss)
+    gb, wb = blocks(g.astype(np.float64)), blocks(want_g)
+    for name in gb:
+        err = np.linalg.norm(gb[name] - wb[name]) / max(np.linalg.norm(wb[name]), 1e-30)
+        assert err < 5e-2, (name, err)
+    # the padded input columns of the first layer get no gradient
+    W1 = gb["W1"].reshape(256, 32)
+    assert np.all(W1[:, 3 * M - 1:] == 0)
+
+
+def test_parameters_round_trip(fca):
+    net = fca.Mlp(4, seed=1, max_batch=256)
+    p = fca.fca_mlp_get_params(net)
+    q = (p * 0.5).astype(np.float32)
+    fca.fca_mlp_set_params(net, q)
+    np.testing.assert_array_equal(fca.fca_mlp_get_params(net), q)
+
+
+def test_training_beats_constant_predictor(fca):
+    from paper_1805_06572_amd import learned_init
+    net, losses = learned_init.train(M=4, steps=150, batch=4096, chunk_steps=50, seed=2)
+    assert np.mean(losses[-20:]) < np.mean(losses[:5])
+    bce, bce_const = learned_init.evaluate(net, n=32768, M=4)
+    print(f"held-out BCE: network {bce:.4f}, best constant {bce_const:.4f}")
+    assert bce < bce_const
+
+
+def test_learned_start_feeds_the_em_with_fallback(fca):
+    from paper_1805_06572_amd import learned_init
+    net, _ = learned_init.train(M=4, steps=100, batch=4096, chunk_steps=50, seed=4)
+    rng = np.random.default_rng(123)
+    v = synth.ar1_log_powers(rng, 65, 400)
+    mx = synth.array_mixture(4, 65, 400, seed=123, v=v)
+    y = torch.from_numpy(mx.y).cuda()
+    v0 = fca.fca_mlp_init_powers(net, y)
+    s = 2 * (np.abs(mx.y) ** 2).sum(-1) / 4
+    v0h = v0.cpu().numpy()
+    np.testing.assert_allclose(v0h[0] + v0h[1], s, rtol=1e-5)
+    assert np.all(v0h > 0)
+    chosen, ll_plain, ll_learned = learned_init.choose_start(net, y)
+    print(f"LL(theta0): plain {ll_plain:.1f}, learned {ll_learned:.1f}")
+    assert (chosen is None) == (ll_learned <= ll_plain)

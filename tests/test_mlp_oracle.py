@@ -1,0 +1,56 @@
+"""Pins of the FP64 MLP reference (CPU): its analytic gradient against
+central finite differences, GELU against its definition, and the feature
+map on a hand-checked bin."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import mlp
+from paper_1805_06572_amd import synth
+
+
+def small_params(rng):
+    n_par = 256 * 32 + 256 + 2 * (256 * 256 + 256) + 256 + 1
+    p = rng.standard_normal(n_par) * 0.05
+    Ws, bs, w4, b4 = mlp.unpack(p)
+    return p
+
+
+def test_gradient_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    p = small_params(rng)
+    y, fpos, r = synth.array_bins(16, 4, 513, rng)
+    X = mlp.features(y, fpos)
+    L, g = mlp.loss_and_grad(p, X, r.astype(np.float64))
+    idx = rng.choice(len(p), 40, replace=False)
+    for i in idx:
+        h = 1e-5
+        e = np.zeros_like(p)
+        e[i] = h
+        fd = (mlp.loss(p + e, X, r) - mlp.loss(p - e, X, r)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 + 1e-5 * abs(fd), (i, fd, g[i])
+
+
+def test_gelu_definition_and_derivative():
+    x = np.linspace(-6, 6, 101)
+    from scipy.stats import norm
+    np.testing.assert_allclose(mlp.gelu(x), x * norm.cdf(x), rtol=1e-12, atol=1e-15)
+    h = 1e-6
+    np.testing.assert_allclose(mlp.gelu_grad(x), (mlp.gelu(x + h) - mlp.gelu(x - h)) / (2 * h), rtol=1e-7, atol=1e-9)
+
+
+def test_features_of_a_hand_checked_bin():
+    y = np.array([[1 + 1j, 2j, -3.0, 0.0]])
+    X = mlp.features(y, np.array([0.25]))
+    np.testing.assert_allclose(X[0, :3], np.log([2.0, 4.0, 9.0]), rtol=1e-12)
+    # angle(2j) - angle(1+1j) = pi/4; angle(-3) - angle(1+1j) = 3pi/4; y_4 = 0 -> (0, 0)
+    np.testing.assert_allclose(X[0, 4:10], [np.cos(np.pi / 4), np.sin(np.pi / 4), np.cos(3 * np.pi / 4),
+                                            np.sin(3 * np.pi / 4), 0.0, 0.0], atol=1e-12)
+    assert X[0, 10] == 0.25 and np.all(X[0, 11:] == 0)
+
+
+def test_bf16_rounding_is_nearest_even():
+    a = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 3.14159265], np.float32)
+    b = mlp.bf16_round(a)
+    np.testing.assert_array_equal(b[:3], [1.0, 1.0, 1.0 + 2 ** -6])
+    assert abs(b[3] - 3.140625) < 1e-7
