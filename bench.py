@@ -1,6 +1,6 @@
 """Benchmark of the FastFCA EM hot path on one MI355X.
 
-Workload (default): one synthetic array mixture, M = 4 microphones, F = 513
+Default workload: one synthetic array mixture, M = 4 microphones, F = 513
 bins, N = 1000 frames, complex64 input, FP32 bulk arithmetic with FP64
 eigendecomposition and log-likelihood sums, 50 EM iterations. One step is the
 whole path on that input, with the input already resident in HBM: set the
@@ -8,9 +8,16 @@ initial values (plain start), 50 EM iterations returning the per-iteration
 log-likelihood, R_j(f) and v_j(n,f), then the MMSE source images.
 
 Metric: time-frequency-bin EM updates per second = F * N * iterations / step
-time. Prints one JSON line (rank 0) with a roofline entry for the EM-iteration
-kernel (timed with HIP events on the stream it runs on) and the CPU oracle
-(conventional FCA EM, FP64) timed on the host's cores on the same workload.
+time. Prints one JSON line with a roofline entry for the EM-iteration kernel
+(timed with HIP events on the stream it runs on), the conventional-EM kernel
+timed on the same workload (in-run baseline) and the CPU oracle
+(conventional FCA EM, FP64) on the host's cores.
+
+Other workloads (--workload): "batched" = 64 mixtures with N uniform in
+[200, 2000] and M drawn from {2, 4, 8}; "large" = 16 mixtures, M = 8,
+F = 1025, N = 8000, 100 iterations (frames streamed); "time-to-target" =
+learned start + one batched run of held-out mixtures against the plain start
+run one mixture at a time.
 """
 from __future__ import annotations
 
@@ -26,10 +33,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TF-bin EM updates/sec at M=4; time-to-target log-lik vs plain FastFCA"
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak
-FLOP_PER_UPDATE_M4 = 24 * 4 * 4 + 25 * 4   # A1 8M^2 + A5 16M^2 + A2..A4 ~25M (per bin per iteration)
+PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "em_kernel_array_m4_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1805_06572_amd", "csrc", f)
                   for f in ("fca_kernels.hip", "fca_device.h", "fca_internal.h")]
+
+
+def flop_per_update(M: int) -> int:
+    """Algorithmic flops of one bin through one iteration: y~ = P^H y (8 M^2),
+    the S~ accumulation (16 M^2), the scalar E/M-step and log-likelihood (~25 M)."""
+    return 24 * M * M + 25 * M
+
+
+def bytes_per_update(M: int) -> int:
+    """y read (8 M B, complex64), v read and written (2 x 8 B)."""
+    return 8 * M + 16
 
 
 def kernel_source_hash() -> str:
@@ -51,27 +69,261 @@ def load_traffic():
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(mx, iters: int, sample_freqs: int):
-    """Time the CPU oracle on a bounded frequency sample of the same workload
-    (frequencies are independent EM problems, so a subset is an exact
-    sub-problem)."""
+def cpu_baseline(mixtures, iters: int, freqs_per_mixture: int, frames: int | None = None):
+    """Time the CPU oracle (conventional EM, FP64) on a bounded sample of the
+    workload: the given mixtures, evenly spaced frequencies (frequencies are
+    independent EM problems, so a subset is an exact sub-problem) and
+    optionally the first `frames` frames."""
     import numpy as np
     import oracle
 
-    F = mx.y.shape[0]
-    idx = np.linspace(0, F - 1, sample_freqs).round().astype(int)
-    y64 = mx.y.astype(np.complex128)
-    S0, v0 = oracle.default_init(y64)
-    ys, S0s, v0s = np.ascontiguousarray(y64[idx]), np.ascontiguousarray(S0[:, idx]), np.ascontiguousarray(v0[:, idx])
     cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
-    oracle.em(ys[:2], S0s[:, :2], v0s[:, :2], 1, threads=cores)     # load + warm
+    total_t, updates, desc = 0.0, 0, []
+    for y in mixtures:
+        F, N, _ = y.shape
+        idx = np.linspace(0, F - 1, min(freqs_per_mixture, F)).round().astype(int)
+        y64 = np.ascontiguousarray(np.asarray(y, dtype=np.complex128)[idx, :frames])
+        S0, v0 = oracle.default_init(y64)
+        oracle.em(y64[:1, :8], S0[:, :1], v0[:, :1, :8], 1, threads=cores)   # load + warm
+        t0 = time.perf_counter()
+        oracle.em(y64, S0, v0, iters, threads=cores)
+        total_t += time.perf_counter() - t0
+        updates += y64.shape[0] * y64.shape[1] * iters
+        desc.append(f"{len(idx)}/{F} frequencies x {y64.shape[1]} frames")
+    return {"value": updates / total_t, "unit": "updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{'; '.join(desc[:2])}{' ...' if len(desc) > 2 else ''} ({len(mixtures)} mixture(s)), "
+                      f"{iters} iterations of the conventional FCA EM in FP64 ({total_t:.2f} s wall)"}
+
+
+class Runner:
+    """One context with device buffers for the outputs and a timed step."""
+
+    def __init__(self, fca, ys, iters, prec, v0s=None):
+        import torch
+        self.fca, self.iters = fca, iters
+        self.ctx = fca.fca_init_batch(ys, v0s=v0s, prec=prec)
+        c = self.ctx
+        dev = c.device
+        self.ll = torch.empty((c.B, max(iters, 1)), dtype=torch.float64, device=dev)
+        self.R = torch.empty(sum(2 * c.F * m * m for m in c.Ms), dtype=torch.complex128, device=dev)
+        self.v = torch.empty(sum(2 * c.F * n for n in c.Ns), dtype=c.real_dtype, device=dev)
+        self.x = torch.empty(sum(2 * c.F * n * m for n, m in zip(c.Ns, c.Ms)), dtype=c.complex_dtype, device=dev)
+        self.lib = fca.lib()
+        self.ok = (fca.FCA_OK, fca.FCA_E_NOT_PD, fca.FCA_E_NONFINITE)
+
+    def step(self, conventional=False, separate=True):
+        fca, h = self.fca, self.ctx.handle
+        st = self.lib.fca_reset(h)
+        assert st == fca.FCA_OK, fca.fca_last_error(self.ctx)
+        entry = self.lib.fca_conv_em_step if conventional else self.lib.fca_em_step
+        st = entry(h, self.iters, self.ll.data_ptr(), self.R.data_ptr(), self.v.data_ptr())
+        assert st in self.ok, fca.fca_last_error(self.ctx)
+        if separate:
+            st = self.lib.fca_separate(h, self.x.data_ptr())
+            assert st == fca.FCA_OK, fca.fca_last_error(self.ctx)
+
+    def timed(self, steps, warmup, **kw):
+        """(ms per step, EM-kernel ms per step)."""
+        import torch
+        for _ in range(warmup):
+            self.step(**kw)
+        torch.cuda.synchronize()
+        self.fca.fca_timing(self.ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step(**kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms, _ = self.fca.fca_timing(self.ctx, False)
+        return dt * 1e3 / steps, ms / steps
+
+    def close(self):
+        self.fca.fca_destroy(self.ctx)
+
+
+def roofline_entry(kernel_ms, flop, bytes_alg, traffic, kernel_name):
+    achieved = flop / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic, "kernel": kernel_name,
+            "kernel_ms_per_step": kernel_ms, "flop_per_step": flop, "algorithmic_bytes_per_step": bytes_alg,
+            "hbm_equivalent_GBps": bytes_alg / (kernel_ms * 1e-3) / 1e9}
+
+
+def base_record(args, value, ms_per_step, config):
+    return {"metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": config}
+
+
+# ---------------------------------------------------------------------------- workloads
+def run_array(args):
+    import torch
+    from paper_1805_06572_amd import fca, synth
+
+    mx = synth.array_mixture(args.M, args.F, args.N, seed=1, complex64=True)
+    y = torch.from_numpy(mx.y).cuda()
+    torch.cuda.synchronize()
+    if args.copy_calibration:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    L = args.iters
+    run = Runner(fca, [y], L, fca.FCA_FP32_BULK)
+    ms_step, em_ms = run.timed(args.steps, args.warmup)
+    lls = run.ll.cpu().numpy()[0]
+    flags = fca.fca_status_per_freq(run.ctx)[0]
+    conv_steps = max(1, args.steps // 10)
+    _, conv_ms = run.timed(conv_steps, 1, conventional=True, separate=False)
+    conv_flags = fca.fca_status_per_freq(run.ctx)[0]
+    run.close()
+
+    F, N, M = args.F, args.N, args.M
+    updates = F * N * L
+    rec = base_record(args, updates / (ms_step * 1e-3), ms_step,
+                      {"workload": f"array mixture M={M} F={F} N={N}, {L} EM iterations, plain start",
+                       "mixtures": 1, "M": M, "F": F, "N": N, "iterations": L,
+                       "precision": "f32 per-bin arithmetic; f64 eigendecomposition and sums",
+                       "step": "reset + em_step(loglik, R, v) + separate"})
+    rec["roofline"] = roofline_entry(em_ms, flop_per_update(M) * updates, bytes_per_update(M) * F * N,
+                                     load_traffic() if M == 4 else None,
+                                     "em_kernel (all iterations of a call, one workgroup per frequency)")
+    rec["in_run_baseline"] = {"kernel": "conv_em_kernel (conventional frame-wise EM, same workload)",
+                              "kernel_ms_per_step": conv_ms, "updates_per_s": updates / (conv_ms * 1e-3),
+                              "fastfca_kernel_speedup": conv_ms / em_ms,
+                              "flagged_frequencies": int((conv_flags != 0).sum())}
+    rec["loglik_first_last"] = [float(lls[0]), float(lls[-1])]
+    rec["flagged_frequencies"] = int((flags != 0).sum())
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline([mx.y], L, args.F)
+    return rec
+
+
+def run_batched(args):
+    import numpy as np
+    import torch
+    from paper_1805_06572_amd import fca, synth
+
+    rng = np.random.default_rng(2)
+    B, F, L = 64, 513, args.iters
+    Ns = rng.integers(200, 2001, size=B)
+    Ms = rng.choice([2, 4, 8], size=B)
+    ys = [synth.array_mixture_device(int(Ms[b]), F, int(Ns[b]), seed=1000 + b)[0] for b in range(B)]
+    torch.cuda.synchronize()
+    run = Runner(fca, ys, L, fca.FCA_FP32_BULK)
+    ms_step, em_ms = run.timed(args.steps, args.warmup)
+    flags = fca.fca_status_per_freq(run.ctx)
+    run.close()
+    updates = int(F * Ns.sum() * L)
+    flop = int(sum(flop_per_update(int(m)) * F * int(n) * L for m, n in zip(Ms, Ns)))
+    bts = int(sum(bytes_per_update(int(m)) * F * int(n) for m, n in zip(Ms, Ns)))
+    rec = base_record(args, updates / (ms_step * 1e-3), ms_step,
+                      {"workload": f"{B} array mixtures, F={F}, N uniform in [200, 2000], M in {{2, 4, 8}}, "
+                                   f"{L} EM iterations, plain start, one batched context",
+                       "mixtures": B, "F": F, "N_total": int(Ns.sum()),
+                       "M_counts": {str(m): int((Ms == m).sum()) for m in (2, 4, 8)},
+                       "iterations": L, "precision": "f32 per-bin arithmetic; f64 eigendecomposition and sums"})
+    rec["roofline"] = roofline_entry(em_ms, flop, bts, None, "em_kernel, one launch per (M, frames-per-thread) group")
+    rec["flagged_frequencies"] = int((flags != 0).sum())
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline([ys[i].cpu().numpy() for i in range(2)], L, 64)
+    return rec
+
+
+def run_large(args):
+    import torch
+    from paper_1805_06572_amd import fca, synth
+
+    B, M, F, N, L = 16, 8, 1025, 8000, args.iters
+    ys = [synth.array_mixture_device(M, F, N, seed=4000 + b)[0] for b in range(B)]
+    torch.cuda.synchronize()
+    run = Runner(fca, ys, L, fca.FCA_FP32_BULK)
+    ms_step, em_ms = run.timed(args.steps, args.warmup)
+    flags = fca.fca_status_per_freq(run.ctx)
+    run.close()
+    updates = B * F * N * L
+    rec = base_record(args, updates / (ms_step * 1e-3), ms_step,
+                      {"workload": f"{B} array mixtures, M={M}, F={F}, N={N}, {L} EM iterations, plain start "
+                                   "(frames streamed from memory every pass)",
+                       "mixtures": B, "M": M, "F": F, "N": N, "iterations": L,
+                       "precision": "f32 per-bin arithmetic; f64 eigendecomposition and sums"})
+    bts = bytes_per_update(M) * B * F * N * L   # streamed: y and v move every iteration
+    rec["roofline"] = roofline_entry(em_ms, flop_per_update(M) * updates, bts, None,
+                                     "em_stream_kernel (frames re-read every iteration)")
+    rec["roofline"]["hbm_frac"] = rec["roofline"]["hbm_equivalent_GBps"] / PEAK_HBM_GBS
+    rec["flagged_frequencies"] = int((flags != 0).sum())
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline([ys[0].cpu().numpy()], 5, 32)
+    return rec
+
+
+def run_time_to_target(args):
+    import numpy as np
+    import torch
+    from paper_1805_06572_amd import fca, learned_init, synth
+
+    M, F, N, K, L = 4, 513, 1000, args.mixtures, args.iters
     t0 = time.perf_counter()
-    oracle.em(ys, S0s, v0s, iters, threads=cores)
-    dt = time.perf_counter() - t0
-    updates = len(idx) * mx.y.shape[1] * iters
-    return {"value": updates / dt, "unit": "updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(idx)} of {F} frequencies (evenly spaced), all {mx.y.shape[1]} frames, "
-                      f"{iters} iterations of the conventional FCA EM in FP64 ({dt:.2f} s wall)"}
+    net, losses = learned_init.train(M=M, F=F, steps=args.train_steps, batch=8192, seed=0)
+    train_s = time.perf_counter() - t0
+    bce, bce_const = learned_init.evaluate(net, n=65536, M=M, F=F)
+    ys = [synth.array_mixture_device(M, F, N, seed=3000 + k, ar1=True)[0] for k in range(K)]
+    torch.cuda.synchronize()
+
+    def iters_to_target(ll, target, ll0):
+        thr = target - 1e-3 * (target - ll0)
+        hit = np.nonzero(ll >= thr)[0]
+        return int(hit[0]) if len(hit) else None
+
+    # plain start, one mixture at a time: L iterations give the target LL(theta^L)
+    plain_iters, plain_ms, targets = [], [], []
+    for y in ys:
+        run = Runner(fca, [y], L, fca.FCA_FP32_BULK)
+        step_ms, _ = run.timed(1, 1, separate=False)
+        ll = run.ll.cpu().numpy()[0]
+        last, _, _ = fca.fca_em_step(run.ctx, 0, want_R=False, want_v=False, allow_flags=True)
+        target = float(last.cpu().numpy()[0, 0])
+        targets.append(target)
+        it = iters_to_target(np.r_[ll, target], target, ll[0])
+        plain_iters.append(it)
+        plain_ms.append(step_ms * it / L)
+        run.close()
+
+    # learned start (plain fallback judged by LL at iteration 0), all mixtures in one batch
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    v0s, chosen = [], []
+    for y in ys:
+        v0, llp, lll = learned_init.choose_start(net, y)
+        v0s.append(v0)
+        chosen.append(v0 is not None)
+    torch.cuda.synchronize()
+    init_ms = (time.perf_counter() - t1) * 1e3
+    run = Runner(fca, ys, L, fca.FCA_FP32_BULK, v0s=v0s)
+    batch_step_ms, _ = run.timed(1, 1, separate=False)
+    ll = run.ll.cpu().numpy()
+    run.close()
+    learned_iters = [iters_to_target(ll[k], targets[k], ll[k, 0]) for k in range(K)]
+    reached = [i for i in learned_iters if i is not None]
+    need = max(reached) if reached else L
+    batch_ms = batch_step_ms * need / L
+    plain_total = float(np.sum(plain_ms))
+    learned_total = init_ms + batch_ms
+    rec = base_record(args, K * F * N * L / (batch_step_ms * 1e-3), batch_step_ms,
+                      {"workload": f"time to target: {K} held-out array mixtures (AR(1) log-powers), M={M}, "
+                                   f"F={F}, N={N}; target = LL after {L} plain-start iterations",
+                       "mixtures": K, "M": M, "F": F, "N": N, "iterations": L})
+    rec["time_to_target"] = {
+        "plain_one_at_a_time_ms": plain_total, "learned_batched_ms": learned_total,
+        "speedup": plain_total / learned_total, "learned_init_and_fallback_ms": init_ms,
+        "plain_iterations": plain_iters, "learned_iterations": learned_iters,
+        "learned_start_chosen": int(sum(chosen)), "mlp_train_s": train_s,
+        "mlp_heldout_bce": bce, "constant_predictor_bce": bce_const}
+    return rec
 
 
 def main():
@@ -79,130 +331,30 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--workload", default="array", choices=["array", "batched", "large", "time-to-target"])
+    ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--M", type=int, default=4)
     ap.add_argument("--F", type=int, default=513)
     ap.add_argument("--N", type=int, default=1000)
+    ap.add_argument("--mixtures", type=int, default=16)
+    ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-freqs", type=int, default=513)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (3 times) so that "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE can be scaled to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the (mixture, frequency) problems shard with no per-iteration communication, "
-              "but multi-GPU runs are not part of it.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the (mixture, frequency) "
+              "problems shard with no per-iteration communication, but no multi-GPU path is "
+              "implemented.", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
+    if args.iters is None:
+        args.iters = 100 if args.workload == "large" else 50
     import torch
-
-    from paper_1805_06572_amd import fca, synth
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    mx = synth.array_mixture(args.M, args.F, args.N, seed=1, complex64=True)
-    y = torch.from_numpy(mx.y).to(dev)
-    torch.cuda.synchronize()
-    F, N, L = args.F, args.N, args.iters
-
-    ctx = fca.fca_init(y, prec=fca.FCA_FP32_BULK)
-    ll = torch.empty((1, L), dtype=torch.float64, device=dev)
-    R = torch.empty(2 * F * args.M * args.M, dtype=torch.complex128, device=dev)
-    v = torch.empty(2 * F * N, dtype=torch.float32, device=dev)
-    x = torch.empty(2 * F * N * args.M, dtype=torch.complex64, device=dev)
-    lib = fca.lib()
-    ok = (fca.FCA_OK, fca.FCA_E_NOT_PD, fca.FCA_E_NONFINITE)
-
-    def step():
-        st = lib.fca_reset(ctx.handle)
-        assert st == fca.FCA_OK, fca.fca_last_error(ctx)
-        st = lib.fca_em_step(ctx.handle, L, ll.data_ptr(), R.data_ptr(), v.data_ptr())
-        assert st in ok, fca.fca_last_error(ctx)
-        st = lib.fca_separate(ctx.handle, x.data_ptr())
-        assert st == fca.FCA_OK, fca.fca_last_error(ctx)
-
-    if args.copy_calibration:
-        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    fca.fca_timing(ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    em_ms, em_launches = fca.fca_timing(ctx, False)
-    lls = ll.cpu().numpy()[0]
-    flags = fca.fca_status_per_freq(ctx)[0]
-
-    # in-run baseline: the conventional frame-wise EM kernel, same workload
-    conv_steps = max(1, args.steps // 10)
-    st = lib.fca_reset(ctx.handle)
-    assert st == fca.FCA_OK, fca.fca_last_error(ctx)
-    lib.fca_conv_em_step(ctx.handle, L, ll.data_ptr(), R.data_ptr(), v.data_ptr())
-    torch.cuda.synchronize()
-    fca.fca_timing(ctx, True)
-    for _ in range(conv_steps):
-        st = lib.fca_reset(ctx.handle)
-        assert st == fca.FCA_OK, fca.fca_last_error(ctx)
-        st = lib.fca_conv_em_step(ctx.handle, L, ll.data_ptr(), R.data_ptr(), v.data_ptr())
-        assert st in ok, fca.fca_last_error(ctx)
-    torch.cuda.synchronize()
-    conv_ms, conv_launches = fca.fca_timing(ctx, False)
-    conv_flags = fca.fca_status_per_freq(ctx)[0]
-    fca.fca_destroy(ctx)
-
-    ms_per_step = dt * 1e3 / args.steps
-    updates = F * N * L
-    value = updates / (ms_per_step * 1e-3)
-    launch_ms = em_ms / max(em_launches, 1)
-    flop_per_launch = FLOP_PER_UPDATE_M4 * updates if args.M == 4 else (24 * args.M ** 2 + 25 * args.M) * updates
-    achieved_tflops = flop_per_launch / (launch_ms * 1e-3) / 1e12
-    bytes_alg = (8 * args.M + 16) * F * N          # y read + v read + v written, once per launch
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"array mixture M={args.M} F={F} N={N}, {L} EM iterations, plain start",
-                   "mixtures": 1, "M": args.M, "F": F, "N": N, "iterations": L,
-                   "precision": "f32 per-bin arithmetic; f64 eigendecomposition and sums",
-                   "step": "reset + em_step(loglik, R, v) + separate"},
-        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": load_traffic(),
-                     "kernel": "em_kernel (all iterations of a call, one workgroup per frequency)",
-                     "kernel_ms_per_launch": launch_ms, "launches": em_launches,
-                     "flop_per_launch": flop_per_launch, "algorithmic_bytes_per_launch": bytes_alg},
-        "in_run_baseline": {"kernel": "conv_em_kernel (conventional frame-wise EM, same workload)",
-                            "kernel_ms_per_launch": conv_ms / max(conv_launches, 1),
-                            "updates_per_s": updates / (conv_ms / max(conv_launches, 1) * 1e-3),
-                            "fastfca_kernel_speedup": (conv_ms / max(conv_launches, 1)) / launch_ms,
-                            "flagged_frequencies": int((conv_flags != 0).sum())},
-        "loglik_first_last": [float(lls[0]), float(lls[-1])],
-        "flagged_frequencies": int((flags != 0).sum()),
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mx, L, args.cpu_sample_freqs)
-    print(json.dumps(out), flush=True)
+    torch.cuda.set_device(0)
+    runner = {"array": run_array, "batched": run_batched, "large": run_large,
+              "time-to-target": run_time_to_target}[args.workload]
+    print(json.dumps(runner(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -198,3 +198,38 @@ def default_initial_covariances(M: int, F: int) -> np.ndarray:
     R0[:] = np.eye(M)
     R0[1, :, 0, 0] += 0.5
     return R0
+
+
+def array_mixture_device(M: int, F: int, N: int, seed: int, device="cuda:0", ar1: bool = False):
+    """The array workload drawn with torch on a device (for multi-GB inputs).
+
+    Same model as ``array_mixture`` (DOAs uniform in [0, pi), R_j = a a^H +
+    0.1 Gamma(f), eigen square root, powers Gamma(0.5, 1) or, with ar1, the
+    AR(1) log-powers of ``ar1_log_powers``), but torch's generator: the draws
+    differ from the numpy version with the same seed. Returns (y [F, N, M]
+    complex64 on the device, theta [2] numpy, R [2, F, M, M] numpy)."""
+    import torch
+
+    g = torch.Generator(device=device).manual_seed(int(seed))
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(0.0, np.pi, size=2)
+    R = array_covariances(theta, M, F)
+    w, U = np.linalg.eigh(R)
+    B = torch.from_numpy(U * np.sqrt(np.clip(w, 0.0, None))[..., None, :]).to(device=device, dtype=torch.complex64)
+    y = torch.zeros((F, N, M), dtype=torch.complex64, device=device)
+    for j in range(2):
+        if ar1:
+            mu, var, rho = -1.9635100260214235, np.pi ** 2 / 2.0, 0.9
+            e = torch.randn((F, N), generator=g, device=device) * float(np.sqrt(var * (1 - rho * rho)))
+            lv = torch.empty((F, N), device=device)
+            lv[:, 0] = mu + float(np.sqrt(var)) * torch.randn((F,), generator=g, device=device)
+            for n in range(1, N):
+                lv[:, n] = mu + rho * (lv[:, n - 1] - mu) + e[:, n]
+            v = torch.exp(lv)
+        else:
+            v = torch._standard_gamma(torch.full((F, N), 0.5, device=device), generator=g)
+        z = torch.complex(torch.randn((F, N, M), generator=g, device=device),
+                          torch.randn((F, N, M), generator=g, device=device)) / float(np.sqrt(2.0))
+        x = torch.matmul(z, B[j].transpose(-1, -2))       # x[f, n] = B_j(f) z[f, n]
+        y += x * torch.sqrt(v).unsqueeze(-1)
+    return y, theta, R
