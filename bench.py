@@ -138,6 +138,32 @@ class Runner:
         ms, _ = self.fca.fca_timing(self.ctx, False)
         return dt * 1e3 / steps, ms / steps
 
+    def graph_timed(self, steps, warmup, separate=True):
+        """ms per step of the captured step (reset + iterations + LL, R, v
+        out [+ separation]) replayed `steps` times back to back; the outputs
+        land in the same buffers as step()."""
+        import torch
+        import ctypes
+        x = self.x.data_ptr() if separate else None
+        st = self.lib.fca_graph_capture(self.ctx.handle, self.iters, 1, self.ll.data_ptr(), self.R.data_ptr(),
+                                        self.v.data_ptr(), ctypes.c_void_p(x) if x else None)
+        assert st == self.fca.FCA_OK, self.fca.fca_last_error(self.ctx)
+        if warmup:
+            st = self.lib.fca_graph_launch(self.ctx.handle, warmup)
+            assert st in self.ok, self.fca.fca_last_error(self.ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = self.lib.fca_graph_launch(self.ctx.handle, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert st in self.ok, self.fca.fca_last_error(self.ctx)
+        return dt * 1e3 / steps
+
+    def autotune(self, iters=3):
+        self.fca.fca_autotune(self.ctx, iters)
+        return [(g["M"], g["threads"], g["frames_per_thread"], g["problems"])
+                for g in self.fca.fca_launch_groups(self.ctx)]
+
     def close(self):
         self.fca.fca_destroy(self.ctx)
 
@@ -174,7 +200,9 @@ def run_array(args):
         del src, dst
     L = args.iters
     run = Runner(fca, [y], L, fca.FCA_FP32_BULK)
-    ms_step, em_ms = run.timed(args.steps, args.warmup)
+    shapes = run.autotune() if args.autotune else None
+    eager_ms, em_ms = run.timed(args.steps, args.warmup)
+    ms_step = run.graph_timed(args.steps, args.warmup) if args.graph else eager_ms
     lls = run.ll.cpu().numpy()[0]
     flags = fca.fca_status_per_freq(run.ctx)[0]
     conv_steps = max(1, args.steps // 10)
@@ -188,7 +216,10 @@ def run_array(args):
                       {"workload": f"array mixture M={M} F={F} N={N}, {L} EM iterations, plain start",
                        "mixtures": 1, "M": M, "F": F, "N": N, "iterations": L,
                        "precision": "f32 per-bin arithmetic; f64 eigendecomposition and sums",
-                       "step": "reset + em_step(loglik, R, v) + separate"})
+                       "step": "reset + em_step(loglik, R, v) + separate" +
+                               (", captured in one HIP graph and replayed" if args.graph else ""),
+                       "launch_shapes": shapes})
+    rec["eager_ms_per_step"] = eager_ms
     rec["roofline"] = roofline_entry(em_ms, flop_per_update(M) * updates, bytes_per_update(M) * F * N,
                                      load_traffic() if M == 4 else None,
                                      "em_kernel (all iterations of a call, one workgroup per frequency)")
@@ -215,7 +246,9 @@ def run_batched(args):
     ys = [synth.array_mixture_device(int(Ms[b]), F, int(Ns[b]), seed=1000 + b)[0] for b in range(B)]
     torch.cuda.synchronize()
     run = Runner(fca, ys, L, fca.FCA_FP32_BULK)
-    ms_step, em_ms = run.timed(args.steps, args.warmup)
+    shapes = run.autotune() if args.autotune else None
+    eager_ms, em_ms = run.timed(args.steps, args.warmup)
+    ms_step = run.graph_timed(args.steps, args.warmup) if args.graph else eager_ms
     flags = fca.fca_status_per_freq(run.ctx)
     run.close()
     updates = int(F * Ns.sum() * L)
@@ -226,8 +259,13 @@ def run_batched(args):
                                    f"{L} EM iterations, plain start, one batched context",
                        "mixtures": B, "F": F, "N_total": int(Ns.sum()),
                        "M_counts": {str(m): int((Ms == m).sum()) for m in (2, 4, 8)},
-                       "iterations": L, "precision": "f32 per-bin arithmetic; f64 eigendecomposition and sums"})
-    rec["roofline"] = roofline_entry(em_ms, flop, bts, None, "em_kernel, one launch per (M, frames-per-thread) group")
+                       "iterations": L, "precision": "f32 per-bin arithmetic; f64 eigendecomposition and sums",
+                       "step": "reset + em_step(loglik, R, v) + separate" +
+                               (", captured in one HIP graph and replayed" if args.graph else ""),
+                       "launch_shapes": shapes})
+    rec["eager_ms_per_step"] = eager_ms
+    rec["roofline"] = roofline_entry(em_ms, flop, bts, None,
+                                     "em_kernel, one launch per (M, frames-per-thread) group, groups concurrent")
     rec["flagged_frequencies"] = int((flags != 0).sum())
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline([ys[i].cpu().numpy() for i in range(2)], L, 64)
@@ -239,11 +277,14 @@ def run_large(args):
     from paper_1805_06572_amd import fca, synth
 
     B, M, F, N, L = 16, 8, 1025, 8000, args.iters
-    ys = [synth.array_mixture_device(M, F, N, seed=4000 + b)[0] for b in range(B)]
+    gen = [synth.array_mixture_device(M, F, N, seed=4000 + b) for b in range(B)]
+    ys, R_true0 = [g[0] for g in gen], gen[0][2]
+    del gen
     torch.cuda.synchronize()
     run = Runner(fca, ys, L, fca.FCA_FP32_BULK)
     ms_step, em_ms = run.timed(args.steps, args.warmup)
     flags = fca.fca_status_per_freq(run.ctx)
+    run_R, run_v = run.R, run.v
     run.close()
     updates = B * F * N * L
     rec = base_record(args, updates / (ms_step * 1e-3), ms_step,
@@ -256,15 +297,45 @@ def run_large(args):
                                      "em_stream_kernel (frames re-read every iteration)")
     rec["roofline"]["hbm_frac"] = rec["roofline"]["hbm_equivalent_GBps"] / PEAK_HBM_GBS
     rec["flagged_frequencies"] = int((flags != 0).sum())
+    # error against the FP64 oracle on a subsample: mixture 0, 8 evenly spaced
+    # frequencies (each frequency is an independent EM problem), same start and
+    # iteration count; the oracle run is also the CPU baseline
+    import numpy as np
+    import oracle
+    idx = np.linspace(0, F - 1, 8).round().astype(int)
+    y64 = np.ascontiguousarray(ys[0].cpu().numpy().astype(np.complex128)[idx])
+    S0, v0 = oracle.default_init(y64)
+    cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+    t0 = time.perf_counter()
+    S, v, ll, oflags = oracle.em(y64, S0, v0, L, threads=cores)
+    cpu_s = time.perf_counter() - t0
+    gR = run_R[: 2 * F * M * M].view(2, F, M, M)[:, idx].cpu().numpy()
+    gv = run_v[: 2 * F * N].view(2, F, N)[:, idx].cpu().numpy().astype(np.float64)
+
+    def rel(a, b, axes):
+        return np.sqrt((np.abs(a - b) ** 2).sum(axes)) / np.sqrt((np.abs(b) ** 2).sum(axes))
+    ev, eR = rel(gv, v, (-1,)).max(0), rel(gR, S, (-2, -1)).max(0)
+    kappa = synth.condition_numbers(R_true0[:, idx])
+    good = kappa <= 1e3
+    rec["oracle_error_subsample"] = {
+        "sample": f"mixture 0, frequencies {idx.tolist()}, all {N} frames, {L} iterations, same plain start",
+        "kappa_R_true": [float(k) for k in kappa],
+        "v_rel_err": [float(e) for e in ev], "R_rel_err": [float(e) for e in eR],
+        "v_rel_err_max_kappa_le_1e3": float(ev[good].max()) if good.any() else None,
+        "R_rel_err_max_kappa_le_1e3": float(eR[good].max()) if good.any() else None,
+        "oracle_flagged": int((oflags != 0).sum()), "gpu_flagged": int((flags[0, idx] != 0).sum())}
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline([ys[0].cpu().numpy()], 5, 32)
+        rec["cpu_baseline"] = {"value": len(idx) * N * L / cpu_s, "unit": "updates/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{len(idx)}/{F} frequencies x {N} frames of 1 mixture, {L} iterations "
+                                         f"of the conventional FCA EM in FP64 ({cpu_s:.2f} s wall)"}
     return rec
 
 
 def run_time_to_target(args):
     import numpy as np
     import torch
-    from paper_1805_06572_amd import fca, learned_init, synth
+    from paper_1805_06572_amd import fca, learned_init, schedule, synth
 
     M, F, N, K, L = 4, 513, 1000, args.mixtures, args.iters
     t0 = time.perf_counter()
@@ -272,56 +343,92 @@ def run_time_to_target(args):
     train_s = time.perf_counter() - t0
     bce, bce_const = learned_init.evaluate(net, n=65536, M=M, F=F)
     ys = [synth.array_mixture_device(M, F, N, seed=3000 + k, ar1=True)[0] for k in range(K)]
+    ys64 = [y.to(torch.complex128) for y in ys]
     torch.cuda.synchronize()
 
-    def iters_to_target(ll, target, ll0):
-        thr = target - 1e-3 * (target - ll0)
-        hit = np.nonzero(ll >= thr)[0]
+    # Plain FastFCA (plain start, FP64, one mixture at a time, L iterations)
+    # defines each mixture's target: LL(theta^L), with a threshold at 99.9 % of
+    # the rise from LL(theta^0).
+    def one_at_a_time(yl, prec):
+        out = []
+        for y in yl:
+            run = Runner(fca, [y], L, prec)
+            step_ms, _ = run.timed(2, 1, separate=False)
+            ll = run.ll.cpu().numpy()[0]
+            last, _, _ = fca.fca_em_step(run.ctx, 0, want_R=False, want_v=False, allow_flags=True)
+            out.append((step_ms, np.r_[ll, last.cpu().numpy()[0, 0]]))
+            run.close()
+        return out
+
+    p64 = one_at_a_time(ys64, fca.FCA_FP64)
+    targets = np.array([h[-1] for _, h in p64])
+    thr = targets - 1e-3 * (targets - np.array([h[0] for _, h in p64]))
+
+    def first_hit(h, t):
+        hit = np.nonzero(np.asarray(h) >= t)[0]
         return int(hit[0]) if len(hit) else None
 
-    # plain start, one mixture at a time: L iterations give the target LL(theta^L)
-    plain_iters, plain_ms, targets = [], [], []
-    for y in ys:
-        run = Runner(fca, [y], L, fca.FCA_FP32_BULK)
-        step_ms, _ = run.timed(1, 1, separate=False)
-        ll = run.ll.cpu().numpy()[0]
-        last, _, _ = fca.fca_em_step(run.ctx, 0, want_R=False, want_v=False, allow_flags=True)
-        target = float(last.cpu().numpy()[0, 0])
-        targets.append(target)
-        it = iters_to_target(np.r_[ll, target], target, ll[0])
-        plain_iters.append(it)
-        plain_ms.append(step_ms * it / L)
-        run.close()
+    def prorated(runs):
+        its = [first_hit(h, thr[k]) for k, (_, h) in enumerate(runs)]
+        ms = sum(step_ms * (L if it is None else it) / L for (step_ms, _), it in zip(runs, its))
+        return ms, its
 
-    # learned start (plain fallback judged by LL at iteration 0), all mixtures in one batch
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    v0s, chosen = [], []
-    for y in ys:
-        v0, llp, lll = learned_init.choose_start(net, y)
-        v0s.append(v0)
-        chosen.append(v0 is not None)
-    torch.cuda.synchronize()
-    init_ms = (time.perf_counter() - t1) * 1e3
-    run = Runner(fca, ys, L, fca.FCA_FP32_BULK, v0s=v0s)
-    batch_step_ms, _ = run.timed(1, 1, separate=False)
-    ll = run.ll.cpu().numpy()
-    run.close()
-    learned_iters = [iters_to_target(ll[k], targets[k], ll[k, 0]) for k in range(K)]
-    reached = [i for i in learned_iters if i is not None]
-    need = max(reached) if reached else L
-    batch_ms = batch_step_ms * need / L
-    plain_total = float(np.sum(plain_ms))
-    learned_total = init_ms + batch_ms
-    rec = base_record(args, K * F * N * L / (batch_step_ms * 1e-3), batch_step_ms,
+    plain64_ms, plain64_its = prorated(p64)
+    plain32_ms, plain32_its = prorated(one_at_a_time(ys, fca.FCA_FP32_BULK))
+
+    hit_rule = schedule.reached(thr)
+    conv_rule = schedule.converged(1e-6)
+
+    def stop(b, ll):
+        return hit_rule(b, ll) or conv_rule(b, ll)
+
+    def batched(learned):
+        """Wall time of one batched FP32 run from context-ready to every
+        mixture stopped (warm: the same run once before, untimed)."""
+        res = None
+        for rep in range(2):
+            ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            chosen = None
+            if learned:
+                chosen, _, _ = learned_init.choose_starts(net, ctx, ys)
+            t2 = time.perf_counter()
+            iters, hist = schedule.run_batch(ctx, 2 * L, 2, stop)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            fca.fca_destroy(ctx)
+            res = ((t3 - t1) * 1e3, (t2 - t1) * 1e3, iters, hist, chosen)
+        return res
+
+    bp_ms, _, bp_iters, bp_hist, _ = batched(False)
+    bl_ms, bl_init_ms, bl_iters, bl_hist, chosen = batched(True)
+    bl_hits = [first_hit(h, thr[k]) for k, h in enumerate(bl_hist)]
+    bp_hits = [first_hit(h, thr[k]) for k, h in enumerate(bp_hist)]
+    rec = base_record(args, K * F * N * float(np.mean(bl_iters)) / (bl_ms * 1e-3), bl_ms,
                       {"workload": f"time to target: {K} held-out array mixtures (AR(1) log-powers), M={M}, "
-                                   f"F={F}, N={N}; target = LL after {L} plain-start iterations",
+                                   f"F={F}, N={N}; target = LL of plain FastFCA (FP64, plain start) after "
+                                   f"{L} iterations, reached at 99.9 % of its rise",
                        "mixtures": K, "M": M, "F": F, "N": N, "iterations": L})
+    rec["steps"], rec["warmup"] = 1, 1
     rec["time_to_target"] = {
-        "plain_one_at_a_time_ms": plain_total, "learned_batched_ms": learned_total,
-        "speedup": plain_total / learned_total, "learned_init_and_fallback_ms": init_ms,
-        "plain_iterations": plain_iters, "learned_iterations": learned_iters,
-        "learned_start_chosen": int(sum(chosen)), "mlp_train_s": train_s,
+        "plain_fastfca_fp64_one_at_a_time_ms": plain64_ms,
+        "plain_fastfca_fp32_one_at_a_time_ms": plain32_ms,
+        "batched_plain_start_fp32_ms": bp_ms,
+        "batched_learned_start_fp32_ms": bl_ms,
+        "learned_start_and_fallback_ms": bl_init_ms,
+        "speedup_vs_plain_fp64": plain64_ms / bl_ms,
+        "speedup_vs_plain_fp32": plain32_ms / bl_ms,
+        "speedup_of_learned_start_in_batch": bp_ms / bl_ms,
+        "iterations_to_target": {"plain_fp64": plain64_its, "plain_fp32": plain32_its,
+                                 "batched_plain": bp_hits, "batched_learned": bl_hits},
+        "reached": {"plain_fp32": sum(i is not None for i in plain32_its),
+                    "batched_plain": sum(i is not None for i in bp_hits),
+                    "batched_learned": sum(i is not None for i in bl_hits)},
+        "learned_start_chosen": int(np.sum(chosen)), "stop_rule": "reached target, or LL rise below 1e-6 of "
+                                                                   "the total (converged elsewhere), checked every "
+                                                                   "2 iterations",
+        "mlp_train_s": train_s, "mlp_train_steps": args.train_steps,
         "mlp_heldout_bce": bce, "constant_predictor_bce": bce_const}
     return rec
 
@@ -339,6 +446,9 @@ def main():
     ap.add_argument("--mixtures", type=int, default=16)
     ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="time the eager calls instead of the captured step")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (3 times) so that "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE can be scaled to bytes")

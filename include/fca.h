@@ -104,11 +104,34 @@ fca_status fca_init(const fca_problem *p, fca_ctx **out);
 fca_status fca_init_batch(const fca_problem *p, int32_t B, fca_ctx **out);
 
 /* Set the initial values again from the R0 and v0 given at init (or the
- * plain start), clearing all per-frequency flags (Algorithm 1, step 1).
- * Allocates nothing. */
+ * plain start), clearing all per-frequency flags (Algorithm 1, step 1), and
+ * make every mixture active again (fca_set_active). Allocates nothing. */
 fca_status fca_reset(fca_ctx *c);
 
-/* Run `iters` >= 0 EM iterations (Algorithm 1, steps 3-9) on every mixture.
+/* Replace the initial values of mixture b and reset that mixture to them
+ * (Algorithm 1, step 1); every other mixture keeps its current state.
+ *   R0  NULL (R1 = I, R2 = I + 0.5 e1 e1^H) or [2][F][M][M] complex128,
+ *       host or device, copied; must be Hermitian positive definite.
+ *   v0  NULL (the plain start ||y(n,f)||^2 / M) or [2][F][N] prec reals,
+ *       host or device, copied; must be positive.
+ * The new start is what later fca_reset calls return to, and the mixture is
+ * made active. A non-positive-definite R0 gives FCA_E_ARG and leaves mixture
+ * b reset to its previous start. The first call with v0 != NULL on a context
+ * created without any v0 allocates the context's start-power buffer. Runs
+ * asynchronously on the context's stream unless R0 or v0 is a host pointer
+ * or R0 is given (its definiteness is checked before returning). */
+fca_status fca_set_start(fca_ctx *c, int32_t b, const double *R0, const void *v0);
+
+/* Take mixture b out of (active = 0) or back into (active != 0) later
+ * fca_em_step and fca_conv_em_step calls. An inactive mixture keeps its
+ * parameters; those calls skip its frequencies and write NaN to its loglik
+ * rows (R_out, v_out and fca_separate still cover it). Lets a batch stop each
+ * mixture once it has converged. Host-only bookkeeping: the launch tables
+ * are rebuilt by the next EM call. Allocates nothing. */
+fca_status fca_set_active(fca_ctx *c, int32_t b, int32_t active);
+
+/* Run `iters` >= 0 EM iterations (Algorithm 1, steps 3-9) on every active
+ * mixture (all of them unless fca_set_active took some out).
  *   loglik  NULL, or [B][iters] doubles: the log-likelihood (eq. like,
  *           summed over all bins of the mixture) of theta^(l) at the start
  *           of iteration l. With iters == 0 nothing is updated and
@@ -162,6 +185,54 @@ fca_status fca_gevd(int32_t M, int32_t count, const double *S1, const double *S2
  * totals accumulated since the previous fca_timing call (either may be
  * NULL), and the totals restart from zero. */
 fca_status fca_timing(fca_ctx *c, int32_t enable, double *em_kernel_ms, int64_t *em_launches);
+
+/* ------------------------------------------------------------------
+ * Orchestration of batched runs: launch shapes, autotuning, captured steps.
+ * The problems of a context are launched in groups of equal M and frames-
+ * per-thread class (one launch per group and chunk of iterations; the groups
+ * of one call run concurrently on forked streams). */
+typedef struct {
+    int32_t M;                 /* microphones of the group's mixtures */
+    int32_t threads;           /* workgroup size of its EM launches (256 or 128) */
+    int32_t frames_per_thread; /* frames each thread keeps in registers; 0 = streamed */
+    int32_t problems;          /* (mixture, frequency) problems in the group */
+    int32_t max_frames;        /* largest N among them */
+} fca_launch_group;
+
+/* Copy up to cap launch-group descriptions to out; *count (if not NULL)
+ * receives the number of groups. */
+fca_status fca_launch_groups(const fca_ctx *c, fca_launch_group *out, int32_t cap, int32_t *count);
+
+/* Set the workgroup size of launch group `group`: 0 or 256 (the default), or
+ * 128 (groups of at most 1024 frames; each thread then keeps up to 8
+ * frames). Results differ only by rounding (a different reduction order).
+ * FCA_E_ARG for a group index out of range or a shape that cannot hold it. */
+fca_status fca_set_launch_shape(fca_ctx *c, int32_t group, int32_t threads);
+
+/* Pick the launch shape of every group by measurement: each admissible shape
+ * runs `iters` EM iterations (<= 0: 3) of that group alone, timed with HIP
+ * events (best of two after one warm run), and the fastest is kept. The
+ * parameters are saved before and restored after the trials, so the state
+ * of the context is unchanged. Allocates a temporary copy of v, P, Lambda,
+ * log|det P|^2 and the flags. */
+fca_status fca_autotune(fca_ctx *c, int32_t iters);
+
+/* Capture one whole step into a HIP graph owned by the context: optionally
+ * (with_reset != 0) the reset of every mixture to its start as fca_reset
+ * does (without its host-side definiteness check, already done when the
+ * start was set), `iters` EM iterations of the active mixtures, then the
+ * requested outputs, laid out as for fca_em_step and fca_separate: loglik
+ * [B][iters] (iters = 0: [B][1]), R_out, v_out, x_out. Every output must be
+ * a DEVICE pointer (or NULL) and stay valid while the graph is used. Nothing
+ * runs at capture. A new capture replaces the previous graph. */
+fca_status fca_graph_capture(fca_ctx *c, int32_t iters, int32_t with_reset, double *loglik, double *R_out,
+                             void *v_out, void *x_out);
+
+/* Replay the captured step `count` >= 1 times back to back on the context's
+ * stream and wait for them; returns FCA_E_NOT_PD / FCA_E_NONFINITE as
+ * fca_em_step does. FCA_E_STATE when nothing is captured or when the active
+ * mixtures, launch shapes or kinds of start changed since the capture. */
+fca_status fca_graph_launch(fca_ctx *c, int32_t count);
 
 /* ------------------------------------------------------------------
  * Learned initial powers (optional; not part of the paper's method).

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfca.so")
-SOURCES = ["fca_kernels.hip", "fca_conv.hip", "fca_mlp.hip", "fca_api.hip"]
+SOURCES = ["fca_em_nt256.hip", "fca_em_nt128.hip", "fca_kernels.hip", "fca_conv.hip", "fca_mlp.hip", "fca_api.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -38,11 +38,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source and link libfca.so (always rebuilds)."""
+def _stale(src: str) -> bool:
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    deps.append(os.path.join(ROOT, "include", "fca.h"))
+    return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
+
+
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile the HIP sources and link libfca.so. force=True (the default)
+    recompiles everything; force=False only sources newer than their object
+    (any header change counts for every source)."""
     os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    todo = [s for s in SOURCES if force or _stale(s)]
+    with ThreadPoolExecutor(max_workers=max(len(todo), 1)) as ex:
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(OBJ, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,5 +68,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, force="--changed" not in sys.argv)
     sys.exit(0)

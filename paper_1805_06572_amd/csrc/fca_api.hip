@@ -38,9 +38,15 @@ struct MixInfo {
     bool has_v0;
 };
 
+// A launch group: problems of equal M and frames-per-thread class (fpt for
+// kEmThreads threads, 0 = streamed), consecutive in the problem table. nt and
+// run_fpt are the launch shape used (kEmThreads and fpt unless tuned).
 struct Group {
     int M, fpt, first, count, max_n;
+    int nt = kEmThreads, run_fpt = 0;
 };
+
+constexpr int kMaxSide = 3;  // extra streams for concurrent launch groups
 
 thread_local std::string g_init_error;
 
@@ -72,6 +78,32 @@ struct fca_ctx {
     EmProblem* probs = nullptr;
     int64_t* x_off = nullptr;
     std::vector<int> flags_host;
+    int64_t v_tot = 0;  // reals in one power buffer (v, v_init)
+
+    // Launch tables: every problem (probs, groups; used by fca_separate) and
+    // the problems of active mixtures only (probs_act, groups_act; used by the
+    // EM calls while some mixture is inactive), rebuilt lazily.
+    std::vector<EmProblem> table;
+    std::vector<EmProblem> table_act;
+    EmProblem* probs_act = nullptr;
+    std::vector<Group> groups_act;
+    std::vector<char> active;
+    bool all_active = true;
+    bool act_dirty = false;
+
+    // concurrent launch groups: side streams forked from and joined to the
+    // context's stream with events (captured as parallel graph branches)
+    hipStream_t side[kMaxSide] = {nullptr, nullptr, nullptr};
+    int nside = 0;
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kMaxSide] = {nullptr, nullptr, nullptr};
+
+    // captured step (fca_graph_capture / fca_graph_launch)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int64_t shape_version = 0;  // bumped when activity or launch shapes change
+    int64_t graph_version = -1;
 
     bool broken = false;
     bool timing = false;
@@ -128,12 +160,20 @@ fca_status dev_alloc(fca_ctx* c, P** p, size_t bytes) {
 
 void free_ctx_memory(fca_ctx* c) {
     void* dev[] = {c->y, c->v, c->v_init, c->R_init, c->P, c->lam, c->logdet, c->flags, c->ll,
-                   c->ll_tot, c->fsum, c->R_stage, c->probs, c->x_off};
+                   c->ll_tot, c->fsum, c->R_stage, c->probs, c->x_off, c->probs_act};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->ll_host) (void)hipHostFree(c->ll_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (int i = 0; i < kMaxSide; ++i) {
+        if (c->side[i]) (void)hipStreamDestroy(c->side[i]);
+        if (c->join_ev[i]) (void)hipEventDestroy(c->join_ev[i]);
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
 }
 
 // Frames per thread of the resident EM kernel, or 0 (streaming kernel) when
@@ -168,41 +208,91 @@ fca_status validate(const fca_problem* p, int b, const fca_problem* p0) {
     return FCA_OK;
 }
 
-// Initial values (Algorithm 1, step 1) for every mixture.
-fca_status do_reset(fca_ctx* c) {
-    const hipStream_t s = c->stream;
-    for (int b = 0; b < c->B; ++b) {
-        const MixInfo& mi = c->mix[b];
-        char* v = static_cast<char*>(c->v) + mi.v_base * c->rsz;
-        if (mi.has_v0) {
-            FCA_HIP(c, hipMemcpyAsync(v, static_cast<char*>(c->v_init) + mi.v_base * c->rsz,
-                                      2ull * c->F * mi.npad * c->rsz, hipMemcpyDeviceToDevice, s));
-        } else {
-            const void* yb = static_cast<char*>(c->y) + mi.y_base * c->esz;
-            double* fs = c->fsum + (int64_t)b * (c->F + 1);
-            FCA_HIP(c, launch_power_sums(c->fp64, yb, mi.M, c->F, mi.N, mi.npad, fs, s));
-            FCA_HIP(c, launch_default_v(c->fp64, yb, fs, mi.M, c->F, mi.N, mi.npad, v, s));
-        }
-        const int64_t mm = (int64_t)mi.M * mi.M;
-        const double2* R1 = c->R_init + mi.R_base;
-        const double2* R2 = R1 + (int64_t)c->F * mm;
-        FCA_HIP(c, launch_gevd(mi.M, c->F, R1, R2, mm, mm, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM,
-                               kMaxM * kMaxM, c->lam + (int64_t)mi.pid0 * kMaxM, kMaxM,
-                               c->logdet + mi.pid0, c->flags + mi.pid0, s));
+// Initial values (Algorithm 1, step 1) of mixture b: v^(0) from v_init or the
+// plain start, then the FP64 GEVD of (R1^(0), R2^(0)) read from R (R_init of
+// the mixture unless a staged copy is given). Enqueued only.
+fca_status reset_mixture(fca_ctx* c, int b, const double2* R, hipStream_t s) {
+    const MixInfo& mi = c->mix[b];
+    char* v = static_cast<char*>(c->v) + mi.v_base * c->rsz;
+    if (mi.has_v0) {
+        FCA_HIP(c, hipMemcpyAsync(v, static_cast<char*>(c->v_init) + mi.v_base * c->rsz,
+                                  2ull * c->F * mi.npad * c->rsz, hipMemcpyDeviceToDevice, s));
+    } else {
+        const void* yb = static_cast<char*>(c->y) + mi.y_base * c->esz;
+        double* fs = c->fsum + (int64_t)b * (c->F + 1);
+        FCA_HIP(c, launch_power_sums(c->fp64, yb, mi.M, c->F, mi.N, mi.npad, fs, s));
+        FCA_HIP(c, launch_default_v(c->fp64, yb, fs, mi.M, c->F, mi.N, mi.npad, v, s));
     }
-    FCA_HIP(c, hipMemcpyAsync(c->flags_host.data(), c->flags, sizeof(int) * c->nprob,
+    const int64_t mm = (int64_t)mi.M * mi.M;
+    const double2* R1 = R ? R : c->R_init + mi.R_base;
+    const double2* R2 = R1 + (int64_t)c->F * mm;
+    FCA_HIP(c, launch_gevd(mi.M, c->F, R1, R2, mm, mm, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM,
+                           kMaxM * kMaxM, c->lam + (int64_t)mi.pid0 * kMaxM, kMaxM,
+                           c->logdet + mi.pid0, c->flags + mi.pid0, s));
+    return FCA_OK;
+}
+
+// Waits for the stream and reports the first frequency of mixtures
+// [b0, b1) whose initial eigendecomposition failed; on success clears their
+// flags (the sweep-limit bit of the initial eigendecomposition is not kept).
+fca_status check_initial_flags(fca_ctx* c, int b0, int b1) {
+    const hipStream_t s = c->stream;
+    const int p0 = b0 * c->F, cnt = (b1 - b0) * c->F;
+    FCA_HIP(c, hipMemcpyAsync(c->flags_host.data() + p0, c->flags + p0, sizeof(int) * cnt,
                               hipMemcpyDeviceToHost, s));
     FCA_HIP(c, hipStreamSynchronize(s));
-    for (int i = 0; i < c->nprob; ++i) {
+    for (int i = p0; i < p0 + cnt; ++i) {
         if (c->flags_host[i] & kFreezeMask) {
             set_err(c, "initial R2 (or R1) not positive definite at mixture %d, frequency %d",
                     i / c->F, i % c->F);
             return FCA_E_NOT_PD;
         }
     }
-    // the sweep-limit bit of the initial eigendecomposition is not kept
-    FCA_HIP(c, hipMemsetAsync(c->flags, 0, sizeof(int) * c->nprob, s));
+    FCA_HIP(c, launch_fill_u32(c->flags + p0, 0u, cnt, s));
     FCA_HIP(c, hipStreamSynchronize(s));
+    return FCA_OK;
+}
+
+// Initial values (Algorithm 1, step 1) for every mixture; all mixtures active.
+fca_status do_reset(fca_ctx* c) {
+    for (int b = 0; b < c->B; ++b) {
+        fca_status st = reset_mixture(c, b, nullptr, c->stream);
+        if (st != FCA_OK) return st;
+    }
+    if (!c->all_active || c->act_dirty) c->shape_version += 1;
+    std::fill(c->active.begin(), c->active.end(), 1);
+    c->all_active = true;
+    c->act_dirty = false;
+    return check_initial_flags(c, 0, c->B);
+}
+
+// Launch tables of the active mixtures (the full tables filtered, group
+// order kept), uploaded when the set of active mixtures changed.
+fca_status refresh_active(fca_ctx* c) {
+    if (!c->act_dirty) return FCA_OK;
+    c->act_dirty = false;
+    c->shape_version += 1;
+    c->all_active = std::all_of(c->active.begin(), c->active.end(), [](char a) { return a != 0; });
+    if (c->all_active) return FCA_OK;
+    c->table_act.clear();
+    c->groups_act.clear();
+    for (const Group& g : c->groups) {
+        Group ga = g;
+        ga.first = (int)c->table_act.size();
+        ga.count = 0;
+        ga.max_n = 0;
+        for (int i = g.first; i < g.first + g.count; ++i) {
+            const EmProblem& e = c->table[i];
+            if (!c->active[e.pid / c->F]) continue;
+            c->table_act.push_back(e);
+            ga.count += 1;
+            ga.max_n = std::max(ga.max_n, (int)e.n);
+        }
+        if (ga.count) c->groups_act.push_back(ga);
+    }
+    if (!c->table_act.empty())
+        FCA_HIP(c, hipMemcpyAsync(c->probs_act, c->table_act.data(), c->table_act.size() * sizeof(EmProblem),
+                                  hipMemcpyHostToDevice, c->stream));
     return FCA_OK;
 }
 
@@ -288,6 +378,8 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     bool any_stream = false;
     for (const MixInfo& mi : c->mix) any_stream = any_stream || mi.fpt == 0;
     c->v_alt = any_stream ? v_tot : 0;
+    c->v_tot = v_tot;
+    c->active.assign(B, 1);
     FCA_TRY(dev_alloc(c, &c->v, (any_stream ? 2 : 1) * v_tot * c->rsz));
     if (any_v0) FCA_TRY(dev_alloc(c, &c->v_init, v_tot * c->rsz));
     FCA_TRY(dev_alloc(c, &c->R_init, R_tot * sizeof(double2)));
@@ -300,6 +392,7 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     FCA_TRY(dev_alloc(c, &c->fsum, (size_t)B * (c->F + 1) * sizeof(double)));
     FCA_TRY(dev_alloc(c, &c->R_stage, 2ull * c->F * maxM * maxM * sizeof(double2)));
     FCA_TRY(dev_alloc(c, &c->probs, (size_t)c->nprob * sizeof(EmProblem)));
+    FCA_TRY(dev_alloc(c, &c->probs_act, (size_t)c->nprob * sizeof(EmProblem)));
     FCA_TRY(dev_alloc(c, &c->x_off, (size_t)c->nprob * 2 * sizeof(int64_t)));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->ll_host), (size_t)kLChunk * B * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
@@ -333,7 +426,7 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
             const int b = order[oi];
             const MixInfo& mi = c->mix[b];
             if (c->groups.empty() || c->groups.back().M != mi.M || c->groups.back().fpt != mi.fpt)
-                c->groups.push_back(Group{mi.M, mi.fpt, (int)table.size(), 0, 0});
+                c->groups.push_back(Group{mi.M, mi.fpt, (int)table.size(), 0, 0, kEmThreads, mi.fpt});
             Group& g = c->groups.back();
             for (int f = 0; f < c->F; ++f) {
                 EmProblem e;
@@ -352,7 +445,8 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
             g.max_n = std::max(g.max_n, mi.N);
         }
     }
-    FCA_TRY(hipcall(hipMemcpyAsync(c->probs, table.data(), table.size() * sizeof(EmProblem),
+    c->table = table;
+    FCA_TRY(hipcall(hipMemcpyAsync(c->probs, c->table.data(), c->table.size() * sizeof(EmProblem),
                                    hipMemcpyHostToDevice, s), "hipMemcpyAsync(problems)"));
     FCA_TRY(hipcall(hipMemcpyAsync(c->x_off, xoff.data(), xoff.size() * sizeof(int64_t),
                                    hipMemcpyHostToDevice, s), "hipMemcpyAsync(x offsets)"));
@@ -444,9 +538,195 @@ fca_status fca_reset(fca_ctx* c) {
     return do_reset(c);
 }
 
+fca_status fca_set_start(fca_ctx* c, int32_t b, const double* R0, const void* v0) {
+    if (!c) return FCA_E_ARG;
+    if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
+    if (b < 0 || b >= c->B) { set_err(c, "fca_set_start: mixture %d outside 0..%d", b, c->B - 1); return FCA_E_ARG; }
+    const hipStream_t s = c->stream;
+    MixInfo& mi = c->mix[b];
+    const int64_t mm = (int64_t)mi.M * mi.M;
+    const size_t rbytes = 2ull * c->F * mm * sizeof(double2);
+    double2* Rb = c->R_init + mi.R_base;
+    if (R0) {
+        // stage, decompose and check before the mixture's stored start changes
+        FCA_HIP(c, hipMemcpyAsync(c->R_stage, R0, rbytes, hipMemcpyDefault, s));
+        fca_status st = reset_mixture(c, b, c->R_stage, s);
+        if (st != FCA_OK) return st;
+        st = check_initial_flags(c, b, b + 1);
+        if (st == FCA_E_NOT_PD) {
+            st = reset_mixture(c, b, nullptr, s);
+            if (st == FCA_OK) st = check_initial_flags(c, b, b + 1);
+            if (st == FCA_OK) {
+                set_err(c, "fca_set_start: R0 of mixture %d is not positive definite", b);
+                st = FCA_E_ARG;
+            }
+            return st;
+        }
+        if (st != FCA_OK) return st;
+        FCA_HIP(c, hipMemcpyAsync(Rb, c->R_stage, rbytes, hipMemcpyDeviceToDevice, s));
+    } else {
+        FCA_HIP(c, launch_default_R(mi.M, c->F, Rb, s));
+    }
+    if (v0) {
+        if (!c->v_init) {
+            fca_status st = dev_alloc(c, &c->v_init, c->v_tot * c->rsz);
+            if (st != FCA_OK) return st;
+        }
+        const size_t vbytes = 2ull * c->F * mi.N * c->rsz;
+        const void* vsrc = v0;
+        void* vtmp = nullptr;
+        if (!is_device_ptr(v0)) {
+            fca_status st = dev_alloc(c, &vtmp, vbytes);
+            if (st != FCA_OK) return st;
+            hipError_t e = hipMemcpyAsync(vtmp, v0, vbytes, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) {
+                (void)hipFree(vtmp);
+                FCA_HIP(c, e);
+            }
+            vsrc = vtmp;
+        }
+        hipError_t e = launch_copy_v_in(c->fp64, vsrc, c->F, mi.N, mi.npad,
+                                        static_cast<char*>(c->v_init) + mi.v_base * c->rsz, s);
+        if (vtmp) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(vtmp);
+        }
+        FCA_HIP(c, e);
+    }
+    mi.has_v0 = v0 != nullptr;
+    c->shape_version += 1;  // a captured reset would copy or compute the old kind of start
+    fca_status st = reset_mixture(c, b, nullptr, s);
+    if (st != FCA_OK) return st;
+    FCA_HIP(c, launch_fill_u32(c->flags + mi.pid0, 0u, c->F, s));
+    if (!c->active[b]) {
+        c->active[b] = 1;
+        c->act_dirty = true;
+    }
+    return FCA_OK;
+}
+
+fca_status fca_set_active(fca_ctx* c, int32_t b, int32_t active) {
+    if (!c) return FCA_E_ARG;
+    if (b < 0 || b >= c->B) { set_err(c, "fca_set_active: mixture %d outside 0..%d", b, c->B - 1); return FCA_E_ARG; }
+    const char a = active != 0;
+    if (c->active[b] != a) {
+        c->active[b] = a;
+        c->act_dirty = true;
+    }
+    return FCA_OK;
+}
+
 }  // extern "C"
 
+namespace fca {
+
+hipError_t launch_em(int M, bool fp64, int nt, int fpt, const EmProblem* probs, int count, const void* y,
+                     void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll,
+                     int64_t ll_stride, int iters, hipStream_t s) {
+    if (nt == kEmThreads)
+        return launch_em_nt<kEmThreads>(M, fp64, fpt, probs, count, y, v, v_alt, P, lam, logdet, flags, ll,
+                                        ll_stride, iters, s);
+    if (nt == 128)
+        return launch_em_nt<128>(M, fp64, fpt, probs, count, y, v, v_alt, P, lam, logdet, flags, ll, ll_stride,
+                                 iters, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fca
+
 namespace {
+
+// Side streams and events for concurrent launch groups (created once).
+fca_status ensure_side_streams(fca_ctx* c, int want) {
+    want = std::min(want, kMaxSide);
+    if (!c->fork_ev) FCA_HIP(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    while (c->nside < want) {
+        const int i = c->nside;
+        FCA_HIP(c, hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
+        FCA_HIP(c, hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming));
+        c->nside += 1;
+    }
+    return FCA_OK;
+}
+
+// One chunk of `chunk` iterations for every problem of `groups`: the largest
+// group on stream s, the others spread over the side streams, all forked from
+// and joined back to s (so the groups' tails overlap instead of serialising).
+fca_status enqueue_em_groups(fca_ctx* c, const std::vector<Group>& groups, const EmProblem* probs, int chunk,
+                             bool conventional, hipStream_t s) {
+    const int ng = (int)groups.size();
+    int nside = 0;
+    if (ng > 1 && !conventional) {
+        fca_status st = ensure_side_streams(c, ng - 1);
+        if (st != FCA_OK) return st;
+        nside = std::min(ng - 1, c->nside);
+        FCA_HIP(c, hipEventRecord(c->fork_ev, s));
+        for (int i = 0; i < nside; ++i) FCA_HIP(c, hipStreamWaitEvent(c->side[i], c->fork_ev, 0));
+    }
+    // largest group first on the main stream
+    int big = 0;
+    for (int i = 1; i < ng; ++i)
+        if ((int64_t)groups[i].count * groups[i].max_n > (int64_t)groups[big].count * groups[big].max_n) big = i;
+    int k = 0;
+    for (int i = 0; i < ng; ++i) {
+        const Group& g = groups[i];
+        hipStream_t gs = s;
+        if (nside > 0 && i != big) gs = c->side[(k++) % nside];
+        if (conventional)
+            FCA_HIP(c, launch_conv_em(g.M, c->fp64, g.fpt, probs + g.first, g.count, c->y, c->v, c->P, c->lam,
+                                      c->logdet, c->flags, c->ll, c->nprob, chunk, gs));
+        else
+            FCA_HIP(c, launch_em(g.M, c->fp64, g.nt, g.run_fpt, probs + g.first, g.count, c->y, c->v, c->v_alt,
+                                 c->P, c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, gs));
+    }
+    for (int i = 0; i < nside; ++i) {
+        FCA_HIP(c, hipEventRecord(c->join_ev[i], c->side[i]));
+        FCA_HIP(c, hipStreamWaitEvent(s, c->join_ev[i], 0));
+    }
+    return FCA_OK;
+}
+
+// Log-likelihood totals of one chunk into a device [B][total] array at
+// column `done` (inactive mixtures: NaN rows).
+fca_status enqueue_ll_out(fca_ctx* c, int rows, int total, int done, double* loglik_dev, hipStream_t s) {
+    FCA_HIP(c, launch_ll_reduce(c->ll, c->nprob, rows, c->B, c->F, c->ll_tot, s));
+    if (!c->all_active)  // all-ones words: a NaN double in every row of an inactive mixture
+        for (int b = 0; b < c->B; ++b)
+            if (!c->active[b]) FCA_HIP(c, launch_fill_u32(c->ll_tot + (size_t)b * rows, 0xFFFFFFFFu, 2 * rows, s));
+    if (loglik_dev)
+        FCA_HIP(c, hipMemcpy2DAsync(loglik_dev + done, total * sizeof(double), c->ll_tot, rows * sizeof(double),
+                                    rows * sizeof(double), c->B, hipMemcpyDeviceToDevice, s));
+    return FCA_OK;
+}
+
+// R_j(f) of every mixture into a device batch array (eq. recoverS).
+fca_status enqueue_R_out(fca_ctx* c, double2* R_dev, hipStream_t s) {
+    for (int b = 0; b < c->B; ++b) {
+        const MixInfo& mi = c->mix[b];
+        const int64_t mm = (int64_t)mi.M * mi.M;
+        double2* dst = R_dev + mi.out_R;
+        FCA_HIP(c, launch_recover_R(mi.M, c->F, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM,
+                                    c->lam + (int64_t)mi.pid0 * kMaxM, dst, dst + (int64_t)c->F * mm, s));
+    }
+    return FCA_OK;
+}
+
+fca_status enqueue_v_out(fca_ctx* c, void* v_out, hipStream_t s) {
+    for (int b = 0; b < c->B; ++b) {
+        const MixInfo& mi = c->mix[b];
+        FCA_HIP(c, hipMemcpy2DAsync(static_cast<char*>(v_out) + mi.out_v * c->rsz, mi.N * c->rsz,
+                                    static_cast<char*>(c->v) + mi.v_base * c->rsz, mi.npad * c->rsz,
+                                    mi.N * c->rsz, 2 * c->F, hipMemcpyDefault, s));
+    }
+    return FCA_OK;
+}
+
+fca_status enqueue_separate(fca_ctx* c, void* x_dev, hipStream_t s) {
+    for (const Group& g : c->groups)
+        FCA_HIP(c, launch_separate(g.M, c->fp64, c->probs + g.first, g.count, g.max_n, c->y, c->v, c->P, c->lam,
+                                   x_dev, c->x_off + 2 * (int64_t)g.first, s));
+    return FCA_OK;
+}
 
 // Shared driver of fca_em_step (FastFCA kernels) and fca_conv_em_step
 // (conventional frame-wise EM kernel): chunks of at most kLChunk iterations,
@@ -455,8 +735,14 @@ fca_status em_step_impl(fca_ctx* c, int32_t iters, double* loglik, double* R_out
     if (!c) return FCA_E_ARG;
     if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
     if (iters < 0) { set_err(c, "iters < 0"); return FCA_E_ARG; }
+    {
+        fca_status st = refresh_active(c);
+        if (st != FCA_OK) return st;
+    }
+    const std::vector<Group>& groups = c->all_active ? c->groups : c->groups_act;
+    const EmProblem* probs = c->all_active ? c->probs : c->probs_act;
     if (conventional) {
-        for (const Group& g : c->groups)
+        for (const Group& g : groups)
             if (g.fpt == 0) {
                 set_err(c, "the conventional EM kernel keeps frames in registers: N <= %d", kMaxFrames);
                 return FCA_E_ARG;
@@ -469,23 +755,16 @@ fca_status em_step_impl(fca_ctx* c, int32_t iters, double* loglik, double* R_out
         const int chunk = iters == 0 ? 0 : std::min(kLChunk, iters - done);
         const int rows = chunk > 0 ? chunk : 1;
         if (c->timing) FCA_HIP(c, hipEventRecord(c->ev0, s));
-        for (const Group& g : c->groups) {
-            if (conventional)
-                FCA_HIP(c, launch_conv_em(g.M, c->fp64, g.fpt, c->probs + g.first, g.count, c->y, c->v, c->P,
-                                          c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, s));
-            else
-                FCA_HIP(c, launch_em(g.M, c->fp64, g.fpt, c->probs + g.first, g.count, c->y, c->v, c->v_alt, c->P,
-                                     c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, s));
+        {
+            fca_status st = enqueue_em_groups(c, groups, probs, chunk, conventional, s);
+            if (st != FCA_OK) return st;
         }
         if (c->timing) FCA_HIP(c, hipEventRecord(c->ev1, s));
         if (loglik) {
-            FCA_HIP(c, launch_ll_reduce(c->ll, c->nprob, rows, c->B, c->F, c->ll_tot, s));
             const int total = iters > 0 ? iters : 1;
-            if (ll_dev) {
-                FCA_HIP(c, hipMemcpy2DAsync(loglik + done, total * sizeof(double), c->ll_tot,
-                                            rows * sizeof(double), rows * sizeof(double), c->B,
-                                            hipMemcpyDeviceToDevice, s));
-            } else {
+            fca_status st = enqueue_ll_out(c, rows, total, done, ll_dev ? loglik : nullptr, s);
+            if (st != FCA_OK) return st;
+            if (!ll_dev) {
                 FCA_HIP(c, hipMemcpyAsync(c->ll_host, c->ll_tot, (size_t)rows * c->B * sizeof(double),
                                           hipMemcpyDeviceToHost, s));
                 FCA_HIP(c, hipStreamSynchronize(s));
@@ -498,7 +777,7 @@ fca_status em_step_impl(fca_ctx* c, int32_t iters, double* loglik, double* R_out
             float ms = 0.f;
             FCA_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
             c->em_ms += ms;
-            c->em_launches += (int64_t)c->groups.size();
+            c->em_launches += (int64_t)groups.size();
         }
         done += chunk;
     } while (done < iters);
@@ -619,6 +898,210 @@ fca_status fca_timing(fca_ctx* c, int32_t enable, double* em_kernel_ms, int64_t*
     c->em_launches = 0;
     c->timing = enable != 0;
     return FCA_OK;
+}
+
+
+// ---------------------------------------------------------------- launch shapes and autotuning
+fca_status fca_launch_groups(const fca_ctx* c, fca_launch_group* out, int32_t cap, int32_t* count) {
+    if (!c || (cap > 0 && !out)) return FCA_E_ARG;
+    const int ng = (int)c->groups.size();
+    if (count) *count = ng;
+    for (int i = 0; i < ng && i < cap; ++i) {
+        const Group& g = c->groups[i];
+        out[i].M = g.M;
+        out[i].threads = g.nt;
+        out[i].frames_per_thread = g.fpt == 0 ? 0 : g.run_fpt;
+        out[i].problems = g.count;
+        out[i].max_frames = g.max_n;
+    }
+    return FCA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Frames per thread for `nt` threads and up to max_n frames, or -1 when the
+// shape cannot hold the group (streamed groups keep kEmThreads).
+int shape_fpt(const Group& g, int nt) {
+    if (g.fpt == 0) return nt == kEmThreads ? 0 : -1;
+    if (nt != kEmThreads && nt != 128) return -1;
+    int f = 1;
+    while (f * nt < g.max_n) f *= 2;
+    return f <= kMaxFramesPerThread ? f : -1;
+}
+
+void shapes_changed(fca_ctx* c) {
+    c->act_dirty = true;  // rebuilds the active-mixture tables with the new shapes
+    c->shape_version += 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+fca_status fca_set_launch_shape(fca_ctx* c, int32_t group, int32_t threads) {
+    if (!c) return FCA_E_ARG;
+    if (group < 0 || group >= (int)c->groups.size()) {
+        set_err(c, "fca_set_launch_shape: group %d outside 0..%d", group, (int)c->groups.size() - 1);
+        return FCA_E_ARG;
+    }
+    Group& g = c->groups[group];
+    const int nt = threads == 0 ? kEmThreads : threads;
+    const int f = shape_fpt(g, nt);
+    if (f < 0) {
+        set_err(c, "fca_set_launch_shape: %d threads cannot hold group %d (%d frames%s)", threads, group, g.max_n,
+                g.fpt == 0 ? ", streamed" : "");
+        return FCA_E_ARG;
+    }
+    g.nt = nt;
+    g.run_fpt = f;
+    shapes_changed(c);
+    return FCA_OK;
+}
+
+fca_status fca_autotune(fca_ctx* c, int32_t iters) {
+    if (!c) return FCA_E_ARG;
+    if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
+    iters = iters <= 0 ? 3 : std::min(iters, kLChunk);
+    const hipStream_t s = c->stream;
+    // the parameters are saved and put back after every trial run
+    const size_t vb = (size_t)c->v_tot * c->rsz, pb = (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2),
+                 lb = (size_t)c->nprob * kMaxM * sizeof(double), db = (size_t)c->nprob * sizeof(double),
+                 fb = (size_t)c->nprob * sizeof(int);
+    char* save = nullptr;
+    fca_status st = dev_alloc(c, &save, vb + pb + lb + db + fb);
+    if (st != FCA_OK) return st;
+    struct Buf { void* live; size_t off, bytes; };
+    const Buf bufs[] = {{c->v, 0, vb}, {c->P, vb, pb}, {c->lam, vb + pb, lb}, {c->logdet, vb + pb + lb, db},
+                        {c->flags, vb + pb + lb + db, fb}};
+    auto copy_all = [&](bool to_save) -> hipError_t {
+        for (const Buf& b : bufs) {
+            hipError_t e = to_save ? hipMemcpyAsync(save + b.off, b.live, b.bytes, hipMemcpyDeviceToDevice, s)
+                                   : hipMemcpyAsync(b.live, save + b.off, b.bytes, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipError_t e = copy_all(true);
+    for (size_t gi = 0; gi < c->groups.size() && e == hipSuccess; ++gi) {
+        Group& g = c->groups[gi];
+        int best_nt = g.nt, best_f = g.run_fpt;
+        float best = -1.f;
+        for (int nt : {kEmThreads, 128}) {
+            const int f = shape_fpt(g, nt);
+            if (f < 0) continue;
+            float tmin = -1.f;
+            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // the first run loads the code object
+                e = copy_all(false);
+                if (e == hipSuccess) e = hipEventRecord(c->ev0, s);
+                if (e == hipSuccess)
+                    e = launch_em(g.M, c->fp64, nt, f, c->probs + g.first, g.count, c->y, c->v, c->v_alt, c->P,
+                                  c->lam, c->logdet, c->flags, c->ll, c->nprob, iters, s);
+                if (e == hipSuccess) e = hipEventRecord(c->ev1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(c->ev1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0, c->ev1);
+                if (e == hipSuccess && rep > 0 && (tmin < 0.f || ms < tmin)) tmin = ms;
+            }
+            if (e == hipSuccess && (best < 0.f || tmin < best)) {
+                best = tmin;
+                best_nt = nt;
+                best_f = f;
+            }
+        }
+        g.nt = best_nt;
+        g.run_fpt = best_f;
+    }
+    if (e == hipSuccess) e = copy_all(false);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(save);
+    shapes_changed(c);
+    if (e != hipSuccess) {
+        set_err(c, "fca_autotune: %s", hipGetErrorString(e));
+        c->broken = true;
+        return FCA_E_DEVICE;
+    }
+    return FCA_OK;
+}
+
+// ---------------------------------------------------------------- captured step
+fca_status fca_graph_capture(fca_ctx* c, int32_t iters, int32_t with_reset, double* loglik, double* R_out,
+                             void* v_out, void* x_out) {
+    if (!c) return FCA_E_ARG;
+    if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
+    if (iters < 0) { set_err(c, "iters < 0"); return FCA_E_ARG; }
+    const void* outs[] = {loglik, R_out, v_out, x_out};
+    for (const void* p : outs)
+        if (p && !is_device_ptr(p)) {
+            set_err(c, "fca_graph_capture: outputs must be device pointers");
+            return FCA_E_ARG;
+        }
+    fca_status st = refresh_active(c);
+    if (st != FCA_OK) return st;
+    FCA_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    const std::vector<Group>& groups = c->all_active ? c->groups : c->groups_act;
+    const EmProblem* probs = c->all_active ? c->probs : c->probs_act;
+    if (!c->cap_stream) FCA_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    st = ensure_side_streams(c, (int)groups.size() - 1);
+    if (st != FCA_OK) return st;
+    const hipStream_t s = c->cap_stream;
+    FCA_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    auto body = [&]() -> fca_status {
+        if (with_reset) {
+            for (int b = 0; b < c->B; ++b) {
+                fca_status r = reset_mixture(c, b, nullptr, s);
+                if (r != FCA_OK) return r;
+            }
+            FCA_HIP(c, launch_fill_u32(c->flags, 0u, c->nprob, s));
+        }
+        int done = 0;
+        do {
+            const int chunk = iters == 0 ? 0 : std::min(kLChunk, iters - done);
+            const int rows = chunk > 0 ? chunk : 1;
+            fca_status r = enqueue_em_groups(c, groups, probs, chunk, false, s);
+            if (r == FCA_OK && loglik) r = enqueue_ll_out(c, rows, iters > 0 ? iters : 1, done, loglik, s);
+            if (r != FCA_OK) return r;
+            done += chunk;
+        } while (done < iters);
+        fca_status r = FCA_OK;
+        if (R_out) r = enqueue_R_out(c, reinterpret_cast<double2*>(R_out), s);
+        if (r == FCA_OK && v_out) r = enqueue_v_out(c, v_out, s);
+        if (r == FCA_OK && x_out) r = enqueue_separate(c, x_out, s);
+        return r;
+    };
+    st = body();
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(s, &g);
+    if (st != FCA_OK || ee != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (st == FCA_OK) {
+            set_err(c, "fca_graph_capture: hipStreamEndCapture: %s", hipGetErrorString(ee));
+            st = FCA_E_DEVICE;
+        }
+        c->broken = false;  // nothing ran; the context's state is unchanged
+        (void)hipGetLastError();
+        return st;
+    }
+    c->graph = g;
+    FCA_HIP(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    c->graph_version = c->shape_version;
+    return FCA_OK;
+}
+
+fca_status fca_graph_launch(fca_ctx* c, int32_t count) {
+    if (!c) return FCA_E_ARG;
+    if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
+    if (!c->gexec) { set_err(c, "fca_graph_launch: nothing captured"); return FCA_E_STATE; }
+    if (c->act_dirty || c->graph_version != c->shape_version) {
+        set_err(c, "fca_graph_launch: active mixtures or launch shapes changed since the capture");
+        return FCA_E_STATE;
+    }
+    if (count < 1) { set_err(c, "fca_graph_launch: count < 1"); return FCA_E_ARG; }
+    for (int i = 0; i < count; ++i) FCA_HIP(c, hipGraphLaunch(c->gexec, c->stream));
+    return check_flags(c);
 }
 
 }  // extern "C"

@@ -20,6 +20,7 @@ namespace fca {
 
 template <int M, typename T> struct ConvShared {
     using T2 = typename Vec2<T>::type;
+    static constexpr int NTH = kEmThreads;
     static constexpr int MM = M * M;
     static constexpr int NV = 2 * MM;
     static constexpr int CH = NV < 32 ? NV : 32;

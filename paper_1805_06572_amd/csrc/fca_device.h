@@ -142,11 +142,12 @@ template <> struct Math<double> {
 // per-thread log-likelihood terms into sh.LL (one value per wave). The
 // accumulator layout per source j (offset j M^2): diagonal i at i, the
 // off-diagonal pair (i < k) at M + 2 pair_index(M, i, k) (+1 imaginary).
-// Sh provides red, red2, fin, LL, S and the constants CH, NCH, G, NV.
+// Sh provides red, red2, fin, LL, S and the constants NTH (threads), CH,
+// NCH, G, NV.
 template <int M, typename Sh, typename T>
 __device__ __forceinline__ void wg_reduce_sums(Sh& sh, const T (&acc)[2 * M * M], double llacc, int nf, int tid) {
     constexpr int MM = M * M, NV = Sh::NV, CH = Sh::CH, NCH = Sh::NCH, G = Sh::G;
-    constexpr int NT = kEmThreads;
+    constexpr int NT = Sh::NTH;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) llacc += __shfl_xor(llacc, off, 64);
     if ((tid & 63) == 0) sh.LL[tid >> 6] = llacc;

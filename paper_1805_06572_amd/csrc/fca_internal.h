@@ -39,18 +39,33 @@ struct EmProblem {
     int32_t m;       // microphones (checked against the kernel's template M)
 };
 
-// Launchers (defined in fca_kernels.hip). All return hipSuccess or the
-// launch error. Every pointer is a device pointer.
-// fpt: frames per thread of the resident kernel (1, 2, 4, 8), or 0 for the
-// streaming kernel, whose second power buffer starts at v + v_alt elements.
-hipError_t launch_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
-                     void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags,
-                     double* ll, int64_t ll_stride, int iters, hipStream_t s);
+// Launchers. All return hipSuccess or the launch error. Every pointer is a
+// device pointer.
+// The EM-iteration kernels (fca_em.h), instantiated for workgroup sizes NT =
+// kEmThreads (every problem) and 128 (resident problems of at most
+// 128 * kMaxFramesPerThread frames). fpt: frames per thread of the resident
+// kernel (1, 2, 4, 8; fpt * NT >= frames), or 0 for the streaming kernel
+// (NT = kEmThreads only), whose second power buffer starts at v + v_alt.
+template <int NT>
+hipError_t launch_em_nt(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y, void* v,
+                        int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll,
+                        int64_t ll_stride, int iters, hipStream_t s);
 
-// The conventional frame-wise EM (resident frames only, fpt in 1, 2, 4, 8).
+// Dispatch on nt (kEmThreads or 128); defined in fca_api.hip, which sees only
+// the declaration above, so each instantiation lives in its own translation unit.
+hipError_t launch_em(int M, bool fp64, int nt, int fpt, const EmProblem* probs, int count, const void* y,
+                     void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll,
+                     int64_t ll_stride, int iters, hipStream_t s);
+
+// The conventional frame-wise EM (fca_conv.hip; resident frames only, fpt in
+// 1, 2, 4, 8, kEmThreads threads).
 hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
                           void* v, double2* P, double* lam, double* logdet, int* flags, double* ll,
                           int64_t ll_stride, int iters, hipStream_t s);
+
+// Support kernels (fca_kernels.hip).
+// p[i] = val for count 32-bit words (a kernel, not a memset: graph-capturable).
+hipError_t launch_fill_u32(void* p, uint32_t val, int64_t count, hipStream_t s);
 
 hipError_t launch_ingest(bool fp64, const void* src, int64_t sf, int64_t sn, int64_t sm, int M,
                          int F, int N, int npad, void* dst, hipStream_t s);

@@ -32,8 +32,9 @@ FCA_FLAG_SWEEPS = 4
 STATUS_NAMES = {0: "FCA_OK", -1: "FCA_E_ARG", -2: "FCA_E_NOMEM", -3: "FCA_E_DEVICE",
                 -4: "FCA_E_NOT_PD", -5: "FCA_E_NONFINITE", -6: "FCA_E_STATE"}
 
-EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_em_step", "fca_conv_em_step", "fca_separate",
+EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set_active", "fca_em_step", "fca_conv_em_step", "fca_separate",
             "fca_status_per_freq", "fca_last_error", "fca_destroy", "fca_gevd", "fca_timing",
+            "fca_launch_groups", "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch",
             "fca_mlp_create", "fca_mlp_destroy", "fca_mlp_num_params", "fca_mlp_last_error",
             "fca_mlp_get_params", "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward",
             "fca_mlp_adamw", "fca_mlp_init_powers"]
@@ -67,6 +68,8 @@ def lib() -> ctypes.CDLL:
         L.fca_init.argtypes = [ctypes.POINTER(fca_problem), ctypes.POINTER(vp)]
         L.fca_init_batch.argtypes = [ctypes.POINTER(fca_problem), i32, ctypes.POINTER(vp)]
         L.fca_reset.argtypes = [vp]
+        L.fca_set_start.argtypes = [vp, i32, vp, vp]
+        L.fca_set_active.argtypes = [vp, i32, i32]
         L.fca_em_step.argtypes = [vp, i32, vp, vp, vp]
         L.fca_conv_em_step.argtypes = [vp, i32, vp, vp, vp]
         L.fca_separate.argtypes = [vp, vp]
@@ -77,6 +80,11 @@ def lib() -> ctypes.CDLL:
         L.fca_destroy.restype = None
         L.fca_gevd.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
         L.fca_timing.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        L.fca_launch_groups.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
+        L.fca_set_launch_shape.argtypes = [vp, i32, i32]
+        L.fca_autotune.argtypes = [vp, i32]
+        L.fca_graph_capture.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+        L.fca_graph_launch.argtypes = [vp, i32]
         L.fca_mlp_create.argtypes = [i32, ctypes.c_uint64, i32, vp, ctypes.POINTER(vp)]
         L.fca_mlp_destroy.argtypes = [vp]
         L.fca_mlp_destroy.restype = None
@@ -91,8 +99,9 @@ def lib() -> ctypes.CDLL:
         L.fca_mlp_adamw.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float]
         L.fca_mlp_init_powers.argtypes = [vp, vp, i32, i32, vp]
-        for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_em_step", "fca_conv_em_step", "fca_separate",
-                     "fca_status_per_freq", "fca_gevd", "fca_timing", "fca_mlp_create", "fca_mlp_get_params",
+        for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set_active", "fca_em_step", "fca_conv_em_step", "fca_separate",
+                     "fca_status_per_freq", "fca_gevd", "fca_timing", "fca_launch_groups",
+                     "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch", "fca_mlp_create", "fca_mlp_get_params",
                      "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward", "fca_mlp_adamw",
                      "fca_mlp_init_powers"):
             getattr(L, name).restype = ctypes.c_int
@@ -205,6 +214,29 @@ def fca_reset(ctx: Ctx):
     _check(lib().fca_reset(ctx.handle), ctx)
 
 
+def fca_set_start(ctx: Ctx, b: int, R0=None, v0=None):
+    """New initial values for mixture b (None = default R / plain powers);
+    resets that mixture and makes it active. Tensors may be on host or device."""
+    R0 = _as_tensor(R0, torch.complex128)
+    v0 = _as_tensor(v0, ctx.real_dtype)
+    M, N = ctx.Ms[b], ctx.Ns[b]
+    if R0 is not None:
+        R0 = R0.contiguous()
+        if tuple(R0.shape) != (2, ctx.F, M, M):
+            raise ValueError("R0 must be [2, F, M, M]")
+    if v0 is not None:
+        v0 = v0.contiguous()
+        if tuple(v0.shape) != (2, ctx.F, N):
+            raise ValueError("v0 must be [2, F, N]")
+    _check(lib().fca_set_start(ctx.handle, b, R0.data_ptr() if R0 is not None else None,
+                               v0.data_ptr() if v0 is not None else None), ctx)
+
+
+def fca_set_active(ctx: Ctx, b: int, active: bool):
+    """Include (True) or exclude (False) mixture b from later EM calls."""
+    _check(lib().fca_set_active(ctx.handle, b, 1 if active else 0), ctx)
+
+
 def fca_em_step(ctx: Ctx, iters: int, want_loglik=True, want_R=True, want_v=True, allow_flags=False,
                 _entry="fca_em_step"):
     """Run `iters` EM iterations. Returns (loglik [B, max(iters,1)] float64,
@@ -286,6 +318,59 @@ def fca_timing(ctx: Ctx, enable: bool):
     n = ctypes.c_int64()
     _check(lib().fca_timing(ctx.handle, 1 if enable else 0, ctypes.byref(ms), ctypes.byref(n)), ctx)
     return ms.value, n.value
+
+
+class fca_launch_group(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("threads", ctypes.c_int32), ("frames_per_thread", ctypes.c_int32),
+                ("problems", ctypes.c_int32), ("max_frames", ctypes.c_int32)]
+
+
+def fca_launch_groups(ctx: Ctx) -> list:
+    """Launch groups as dicts (M, threads, frames_per_thread, problems, max_frames)."""
+    n = ctypes.c_int32()
+    _check(lib().fca_launch_groups(ctx.handle, None, 0, ctypes.byref(n)), ctx)
+    arr = (fca_launch_group * max(n.value, 1))()
+    _check(lib().fca_launch_groups(ctx.handle, arr, n.value, ctypes.byref(n)), ctx)
+    return [{k: getattr(arr[i], k) for k, _ in fca_launch_group._fields_} for i in range(n.value)]
+
+
+def fca_set_launch_shape(ctx: Ctx, group: int, threads: int):
+    _check(lib().fca_set_launch_shape(ctx.handle, group, threads), ctx)
+
+
+def fca_autotune(ctx: Ctx, iters: int = 3):
+    _check(lib().fca_autotune(ctx.handle, iters), ctx)
+
+
+class Graph:
+    """Device outputs of a captured step (loglik [B, max(iters,1)], flat R, v, x)."""
+
+    def __init__(self, ctx: Ctx, iters: int, with_reset=True, want_loglik=True, want_R=True, want_v=True,
+                 want_x=False):
+        dev, F = ctx.device, ctx.F
+        self.ctx = ctx
+        self.loglik = torch.empty((ctx.B, max(iters, 1)), dtype=torch.float64, device=dev) if want_loglik else None
+        self.R = (torch.empty(sum(2 * F * m * m for m in ctx.Ms), dtype=torch.complex128, device=dev)
+                  if want_R else None)
+        self.v = torch.empty(sum(2 * F * n for n in ctx.Ns), dtype=ctx.real_dtype, device=dev) if want_v else None
+        self.x = (torch.empty(sum(2 * F * n * m for n, m in zip(ctx.Ns, ctx.Ms)), dtype=ctx.complex_dtype,
+                              device=dev) if want_x else None)
+        ptr = [t.data_ptr() if t is not None else None for t in (self.loglik, self.R, self.v, self.x)]
+        _check(lib().fca_graph_capture(ctx.handle, iters, 1 if with_reset else 0, *ptr), ctx)
+
+    def launch(self, count: int = 1, allow_flags=False):
+        allow = (FCA_E_NOT_PD, FCA_E_NONFINITE) if allow_flags else ()
+        _check(lib().fca_graph_launch(self.ctx.handle, count), self.ctx, allow)
+
+
+def fca_graph_capture(ctx: Ctx, iters: int, with_reset=True, **want) -> Graph:
+    """Capture one step (reset, iters EM iterations, outputs) into the context's graph."""
+    return Graph(ctx, iters, with_reset, **want)
+
+
+def fca_graph_launch(graph: Graph, count: int = 1, allow_flags=False):
+    """Replay the captured step count times and wait."""
+    graph.launch(count, allow_flags)
 
 
 # ---------------------------------------------------------------------- learned initial powers (MLP)

@@ -54,6 +54,25 @@ def evaluate(net, n: int = 65536, M: int = 4, F: int = 513, seed: int = 99):
     return bce, bce_const
 
 
+def choose_starts(net, ctx, ys):
+    """Per mixture of a batched FP32 context that stands at its plain start,
+    keep whichever of the plain and the learned start has the higher log-
+    likelihood at iteration 0 (both evaluated by the EM itself, all mixtures
+    in one evaluation pass each). Leaves ctx at the chosen starts.
+    Returns (chosen [B] bool: learned start kept, ll_plain [B], ll_learned [B])."""
+    def ll0():
+        ll, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False, allow_flags=True)
+        return ll[:, 0].cpu().numpy()
+    ll_plain = ll0()
+    for b, y in enumerate(ys):
+        fca.fca_set_start(ctx, b, v0=fca.fca_mlp_init_powers(net, y))
+    ll_learned = ll0()
+    chosen = ll_learned > ll_plain
+    for b in np.nonzero(~chosen)[0]:
+        fca.fca_set_start(ctx, int(b))
+    return chosen, ll_plain, ll_learned
+
+
 def choose_start(net, y: torch.Tensor):
     """(v0 or None, ll_plain, ll_learned): the learned start if the EM rates it
     higher than the plain start at iteration 0, else None (plain start)."""

@@ -1,0 +1,58 @@
+"""Batched EM runs that stop each mixture on its own criterion.
+
+All mixtures of a context advance together, `chunk` iterations per
+fca_em_step call; after each call every mixture whose stopping rule holds is
+taken out of later calls with fca_set_active, so the remaining mixtures get
+the whole GPU.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import fca
+
+
+def run_batch(ctx, max_iters: int, chunk: int, stop):
+    """Run until every mixture is stopped or has had max_iters iterations.
+
+    stop(b, ll) -> bool is asked after every chunk with the log-likelihood
+    history ll = [LL(theta^(0)), ..., LL(theta^(l-1))] of each still-active
+    mixture b after l iterations (the parameters then stand at theta^(l), at
+    least as likely by the monotonicity of EM).
+    Returns (iterations run per mixture [B], list of LL histories)."""
+    B = ctx.B
+    hist = [[] for _ in range(B)]
+    iters = np.zeros(B, dtype=np.int64)
+    active = np.ones(B, dtype=bool)
+    while active.any():
+        k = int(min(chunk, max_iters - iters[active].max()))
+        if k <= 0:
+            break
+        ll, _, _ = fca.fca_em_step(ctx, k, want_R=False, want_v=False, allow_flags=True)
+        ll = ll.cpu().numpy()
+        for b in np.nonzero(active)[0]:
+            hist[b].extend(ll[b].tolist())
+            iters[b] += k
+            if iters[b] >= max_iters or stop(int(b), hist[b]):
+                active[b] = False
+                fca.fca_set_active(ctx, int(b), False)
+    for b in range(B):
+        fca.fca_set_active(ctx, b, True)
+    return iters, hist
+
+
+def converged(rel_tol: float):
+    """Stopping rule: the last iteration raised the log-likelihood by less
+    than rel_tol times its total rise from LL(theta^(0))."""
+    def stop(b, ll):
+        if len(ll) < 3:
+            return False
+        return (ll[-1] - ll[-2]) <= rel_tol * abs(ll[-1] - ll[0])
+    return stop
+
+
+def reached(targets):
+    """Stopping rule: the log-likelihood reached targets[b]."""
+    def stop(b, ll):
+        return ll[-1] >= targets[b]
+    return stop

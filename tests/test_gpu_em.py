@@ -156,6 +156,117 @@ def test_fp32_loglik_per_iteration(fca, array_workload):
     assert per_freq_rel(gv.astype(np.float64), vs, (-1,)).max() < 1e-4
 
 
+def test_large_workload_subsample(fca):
+    """M=8, N=8000 (frames streamed): nine frequencies of the F=1025 grid
+    (bins 0, 128, ..., 1024 are the F=9 grid), 30 iterations, FP32 bulk and
+    FP64 against the oracle on the frequencies with kappa(R_true) <= 1e3."""
+    mx = synth.array_mixture(8, 9, 8000, 41, complex64=True)
+    y64 = mx.y.astype(np.complex128)
+    S0, v0 = oracle.default_init(y64)
+    S, v, ll, oflags = oracle.em(y64, S0, v0, 30, threads=16)
+    kappa = synth.condition_numbers(mx.R)
+    gate = (kappa <= 1e3) & (oflags == 0)
+    gll, gR, gv, gflags, _ = run_gpu(fca, mx.y, fca.FCA_FP32_BULK, 30, separate=False, allow_flags=True)
+    gate &= gflags == 0
+    assert gate.sum() >= 5
+    assert per_freq_rel(gv.astype(np.float64), v, (-1,))[:, gate].max() < 1e-4
+    # FP64 on the frequencies with kappa(R_true) <= 1e3 (the grid's lowest
+    # bins are near-singular: kappa ~ 1e7 .. inf, where any two summation
+    # orders drift apart by far more than 1e-10)
+    idx = np.nonzero(kappa <= 1e3)[0]
+    ys = np.ascontiguousarray(y64[idx])
+    S0s, v0s = oracle.default_init(ys)
+    Ss, vs, lls, ofl = oracle.em(ys, S0s, v0s, 30, threads=16)
+    gll64, gR64, gv64, gflags64, _ = run_gpu(fca, ys, fca.FCA_FP64, 30, separate=False)
+    assert not gflags64.any() and not ofl.any()
+    assert per_freq_rel(gv64, vs, (-1,)).max() < 1e-9
+    assert per_freq_rel(gR64, Ss, (-2, -1)).max() < 1e-9
+    np.testing.assert_allclose(gll64, lls[:30].sum(1), rtol=1e-10)
+
+
+# ------------------------------------------------------------------ per-mixture start and activity
+def _pair(fca):
+    a = synth.random_mixture(3, 5, 150, 51)
+    b = synth.random_mixture(2, 5, 2500, 52)      # streamed frames
+    return a, b, torch.from_numpy(a.y).to(DEV), torch.from_numpy(b.y).to(DEV)
+
+
+def test_set_start_equals_init_with_that_start(fca):
+    """fca_set_start restarts one mixture of a batch from a new start (host
+    R0, device v0); the other mixture continues untouched; fca_reset returns
+    to the new start."""
+    a, b, ya, yb = _pair(fca)
+    R0 = torch.from_numpy(b.R.copy())
+    v0 = torch.from_numpy(0.5 * b.v + 0.01).to(DEV)
+    FP = fca.FCA_FP64
+    ctx = fca.fca_init_batch([ya, yb], prec=FP)
+    plain = fca.fca_init_batch([ya, yb], prec=FP)
+    fresh = fca.fca_init_batch([ya, yb], R0s=[None, R0], v0s=[None, v0], prec=FP)
+    try:
+        fca.fca_em_step(ctx, 2)
+        fca.fca_set_start(ctx, 1, R0=R0, v0=v0)
+        ll, R, v = fca.fca_em_step(ctx, 4)
+        llp, Rp, vp = fca.fca_em_step(plain, 6)
+        llf, Rf, vf = fca.fca_em_step(fresh, 4)
+        assert torch.equal(ll[0], llp[0, 2:6]) and torch.equal(R[0], Rp[0]) and torch.equal(v[0], vp[0])
+        assert torch.equal(ll[1], llf[1]) and torch.equal(R[1], Rf[1]) and torch.equal(v[1], vf[1])
+        fca.fca_reset(ctx)
+        ll2, _, _ = fca.fca_em_step(ctx, 4, want_R=False, want_v=False)
+        assert torch.equal(ll2[1], llf[1]) and torch.equal(ll2[0], llp[0, :4])
+    finally:
+        for c in (ctx, plain, fresh):
+            fca.fca_destroy(c)
+
+
+def test_set_start_rejects_indefinite_R0(fca):
+    a, b, ya, yb = _pair(fca)
+    bad = b.R.copy()
+    bad[1] *= -1.0                                    # R2 negative definite
+    ctx = fca.fca_init_batch([ya, yb], prec=fca.FCA_FP64)
+    plain = fca.fca_init_batch([ya, yb], prec=fca.FCA_FP64)
+    try:
+        with pytest.raises(fca.FcaError) as e:
+            fca.fca_set_start(ctx, 1, R0=torch.from_numpy(bad))
+        assert e.value.status == fca.FCA_E_ARG
+        assert not fca.fca_status_per_freq(ctx).any()
+        ll, R, _ = fca.fca_em_step(ctx, 3, want_v=False)
+        llp, Rp, _ = fca.fca_em_step(plain, 3, want_v=False)
+        assert torch.equal(ll, llp) and torch.equal(R[1], Rp[1])
+    finally:
+        fca.fca_destroy(ctx)
+        fca.fca_destroy(plain)
+
+
+def test_set_active_skips_and_resumes(fca):
+    """An inactive mixture keeps its parameters and reports NaN log-
+    likelihoods; the others run as if alone; reactivated, it resumes."""
+    a, b, ya, yb = _pair(fca)
+    for prec in (fca.FCA_FP64, fca.FCA_FP32_BULK):
+        if prec == fca.FCA_FP32_BULK:
+            ya, yb = ya.to(torch.complex64), yb.to(torch.complex64)
+        ctx = fca.fca_init_batch([ya, yb], prec=prec)
+        ref = fca.fca_init_batch([ya, yb], prec=prec)
+        try:
+            _, R0_, v0_ = fca.fca_em_step(ctx, 2, allow_flags=True)
+            fca.fca_set_active(ctx, 0, False)
+            ll, R, v = fca.fca_em_step(ctx, 3, allow_flags=True)
+            llr, Rr, vr = fca.fca_em_step(ref, 5, allow_flags=True)
+            assert torch.isnan(ll[0]).all()
+            assert torch.equal(R[0], R0_[0]) and torch.equal(v[0], v0_[0])
+            assert torch.equal(ll[1], llr[1, 2:5]) and torch.equal(R[1], Rr[1]) and torch.equal(v[1], vr[1])
+            fca.fca_set_active(ctx, 1, False)
+            fca.fca_set_active(ctx, 0, True)
+            ll, R, v = fca.fca_em_step(ctx, 3, allow_flags=True)
+            assert torch.equal(ll[0], llr[0, 2:5]) and torch.equal(R[0], Rr[0]) and torch.equal(v[0], vr[0])
+            assert torch.isnan(ll[1]).all() and torch.equal(v[1], vr[1])
+            fca.fca_set_active(ctx, 0, False)             # nothing active: nothing runs
+            ll, _, v = fca.fca_em_step(ctx, 2, want_R=False, allow_flags=True)
+            assert torch.isnan(ll).all() and torch.equal(v[0], vr[0])
+        finally:
+            fca.fca_destroy(ctx)
+            fca.fca_destroy(ref)
+
+
 # ------------------------------------------------------------------ properties
 def test_separation_sums_to_mixture(fca):
     mx = synth.random_mixture(3, 5, 300, 21)

@@ -100,3 +100,34 @@ def test_learned_start_feeds_the_em_with_fallback(fca):
     chosen, ll_plain, ll_learned = learned_init.choose_start(net, y)
     print(f"LL(theta0): plain {ll_plain:.1f}, learned {ll_learned:.1f}")
     assert (chosen is None) == (ll_learned <= ll_plain)
+
+
+def test_batched_start_choice_and_per_mixture_stop(fca):
+    """choose_starts keeps the better start per mixture in one batch;
+    run_batch stops each mixture on its own rule, and each history equals a
+    lone run of that mixture from the same start."""
+    from paper_1805_06572_amd import learned_init, schedule
+    net, _ = learned_init.train(M=4, steps=100, batch=4096, chunk_steps=50, seed=4)
+    ys = []
+    for k in range(3):
+        n = 300 + 50 * k
+        v = synth.ar1_log_powers(np.random.default_rng(200 + k), 33, n)
+        ys.append(torch.from_numpy(synth.array_mixture(4, 33, n, seed=200 + k, v=v).y).cuda())
+    ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+    try:
+        chosen, llp, lll = learned_init.choose_starts(net, ctx, ys)
+        np.testing.assert_array_equal(chosen, lll > llp)
+        cur, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False, allow_flags=True)
+        np.testing.assert_array_equal(cur.cpu().numpy()[:, 0], np.where(chosen, lll, llp))
+        iters, hist = schedule.run_batch(ctx, 20, 2, lambda b, ll: len(ll) >= 2 * (b + 1))
+        assert list(iters) == [2, 4, 6]
+    finally:
+        fca.fca_destroy(ctx)
+    for k, y in enumerate(ys):
+        v0 = fca.fca_mlp_init_powers(net, y) if chosen[k] else None
+        lone = fca.fca_init(y, v0=v0, prec=fca.FCA_FP32_BULK)
+        try:
+            ll, _, _ = fca.fca_em_step(lone, int(iters[k]), want_R=False, want_v=False, allow_flags=True)
+        finally:
+            fca.fca_destroy(lone)
+        np.testing.assert_array_equal(np.asarray(hist[k]), ll.cpu().numpy()[0])

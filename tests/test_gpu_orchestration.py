@@ -1,0 +1,153 @@
+"""GPU tests of the batched orchestration: launch shapes (128-thread
+workgroups), the autotuner, concurrent launch groups and the captured step
+(HIP graph), all through the C ABI and against the CPU oracle or the eager
+path."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_06572_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def fca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_06572_amd import fca as mod
+    mod.lib()
+    return mod
+
+
+def rel(a, b, axes):
+    return np.sqrt((np.abs(a - b) ** 2).sum(axes)) / np.sqrt((np.abs(b) ** 2).sum(axes))
+
+
+# mixed batch: several launch groups, ragged tails, one streamed mixture
+SHAPES = [(2, 90), (4, 700), (3, 1000), (8, 300), (4, 2500), (6, 129)]
+
+
+def batch(F=5, seed=700, dtype=np.complex128):
+    mxs = [synth.random_mixture(M, F, N, seed + i) for i, (M, N) in enumerate(SHAPES)]
+    return mxs, [torch.from_numpy(m.y.astype(dtype)).to(DEV) for m in mxs]
+
+
+def test_128_thread_shape_matches_oracle(fca):
+    """Every group that 128-thread workgroups can hold runs with them; FP64
+    results match the oracle per mixture."""
+    mxs, ys = batch()
+    ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP64)
+    try:
+        groups = fca.fca_launch_groups(ctx)
+        changed = 0
+        for g, info in enumerate(groups):
+            if info["frames_per_thread"] != 0 and info["max_frames"] <= 1024:
+                fca.fca_set_launch_shape(ctx, g, 128)
+                changed += 1
+            else:
+                with pytest.raises(fca.FcaError):
+                    fca.fca_set_launch_shape(ctx, g, 128)
+        assert changed >= 4
+        after = fca.fca_launch_groups(ctx)
+        for info in after:
+            if info["threads"] == 128:
+                assert info["frames_per_thread"] * 128 >= info["max_frames"]
+        ll, R, v = fca.fca_em_step(ctx, 6)
+    finally:
+        fca.fca_destroy(ctx)
+    for k, mx in enumerate(mxs):
+        S0, v0 = oracle.default_init(mx.y)
+        S, vo, llo, fl = oracle.em(mx.y, S0, v0, 6, threads=8)
+        assert not fl.any()
+        assert rel(v[k].cpu().numpy(), vo, (-1,)).max() < 1e-9
+        assert rel(R[k].cpu().numpy(), S, (-2, -1)).max() < 1e-9
+        np.testing.assert_allclose(ll[k].cpu().numpy(), llo[:6].sum(1), rtol=1e-10)
+
+
+def test_autotune_restores_state_and_keeps_results(fca):
+    mxs, ys = batch(dtype=np.complex64)
+    a = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+    b = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+    try:
+        fca.fca_em_step(a, 2, allow_flags=True)
+        fca.fca_em_step(b, 2, allow_flags=True)
+        _, R0, v0 = fca.fca_em_step(a, 0, allow_flags=True)
+        fca.fca_autotune(a, 3)
+        _, R1, v1 = fca.fca_em_step(a, 0, allow_flags=True)
+        for k in range(len(ys)):                     # the trials left no trace
+            assert torch.equal(R0[k], R1[k]) and torch.equal(v0[k], v1[k])
+        shapes = fca.fca_launch_groups(a)
+        assert all(s["threads"] in (128, 256) for s in shapes)
+        lla, Ra, va = fca.fca_em_step(a, 5, allow_flags=True)
+        llb, Rb, vb = fca.fca_em_step(b, 5, allow_flags=True)
+        np.testing.assert_allclose(lla.cpu().numpy(), llb.cpu().numpy(), rtol=1e-5)
+        for k in range(len(ys)):
+            assert rel(va[k].double().cpu().numpy(), vb[k].double().cpu().numpy(), (-1,)).max() < 1e-4
+    finally:
+        fca.fca_destroy(a)
+        fca.fca_destroy(b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replays_equal_the_eager_step(fca, prec):
+    """reset + L iterations + R, v, x out, captured once and replayed three
+    times with eager work in between: every replay equals the eager step
+    bit for bit."""
+    P = fca.FCA_FP64 if prec == "fp64" else fca.FCA_FP32_BULK
+    _, ys = batch(dtype=np.complex128 if prec == "fp64" else np.complex64)
+    L = 7
+    ctx = fca.fca_init_batch(ys, prec=P)
+    try:
+        ll_e, R_e, v_e = fca.fca_em_step(ctx, L, allow_flags=True)
+        x_e = fca.fca_separate(ctx)
+        g = fca.fca_graph_capture(ctx, L, with_reset=True, want_x=True)
+        for rep in range(3):
+            fca.fca_graph_launch(g, 1, allow_flags=True)
+            assert torch.equal(g.loglik, ll_e)
+            assert torch.equal(g.R, torch.cat([r.reshape(-1) for r in R_e]))
+            assert torch.equal(g.v, torch.cat([t.reshape(-1) for t in v_e]))
+            assert torch.equal(g.x, torch.cat([t.reshape(-1) for t in x_e]))
+            # eager work between replays on the same context and stream
+            fca.fca_reset(ctx)
+            fca.fca_em_step(ctx, 2, allow_flags=True)
+            torch.cuda.synchronize()
+        fca.fca_graph_launch(g, 4, allow_flags=True)     # back-to-back replays
+        assert torch.equal(g.loglik, ll_e)
+    finally:
+        fca.fca_destroy(ctx)
+
+
+def test_graph_with_inactive_mixture_and_stale_shape(fca):
+    _, ys = batch()
+    ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP64)
+    ref = fca.fca_init_batch(ys, prec=fca.FCA_FP64)
+    try:
+        fca.fca_set_active(ctx, 1, False)
+        g = fca.fca_graph_capture(ctx, 4, with_reset=True)
+        fca.fca_graph_launch(g, 2)
+        ll_r, R_r, v_r = fca.fca_em_step(ref, 4)
+        ll = g.loglik.cpu().numpy()
+        assert np.isnan(ll[1]).all()
+        others = [k for k in range(len(ys)) if k != 1]
+        np.testing.assert_array_equal(ll[others], ll_r.cpu().numpy()[others])
+        # mixture 1 was reset by the replay but not iterated: its v is the plain start
+        fca.fca_reset(ref)
+        _, _, v_start = fca.fca_em_step(ref, 0)
+        n0 = sum(2 * ctx.F * n for n in ctx.Ns[:1])
+        n1 = n0 + 2 * ctx.F * ctx.Ns[1]
+        assert torch.equal(g.v[n0:n1], v_start[1].reshape(-1))
+        fca.fca_set_active(ctx, 1, True)               # activity changed since the capture
+        with pytest.raises(fca.FcaError) as e:
+            fca.fca_graph_launch(g, 1)
+        assert e.value.status == fca.FCA_E_STATE
+        g2 = fca.fca_graph_capture(ctx, 4, with_reset=True)
+        fca.fca_graph_launch(g2, 1)
+        np.testing.assert_array_equal(g2.loglik.cpu().numpy(), ll_r.cpu().numpy())
+    finally:
+        fca.fca_destroy(ctx)
+        fca.fca_destroy(ref)
