@@ -38,12 +38,26 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _deps(path: str, seen: set) -> set:
+    """The file and the local headers it includes, recursively."""
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    for line in open(path):
+        line = line.strip()
+        if line.startswith('#include "'):
+            name = line.split('"')[1]
+            for d in (CSRC, os.path.join(ROOT, "include")):
+                if os.path.exists(os.path.join(d, name)):
+                    _deps(os.path.join(d, name), seen)
+    return seen
+
+
 def _stale(src: str) -> bool:
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
     if not os.path.exists(obj):
         return True
-    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
-    deps.append(os.path.join(ROOT, "include", "fca.h"))
+    deps = _deps(os.path.join(CSRC, src), set())
     return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
 
 

@@ -377,10 +377,13 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     FCA_TRY(dev_alloc(c, &c->y, y_tot * c->esz));
     bool any_stream = false;
     for (const MixInfo& mi : c->mix) any_stream = any_stream || mi.fpt == 0;
-    c->v_alt = any_stream ? v_tot : 0;
+    // the second power buffer of the streaming kernel is always there, so any
+    // group can be switched to streaming (fca_set_launch_shape, fca_autotune)
+    (void)any_stream;
+    c->v_alt = v_tot;
     c->v_tot = v_tot;
     c->active.assign(B, 1);
-    FCA_TRY(dev_alloc(c, &c->v, (any_stream ? 2 : 1) * v_tot * c->rsz));
+    FCA_TRY(dev_alloc(c, &c->v, 2 * v_tot * c->rsz));
     if (any_v0) FCA_TRY(dev_alloc(c, &c->v_init, v_tot * c->rsz));
     FCA_TRY(dev_alloc(c, &c->R_init, R_tot * sizeof(double2)));
     FCA_TRY(dev_alloc(c, &c->P, (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2)));
@@ -921,10 +924,12 @@ fca_status fca_launch_groups(const fca_ctx* c, fca_launch_group* out, int32_t ca
 
 namespace {
 
-// Frames per thread for `nt` threads and up to max_n frames, or -1 when the
-// shape cannot hold the group (streamed groups keep kEmThreads).
-int shape_fpt(const Group& g, int nt) {
-    if (g.fpt == 0) return nt == kEmThreads ? 0 : -1;
+// Frames per thread for `nt` threads and up to max_n frames (0: streamed),
+// or -1 when the shape cannot hold the group. Every group can stream with
+// kEmThreads threads; groups beyond the resident limit can only stream.
+int shape_fpt(const Group& g, int nt, bool streamed) {
+    if (streamed) return nt == kEmThreads ? 0 : -1;
+    if (g.fpt == 0) return -1;
     if (nt != kEmThreads && nt != 128) return -1;
     int f = 1;
     while (f * nt < g.max_n) f *= 2;
@@ -940,7 +945,7 @@ void shapes_changed(fca_ctx* c) {
 
 extern "C" {
 
-fca_status fca_set_launch_shape(fca_ctx* c, int32_t group, int32_t threads) {
+fca_status fca_set_launch_shape(fca_ctx* c, int32_t group, int32_t threads, int32_t streamed) {
     if (!c) return FCA_E_ARG;
     if (group < 0 || group >= (int)c->groups.size()) {
         set_err(c, "fca_set_launch_shape: group %d outside 0..%d", group, (int)c->groups.size() - 1);
@@ -948,10 +953,10 @@ fca_status fca_set_launch_shape(fca_ctx* c, int32_t group, int32_t threads) {
     }
     Group& g = c->groups[group];
     const int nt = threads == 0 ? kEmThreads : threads;
-    const int f = shape_fpt(g, nt);
+    const int f = shape_fpt(g, nt, streamed != 0);
     if (f < 0) {
-        set_err(c, "fca_set_launch_shape: %d threads cannot hold group %d (%d frames%s)", threads, group, g.max_n,
-                g.fpt == 0 ? ", streamed" : "");
+        set_err(c, "fca_set_launch_shape: %d threads%s cannot hold group %d (%d frames%s)", threads,
+                streamed ? " streaming" : "", group, g.max_n, g.fpt == 0 ? ", streamed only" : "");
         return FCA_E_ARG;
     }
     g.nt = nt;
@@ -988,8 +993,11 @@ fca_status fca_autotune(fca_ctx* c, int32_t iters) {
         Group& g = c->groups[gi];
         int best_nt = g.nt, best_f = g.run_fpt;
         float best = -1.f;
-        for (int nt : {kEmThreads, 128}) {
-            const int f = shape_fpt(g, nt);
+        const int cand_nt[3] = {kEmThreads, 128, kEmThreads};
+        const bool cand_stream[3] = {false, false, true};
+        for (int ci = 0; ci < 3; ++ci) {
+            const int nt = cand_nt[ci];
+            const int f = shape_fpt(g, nt, cand_stream[ci]);
             if (f < 0) continue;
             float tmin = -1.f;
             for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // the first run loads the code object

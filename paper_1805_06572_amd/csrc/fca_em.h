@@ -22,6 +22,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fca_device.h"
 #include "fca_internal.h"
 
@@ -31,6 +33,7 @@ namespace fca {
 // LDS state of one (mixture, frequency) problem inside an EM workgroup.
 template <int M, typename T, int NT_ = kEmThreads> struct EmShared {
     static constexpr int NTH = NT_;  // threads of the workgroup
+    using Tb = T;
     using T2 = typename Vec2<T>::type;
     static constexpr int MM = M * M;
     static constexpr int NV = 2 * MM;             // reals accumulated per thread
@@ -54,8 +57,8 @@ template <int M, typename T, int NT_ = kEmThreads> struct EmShared {
     GevdScratch ws;
 };
 
-template <int M, typename T, int NT_>
-__device__ __forceinline__ void em_load_state(EmShared<M, T, NT_>& sh, const double2* __restrict__ Pg,
+template <int M, typename Sh>
+__device__ __forceinline__ void em_load_state(Sh& sh, const double2* __restrict__ Pg,
                                               const double* __restrict__ lamg,
                                               const double* __restrict__ logdetg,
                                               const int* __restrict__ flagsg, int pid, int tid) {
@@ -68,8 +71,8 @@ __device__ __forceinline__ void em_load_state(EmShared<M, T, NT_>& sh, const dou
     }
 }
 
-template <int M, typename T, int NT_>
-__device__ __forceinline__ void em_store_state(const EmShared<M, T, NT_>& sh, double2* __restrict__ Pg,
+template <int M, typename Sh>
+__device__ __forceinline__ void em_store_state(const Sh& sh, double2* __restrict__ Pg,
                                                double* __restrict__ lamg, double* __restrict__ logdetg,
                                                int* __restrict__ flagsg, int pid, int tid) {
     if (tid < M * M) Pg[(int64_t)pid * kMaxM * kMaxM + tid] = sh.P[tid];
@@ -81,8 +84,9 @@ __device__ __forceinline__ void em_store_state(const EmShared<M, T, NT_>& sh, do
 }
 
 // P^(l) and Lambda^(l) in the bulk precision; a __syncthreads must follow.
-template <int M, typename T, int NT_>
-__device__ __forceinline__ void em_prepare(EmShared<M, T, NT_>& sh, int tid) {
+template <int M, typename Sh>
+__device__ __forceinline__ void em_prepare(Sh& sh, int tid) {
+    using T = typename Sh::Tb;
     if (tid < M * M) {
         const double2 p = sh.P[tid];
         sh.Pt[tid] = make_vec2<T>((T)p.x, (T)p.y);
@@ -96,19 +100,24 @@ __device__ __forceinline__ void em_prepare(EmShared<M, T, NT_>& sh, int tid) {
 //   mu~1_i = v1 lam_i y~_i / d_i, mu~2_i = v2 y~_i / d_i          eq. (MMSEtilde)
 //   c_i = v1 v2 lam_i / d_i  (diagonal of Phi~_j - mu~_j mu~_j^H)  eq. (updatePhitildeeff)
 //   v1' = tr(Lambda^-1 Phi~1)/M, v2' = tr(Phi~2)/M                  eq. (updateveff)
-//   acc += (mu~_j mu~_j^H + diag c) / v_j'  (upper triangle)       eq. (updateStildeeff)
+//   Phi~_j / v_j' = u_j u_j^H + diag(c) / v_j', u_j = mu~_j / sqrt(v_j')
+//                                                                  eq. (updateStildeeff)
 //   llacc += -sum_i log d_i - sum_i |y~_i|^2 / d_i   (log-likelihood of theta^(l))
 // `ok` masks padding frames (no contribution, powers unchanged).
+// em_bin_front: everything up to u_j; leaves y~ (ytr, yti), e_i = |y~_i|^2,
+// r_i = 1 / d_i and w_j = 1 / sqrt(v_j') (0 for padding).
 template <int M, typename T>
-__device__ __forceinline__ void em_bin(const T (&yr)[M], const T (&yi)[M], T a1, T a2, const T (&lm)[M],
-                                       const typename Vec2<T>::type* Pt, bool ok, T (&acc)[2 * M * M],
-                                       double& llacc, T& nv1o, T& nv2o, bool& bad) {
+__device__ __forceinline__ void em_bin_front(const T (&yr)[M], const T (&yi)[M], T a1, T a2, const T (&lm)[M],
+                                             const typename Vec2<T>::type* Pt, bool ok, double& llacc, T& nv1o,
+                                             T& nv2o, bool& bad, T (&ytr)[M], T (&yti)[M], T (&e)[M], T (&r)[M],
+                                             T& w1, T& w2) {
     using T2 = typename Vec2<T>::type;
     using MT = Math<T>;
-    constexpr int MM = M * M;
-    T ytr[M], yti[M], e[M], r[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
+        // from M = 5 on, P (2 M^2 values) is read column by column from LDS
+        // rather than all hoisted into registers
+        if constexpr (M > 4) __builtin_amdgcn_sched_barrier(0);
         T sr = T(0), si = T(0);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -150,9 +159,20 @@ __device__ __forceinline__ void em_bin(const T (&yr)[M], const T (&yi)[M], T a1,
         nv1o = nv1;
         nv2o = nv2;
     }
-    // u_j = mu~_j / sqrt(v_j') makes the rank-one term u_j u_j^H
-    const T w1 = ok ? MT::rsqrt(nv1) : T(0);
-    const T w2 = ok ? MT::rsqrt(nv2) : T(0);
+    w1 = ok ? MT::rsqrt(nv1) : T(0);
+    w2 = ok ? MT::rsqrt(nv2) : T(0);
+}
+
+// The bin with the sums of Phi~_j / v_j' kept per thread: the diagonal of
+// source j at acc[j M^2 + i], the upper-triangle pair (i < k) at
+// acc[j M^2 + M + 2 pair_index(M, i, k)] (+1 imaginary).
+template <int M, typename T>
+__device__ __forceinline__ void em_bin(const T (&yr)[M], const T (&yi)[M], T a1, T a2, const T (&lm)[M],
+                                       const typename Vec2<T>::type* Pt, bool ok, T (&acc)[2 * M * M],
+                                       double& llacc, T& nv1o, T& nv2o, bool& bad) {
+    constexpr int MM = M * M;
+    T ytr[M], yti[M], e[M], r[M], w1, w2;
+    em_bin_front<M, T>(yr, yi, a1, a2, lm, Pt, ok, llacc, nv1o, nv2o, bad, ytr, yti, e, r, w1, w2);
     const T iv1 = w1 * w1, iv2 = w2 * w2;
     T u1r[M], u1i[M], u2r[M], u2i[M];
 #pragma unroll
@@ -181,22 +201,187 @@ __device__ __forceinline__ void em_bin(const T (&yr)[M], const T (&yi)[M], T a1,
     }
 }
 
-// End of one pass over the frames: FP64 reduction of the accumulators and of
-// the log-likelihood over the workgroup (fixed order), S~_j = sums / N, record
-// LL(theta^(it)), then the FP64 GEVD of (S~1, S~2) and the basis update
-// P <- P Q, Lambda <- Sigma (eqs. GEVDeff5, updatePeff, updateLambdaeff) on
-// wave 0. Returns true when the caller must stop iterating: an evaluation-only
-// pass, a problem frozen on entry, or a failure that froze it now (it then
-// keeps theta^(it), whose log-likelihood stands for the later iterations).
-template <int M, typename T, int NT_>
-__device__ __forceinline__ bool em_finish(EmShared<M, T, NT_>& sh, const T (&acc)[2 * M * M], double llacc,
-                                          bool bad, int it, int iters, bool frozen_at_entry, int nf,
+// ---------------------------------------------------------------- S~ accumulation on MFMA
+// For M >= kMfmaMinM in the float bulk mode the sums of u_j u_j^H run on the
+// matrix cores: per wave and 64 frames (one per lane) the real 2M x 64 matrix
+// W_j = [Re u_j; Im u_j] (rows padded to 16 with zeros) is staged in LDS and
+// G_j += W_j W_j^T is 16 MFMA 16x16x4 steps; then
+//   Re (sum u u^H)_ik = G_ik + G_(M+i)(M+k),  Im (sum u u^H)_ik = G_(M+i)k - G_i(M+k).
+// This removes the 2 M^2 per-thread accumulators (register spills at M = 8)
+// and moves 16 M^2 of the 24 M^2 flops per bin off the vector ALUs.
+constexpr int kMfmaMinM = 5;
+// Staging layout of W_j for one wave: element (row r, frame f) at
+// r * kStgRow + (f % 4) * 16 + f / 4, so that the 16 values a lane feeds to the
+// 16 MFMA steps (row lane % 16, frames 4 kb + lane / 16, kb = 0..15) are
+// contiguous (four 16-byte reads); the row pitch of 68 floats keeps those
+// reads free of bank conflicts.
+constexpr int kStgRow = 68;
+constexpr int kStgSrc = 16 * kStgRow;  // floats per source block of a wave
+using f32x4 = float __attribute__((ext_vector_type(4)));
+
+template <int M, typename T>
+constexpr bool use_mfma() { return M >= kMfmaMinM && sizeof(T) == 4; }
+
+template <int M, int NT_> struct EmSharedMf {
+    static constexpr int NTH = NT_;
+    using Tb = float;
+    using T2 = float2;
+    static constexpr int MM = M * M;
+    static constexpr int NV = 2 * M;  // per-thread diagonal terms
+    static constexpr int CH = NV;
+    static constexpr int G = NT_ / 32;
+    static constexpr int NW = NT_ / 64;
+    double2 P[MM];
+    double2 Pn[MM];
+    T2 Pt[MM];
+    float lamT[M];
+    double lam[M], lamN[M];
+    double logdet;
+    int flag;
+    int bad;
+    double2 S[2][MM];
+    double fin[NV];
+    double red2[G * CH];
+    double LL[NW];
+    double Gm[2][256];  // W_j W_j^T summed over the waves (FP64)
+    union {
+        float stg[NW][2 * kStgSrc];  // per wave: W_1 then W_2 (layout above)
+        struct {
+            float red[NT_ * (CH + 1)];
+            float blk[NW][2][256];
+        } r;
+    } u;
+    GevdScratch ws;
+};
+
+// Zero rows 2M..15 of this lane's staged frame (the padding of W_j to 16 rows);
+// needed at every pass since the end-of-pass reduction reuses the area.
+template <int M>
+__device__ __forceinline__ void mf_zero_pad(float* __restrict__ stg, int lane) {
+    const int col = (lane & 3) * 16 + (lane >> 2);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 2 * M; r < 16; ++r) stg[j * kStgSrc + r * kStgRow + col] = 0.0f;
+}
+
+// The bin with u_1, u_2 staged as this lane's column of W_1, W_2 and the
+// diagonal terms c_i / v_j' summed per thread (cd); then G_j += W_j W_j^T over
+// the wave's 64 frames. Must be called by all 64 lanes (wave-uniform control).
+template <int M>
+__device__ __forceinline__ void em_bin_mf(const float (&yr)[M], const float (&yi)[M], float a1, float a2,
+                                          const float (&lm)[M], const float2* Pt, bool ok, double& llacc,
+                                          float& nv1o, float& nv2o, bool& bad, float* __restrict__ stg,
+                                          float (&cd)[2 * M], f32x4 (&am)[2], int lane) {
+    float ytr[M], yti[M], e[M], r[M], w1, w2;
+    em_bin_front<M, float>(yr, yi, a1, a2, lm, Pt, ok, llacc, nv1o, nv2o, bad, ytr, yti, e, r, w1, w2);
+    const float iv1 = w1 * w1, iv2 = w2 * w2;
+    float* __restrict__ c1 = stg + (lane & 3) * 16 + (lane >> 2);
+    float* __restrict__ c2 = c1 + kStgSrc;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const float g1 = a1 * lm[i] * r[i];
+        const float g2 = a2 * r[i];
+        const float c = g1 * a2;
+        const float s1i = g1 * w1, s2i = g2 * w2;
+        c1[i * kStgRow] = s1i * ytr[i];
+        c1[(M + i) * kStgRow] = s1i * yti[i];
+        c2[i * kStgRow] = s2i * ytr[i];
+        c2[(M + i) * kStgRow] = s2i * yti[i];
+        cd[i] = fma(c, iv1, cd[i]);
+        cd[M + i] = fma(c, iv2, cd[M + i]);
+    }
+    wave_lds_sync();
+    // this lane's operand for step kb is W_j(lane % 16, 4 kb + lane / 16)
+    const float4* __restrict__ src = reinterpret_cast<const float4*>(stg + (lane & 15) * kStgRow + (lane >> 4) * 16);
+    float4 a[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[j][q] = src[j * (kStgSrc / 4) + q];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            am[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j][q].x, a[j][q].x, am[j], 0, 0, 0);
+            am[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j][q].y, a[j][q].y, am[j], 0, 0, 0);
+            am[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j][q].z, a[j][q].z, am[j], 0, 0, 0);
+            am[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j][q].w, a[j][q].w, am[j], 0, 0, 0);
+        }
+    }
+    wave_lds_sync();
+}
+
+// End-of-pass reduction for the MFMA scheme: per-wave log-likelihood, the
+// per-thread diagonal terms (two fixed-order stages) and the per-wave Gram
+// blocks (summed over the waves in FP64, fixed order) into S~_j = sums / N.
+template <int M, int NT_>
+__device__ __forceinline__ void wg_reduce_mf(EmSharedMf<M, NT_>& sh, const float (&cd)[2 * M], const f32x4 (&am)[2],
+                                             double llacc, int nf, int tid) {
+    constexpr int MM = M * M, CH = 2 * M, G = NT_ / 32, NW = NT_ / 64;
+    const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) llacc += __shfl_xor(llacc, off, 64);
+    if (lane == 0) sh.LL[w] = llacc;
+    __syncthreads();  // every wave is done with its staging rows (shared with red, blk)
+#pragma unroll
+    for (int c = 0; c < CH; ++c) sh.u.r.red[tid * (CH + 1) + c] = cd[c];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh.u.r.blk[w][j][(4 * (lane >> 4) + q) * 16 + (lane & 15)] = am[j][q];
+    __syncthreads();
+    for (int task = tid; task < CH * G; task += NT_) {
+        const int c = task % CH, g = task / CH;
+        double s = 0.0;
+#pragma unroll 8
+        for (int rr = 0; rr < 32; ++rr) s += (double)sh.u.r.red[(g * 32 + rr) * (CH + 1) + c];
+        sh.red2[g * CH + c] = s;
+    }
+    for (int e = tid; e < 512; e += NT_) {
+        const int j = e >> 8, ent = e & 255;
+        double s = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) s += (double)sh.u.r.blk[ww][j][ent];
+        sh.Gm[j][ent] = s;
+    }
+    __syncthreads();
+    if (tid < CH) {
+        double s = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) s += sh.red2[g * CH + tid];
+        sh.fin[tid] = s;
+    }
+    __syncthreads();
+    if (tid < 2 * MM) {
+        const int j = tid / MM, ent = tid % MM, i = ent / M, q = ent % M;
+        const int a = i < q ? i : q, b = i < q ? q : i;  // upper triangle, mirrored below it
+        const double* Gj = sh.Gm[j];
+        const double invn = 1.0 / (double)nf;
+        double re = Gj[a * 16 + b] + Gj[(M + a) * 16 + (M + b)];
+        double im = Gj[(M + a) * 16 + b] - Gj[a * 16 + (M + b)];
+        if (a == b) {
+            re += sh.fin[j * M + a];
+            im = 0.0;
+        }
+        sh.S[j][ent] = make_double2(re * invn, (i <= q ? im : -im) * invn);
+    }
+    __syncthreads();
+}
+
+// After the reduction of a pass (S~_j in sh.S, per-wave log-likelihood in
+// sh.LL): record LL(theta^(it)), then the FP64 GEVD of (S~1, S~2) and the
+// basis update P <- P Q, Lambda <- Sigma (eqs. GEVDeff5, updatePeff,
+// updateLambdaeff) on wave 0. Returns true when the caller must stop
+// iterating: an evaluation-only pass, a problem frozen on entry, or a failure
+// that froze it now (it then keeps theta^(it), whose log-likelihood stands
+// for the later iterations).
+template <int M, typename Sh>
+__device__ __forceinline__ bool em_update(Sh& sh, int it, int iters, bool frozen_at_entry, int nf,
                                           double* __restrict__ ll, int64_t ll_stride, int pid, double eps2,
                                           int tid) {
-    constexpr int MM = M * M, NW = NT_ / 64;
+    constexpr int MM = M * M, NW = Sh::NW;
     const int ll_count = iters > 0 ? iters : 1;
-    if (bad) sh.bad = 1;
-    wg_reduce_sums<M>(sh, acc, llacc, nf, tid);
     if (tid < 64) {
         const bool last = (iters == 0) || frozen_at_entry;
         double tot = 0.0;
@@ -231,26 +416,93 @@ __device__ __forceinline__ bool em_finish(EmShared<M, T, NT_>& sh, const T (&acc
     return iters == 0 || frozen_at_entry || (sh.flag & kFreezeMask);
 }
 
+
+// End of one pass over the frames (per-thread accumulators): FP64 reduction
+// of the sums and of the log-likelihood over the workgroup (fixed order),
+// S~_j = sums / N, then em_update.
+template <int M, typename T, int NT_>
+__device__ __forceinline__ bool em_finish(EmShared<M, T, NT_>& sh, const T (&acc)[2 * M * M], double llacc,
+                                          bool bad, int it, int iters, bool frozen_at_entry, int nf,
+                                          double* __restrict__ ll, int64_t ll_stride, int pid, double eps2,
+                                          int tid) {
+    if (bad) sh.bad = 1;
+    wg_reduce_sums<M>(sh, acc, llacc, nf, tid);
+    return em_update<M>(sh, it, iters, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid);
+}
+
+// Per-pass accumulation of one thread: per-thread sums (em_bin, em_finish)
+// or the MFMA scheme (em_bin_mf, wg_reduce_mf), selected by
+// use_mfma<M, T>(), with the matching LDS layout EmSh.
+template <int M, typename T, int NT>
+using EmSh = typename std::conditional<use_mfma<M, T>(), EmSharedMf<M, NT>, EmShared<M, T, NT>>::type;
+
+template <int M, typename T, bool MF> struct PassAcc;
+
+template <int M, typename T> struct PassAcc<M, T, false> {
+    T acc[2 * M * M];
+    template <typename Sh>
+    __device__ __forceinline__ void init(Sh&, int) {
+#pragma unroll
+        for (int i = 0; i < 2 * M * M; ++i) acc[i] = T(0);
+    }
+    template <typename Sh>
+    __device__ __forceinline__ void bin(Sh& sh, const T (&yr)[M], const T (&yi)[M], T a1, T a2, const T (&lm)[M],
+                                        bool ok, double& llacc, T& n1, T& n2, bool& bad, int) {
+        em_bin<M, T>(yr, yi, a1, a2, lm, sh.Pt, ok, acc, llacc, n1, n2, bad);
+    }
+    template <typename Sh>
+    __device__ __forceinline__ bool finish(Sh& sh, double llacc, bool bad, int it, int iters, bool frozen, int nf,
+                                           double* __restrict__ ll, int64_t ll_stride, int pid, double eps2, int tid) {
+        return em_finish<M, T>(sh, acc, llacc, bad, it, iters, frozen, nf, ll, ll_stride, pid, eps2, tid);
+    }
+};
+
+template <int M> struct PassAcc<M, float, true> {
+    float cd[2 * M];
+    f32x4 am[2];
+    template <typename Sh>
+    __device__ __forceinline__ void init(Sh& sh, int tid) {
+#pragma unroll
+        for (int i = 0; i < 2 * M; ++i) cd[i] = 0.0f;
+        am[0] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        am[1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        mf_zero_pad<M>(sh.u.stg[tid >> 6], tid & 63);
+    }
+    template <typename Sh>
+    __device__ __forceinline__ void bin(Sh& sh, const float (&yr)[M], const float (&yi)[M], float a1, float a2,
+                                        const float (&lm)[M], bool ok, double& llacc, float& n1, float& n2, bool& bad,
+                                        int tid) {
+        em_bin_mf<M>(yr, yi, a1, a2, lm, sh.Pt, ok, llacc, n1, n2, bad, sh.u.stg[tid >> 6], cd, am, tid & 63);
+    }
+    template <typename Sh>
+    __device__ __forceinline__ bool finish(Sh& sh, double llacc, bool bad, int it, int iters, bool frozen, int nf,
+                                           double* __restrict__ ll, int64_t ll_stride, int pid, double eps2, int tid) {
+        if (bad) sh.bad = 1;
+        wg_reduce_mf<M, Sh::NTH>(sh, cd, am, llacc, nf, tid);
+        return em_update<M>(sh, it, iters, frozen, nf, ll, ll_stride, pid, eps2, tid);
+    }
+};
+
 // ============================================================== EM kernel, frames resident
 // One workgroup owns one (mixture, frequency) EM problem for all iterations of
 // a call; each thread keeps FPT frames of y and v in registers, so y(n,f) and
 // v_j(n,f) cross HBM once per call, not once per iteration.
 template <int M, typename T, int FPT, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void em_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(M <= 4 ? 3 : 2))) void em_kernel(
     const EmProblem* __restrict__ probs, const typename Vec2<T>::type* __restrict__ y,
     T* __restrict__ v, double2* __restrict__ Pg, double* __restrict__ lamg,
     double* __restrict__ logdetg, int* __restrict__ flagsg, double* __restrict__ ll,
     int64_t ll_stride, int iters, double eps2) {
     using T2 = typename Vec2<T>::type;
-    constexpr int NV = 2 * M * M;
-    __shared__ EmShared<M, T, NT> sh;
+    constexpr bool MF = use_mfma<M, T>();
+    __shared__ EmSh<M, T, NT> sh;
 
     const EmProblem pr = probs[blockIdx.x];
     const int tid = threadIdx.x;
     const int nf = pr.n;
     const int npad = pr.npad;
     const int pid = pr.pid;
-    em_load_state(sh, Pg, lamg, logdetg, flagsg, pid, tid);
+    em_load_state<M>(sh, Pg, lamg, logdetg, flagsg, pid, tid);
 
     T yr[FPT][M], yi[FPT][M], v1[FPT], v2[FPT];
     const T2* __restrict__ yb = y + pr.y_off;
@@ -274,14 +526,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void em
     const int passes = (iters > 0 && !frozen_at_entry) ? iters : 1;
 
     for (int it = 0; it < passes; ++it) {
-        em_prepare(sh, tid);
+        em_prepare<M>(sh, tid);
         __syncthreads();
         T lm[M];
 #pragma unroll
         for (int a = 0; a < M; ++a) lm[a] = sh.lamT[a];
-        T acc[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] = T(0);
+        PassAcc<M, T, MF> pa;
+        pa.init(sh, tid);
         double llacc = 0.0;
         T v1n[FPT], v2n[FPT];
         bool bad = false;
@@ -296,11 +547,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void em
             // enough for three workgroups per CU.
             __asm__ volatile("" ::: "memory");
             __builtin_amdgcn_sched_barrier(0);
-            em_bin<M, T>(yr[k], yi[k], v1[k], v2[k], lm, sh.Pt, (k * NT + tid) < nf, acc, llacc, v1n[k],
-                         v2n[k], bad);
+            pa.bin(sh, yr[k], yi[k], v1[k], v2[k], lm, (k * NT + tid) < nf, llacc, v1n[k], v2n[k], bad, tid);
         }
-        if (em_finish<M, T>(sh, acc, llacc, bad, it, iters, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid))
-            break;
+        if (pa.finish(sh, llacc, bad, it, iters, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid)) break;
 #pragma unroll
         for (int k = 0; k < FPT; ++k) {
             v1[k] = v1n[k];
@@ -317,7 +566,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void em
                 v[pr.v_off + pr.v2_off + n] = v2[k];
             }
         }
-        em_store_state(sh, Pg, lamg, logdetg, flagsg, pid, tid);
+        em_store_state<M>(sh, Pg, lamg, logdetg, flagsg, pid, tid);
     }
 }
 
@@ -329,21 +578,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void em
 // that freezes keeps its last complete iterate. On exit the committed powers
 // are in the first buffer.
 template <int M, typename T, int FPT, int NT>
-__global__ __launch_bounds__(NT) void em_stream_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void em_stream_kernel(
     const EmProblem* __restrict__ probs, const typename Vec2<T>::type* __restrict__ y,
     T* __restrict__ v, int64_t v_alt, double2* __restrict__ Pg, double* __restrict__ lamg,
     double* __restrict__ logdetg, int* __restrict__ flagsg, double* __restrict__ ll,
     int64_t ll_stride, int iters, double eps2) {
     using T2 = typename Vec2<T>::type;
-    constexpr int NV = 2 * M * M;
-    __shared__ EmShared<M, T, NT> sh;
+    constexpr bool MF = use_mfma<M, T>();
+    __shared__ EmSh<M, T, NT> sh;
 
     const EmProblem pr = probs[blockIdx.x];
     const int tid = threadIdx.x;
     const int nf = pr.n;
     const int npad = pr.npad;
     const int pid = pr.pid;
-    em_load_state(sh, Pg, lamg, logdetg, flagsg, pid, tid);
+    em_load_state<M>(sh, Pg, lamg, logdetg, flagsg, pid, tid);
     __syncthreads();
     const bool frozen_at_entry = (sh.flag & kFreezeMask) != 0;
     const int passes = (iters > 0 && !frozen_at_entry) ? iters : 1;
@@ -352,14 +601,13 @@ __global__ __launch_bounds__(NT) void em_stream_kernel(
     int cur = 0;
 
     for (int it = 0; it < passes; ++it) {
-        em_prepare(sh, tid);
+        em_prepare<M>(sh, tid);
         __syncthreads();
         T lm[M];
 #pragma unroll
         for (int a = 0; a < M; ++a) lm[a] = sh.lamT[a];
-        T acc[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] = T(0);
+        PassAcc<M, T, MF> pa;
+        pa.init(sh, tid);
         double llacc = 0.0;
         bool bad = false;
         const T* __restrict__ vin = v + (cur ? v_alt : 0) + pr.v_off;
@@ -386,15 +634,14 @@ __global__ __launch_bounds__(NT) void em_stream_kernel(
                 const int n = base + k * NT + tid;
                 const bool ok = n < nf;
                 T n1 = a1[k], n2 = a2[k];
-                em_bin<M, T>(yr[k], yi[k], a1[k], a2[k], lm, sh.Pt, ok, acc, llacc, n1, n2, bad);
+                pa.bin(sh, yr[k], yi[k], a1[k], a2[k], lm, ok, llacc, n1, n2, bad, tid);
                 if (ok && write_v) {
                     vout[n] = n1;
                     vout[pr.v2_off + n] = n2;
                 }
             }
         }
-        if (em_finish<M, T>(sh, acc, llacc, bad, it, iters, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid))
-            break;
+        if (pa.finish(sh, llacc, bad, it, iters, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid)) break;
         cur ^= 1;
     }
 
@@ -405,7 +652,7 @@ __global__ __launch_bounds__(NT) void em_stream_kernel(
                 v[pr.v_off + pr.v2_off + n] = v[v_alt + pr.v_off + pr.v2_off + n];
             }
         }
-        em_store_state(sh, Pg, lamg, logdetg, flagsg, pid, tid);
+        em_store_state<M>(sh, Pg, lamg, logdetg, flagsg, pid, tid);
     }
 }
 

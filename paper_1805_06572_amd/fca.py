@@ -81,7 +81,7 @@ def lib() -> ctypes.CDLL:
         L.fca_gevd.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
         L.fca_timing.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.fca_launch_groups.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
-        L.fca_set_launch_shape.argtypes = [vp, i32, i32]
+        L.fca_set_launch_shape.argtypes = [vp, i32, i32, i32]
         L.fca_autotune.argtypes = [vp, i32]
         L.fca_graph_capture.argtypes = [vp, i32, i32, vp, vp, vp, vp]
         L.fca_graph_launch.argtypes = [vp, i32]
@@ -334,8 +334,8 @@ def fca_launch_groups(ctx: Ctx) -> list:
     return [{k: getattr(arr[i], k) for k, _ in fca_launch_group._fields_} for i in range(n.value)]
 
 
-def fca_set_launch_shape(ctx: Ctx, group: int, threads: int):
-    _check(lib().fca_set_launch_shape(ctx.handle, group, threads), ctx)
+def fca_set_launch_shape(ctx: Ctx, group: int, threads: int, streamed: bool = False):
+    _check(lib().fca_set_launch_shape(ctx.handle, group, threads, 1 if streamed else 0), ctx)
 
 
 def fca_autotune(ctx: Ctx, iters: int = 3):

@@ -69,6 +69,37 @@ def test_128_thread_shape_matches_oracle(fca):
         np.testing.assert_allclose(ll[k].cpu().numpy(), llo[:6].sum(1), rtol=1e-10)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_streamed_shape_for_every_group(fca, prec):
+    """Every group switched to the streaming kernel: FP64 matches the oracle,
+    FP32 matches the resident FP32 run within the float tolerance."""
+    P = fca.FCA_FP64 if prec == "fp64" else fca.FCA_FP32_BULK
+    mxs, ys = batch(dtype=np.complex128 if prec == "fp64" else np.complex64)
+    ctx = fca.fca_init_batch(ys, prec=P)
+    ref = fca.fca_init_batch(ys, prec=P)
+    try:
+        for g in range(len(fca.fca_launch_groups(ctx))):
+            fca.fca_set_launch_shape(ctx, g, 256, streamed=True)
+        assert all(info["frames_per_thread"] == 0 for info in fca.fca_launch_groups(ctx))
+        with pytest.raises(fca.FcaError):
+            fca.fca_set_launch_shape(ctx, 0, 128, streamed=True)
+        ll, R, v = fca.fca_em_step(ctx, 6, allow_flags=True)
+        llr, Rr, vr = fca.fca_em_step(ref, 6, allow_flags=True)
+    finally:
+        fca.fca_destroy(ctx)
+        fca.fca_destroy(ref)
+    if prec == "fp64":
+        for k, mx in enumerate(mxs):
+            S0, v0 = oracle.default_init(mx.y)
+            S, vo, llo, fl = oracle.em(mx.y, S0, v0, 6, threads=8)
+            assert rel(v[k].cpu().numpy(), vo, (-1,)).max() < 1e-9
+            assert rel(R[k].cpu().numpy(), S, (-2, -1)).max() < 1e-9
+            np.testing.assert_allclose(ll[k].cpu().numpy(), llo[:6].sum(1), rtol=1e-10)
+    else:
+        for k in range(len(ys)):
+            assert rel(v[k].double().cpu().numpy(), vr[k].double().cpu().numpy(), (-1,)).max() < 1e-4
+
+
 def test_autotune_restores_state_and_keeps_results(fca):
     mxs, ys = batch(dtype=np.complex64)
     a = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
