@@ -17,6 +17,7 @@
 // with both operands K-contiguous.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -37,19 +38,29 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7, far below the BF16
+// rounding the activations get): erf(a) = 1 - t (a1 + t (a2 + ... a5)) e^-a^2,
+// t = 1 / (1 + p a), a = |x|, odd extension.
+__device__ __forceinline__ float erf_as(float x) {
+    const float a = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
+    float q = fmaf(t, 1.061405429f, -1.453152027f);
+    q = fmaf(t, q, 1.421413741f);
+    q = fmaf(t, q, -0.284496736f);
+    q = fmaf(t, q, 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f);
+    return copysignf(fmaf(-t * q, e, 1.0f), x);
+}
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+    return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) +
+           x * 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.5f * x * x * 1.4426950408889634f);
 }
 
 // ------------------------------------------------------------------ features
-__global__ void mlp_features_kernel(const float2* __restrict__ y, const float* __restrict__ fpos, int n, int M,
-                                    bf16* __restrict__ X, bf16* __restrict__ XT, int ldt) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n) return;
-    float feat[kKP];
+// Features of one bin (zero-padded to kKP).
+__device__ __forceinline__ void bin_features(const float2* __restrict__ yb, int M, float fpos, float (&feat)[kKP]) {
     for (int j = 0; j < kKP; ++j) feat[j] = 0.0f;
-    const float2* yb = y + (int64_t)b * M;
     const float2 y0 = yb[0];
     const float p0 = y0.x * y0.x + y0.y * y0.y;
     for (int m = 0; m < M; ++m) {
@@ -65,7 +76,15 @@ __global__ void mlp_features_kernel(const float2* __restrict__ y, const float* _
             feat[M + 2 * (m - 1) + 1] = okd ? ci / den : 0.0f;
         }
     }
-    feat[3 * M - 2] = fpos[b];
+    feat[3 * M - 2] = fpos;
+}
+
+__global__ void mlp_features_kernel(const float2* __restrict__ y, const float* __restrict__ fpos, int n, int M,
+                                    bf16* __restrict__ X, bf16* __restrict__ XT, int ldt) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    float feat[kKP];
+    bin_features(y + (int64_t)b * M, M, fpos[b], feat);
     for (int j = 0; j < kKP; ++j) {
         const bf16 h = (bf16)feat[j];
         X[(int64_t)b * kKP + j] = h;
@@ -245,31 +264,153 @@ __global__ void mlp_weight_copy_kernel(const float* __restrict__ W, int rows, in
     WTb[(int64_t)c * rows + r] = h;
 }
 
-// ------------------------------------------------------------------ learned start of the powers
-// bins of y[F][N][M] (contiguous) in order f * N + n; v0[j][f][n].
-__global__ void mlp_gather_bins_kernel(const float2* __restrict__ y, int F, int N, int M, int64_t first, int count,
-                                       float2* __restrict__ ybins, float* __restrict__ fpos) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const int64_t bin = first + i;
-    const int f = (int)(bin / N);
-    for (int m = 0; m < M; ++m) ybins[(int64_t)i * M + m] = y[bin * M + m];
-    fpos[i] = F > 1 ? (float)f / (float)(F - 1) : 0.0f;
+// ------------------------------------------------------------------ fused inference (learned start)
+// One workgroup (4 waves) per tile of kTile bins of y[F][N][M] in the order
+// f N + n: features -> three hidden layers (BF16 MFMA 16x16x32, FP32
+// accumulation) -> output layer -> sigmoid -> v0[j][f][n]. The activations of
+// the tile stay in LDS; the weights are read from L2. Wave w owns the output
+// columns 64 w .. 64 w + 63 of every layer for all rows of the tile (8 x 4
+// MFMA tiles). Same arithmetic as the training forward (features, bias,
+// GELU, BF16 rounding of the hidden activations, FP32 output layer) up to
+// the order of the output-layer sum.
+constexpr int kRT = 4;            // row tiles of 16 per wave
+constexpr int kTile = 16 * kRT;   // bins per workgroup
+constexpr int kXP = kKP + 8;      // LDS row pitch of the features (bf16)
+constexpr int kHP = kHidden + 8;  // LDS row pitch of the hidden activations (bf16)
+
+struct InferShared {
+    bf16 X[kTile * kXP];
+    bf16 H[kTile * kHP];
+    float zp[4][kTile];
+    float sv[kTile];
+};
+
+// out^T = W A^T for this wave's 64 output columns and the tile's 128 rows:
+// acc[ct][rt] is the 16 x 16 block (columns c0 + 16 ct.., rows 16 rt..), lane
+// l holding columns c0 + 16 ct + 4 (l / 16) + q, q = 0..3, of row 16 rt + l % 16
+// (the MFMA A operand is W, the B operand the activations, both K-contiguous).
+template <int K, int LDA>
+__device__ __forceinline__ void infer_layer(const bf16* __restrict__ A, const bf16* __restrict__ W, int c0, int lane,
+                                            f32x4 (&acc)[4][kRT]) {
+    const int li = lane & 15, lk = (lane >> 4) * 8;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int rt = 0; rt < kRT; ++rt) acc[ct][rt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 wv[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) wv[ct] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(c0 + ct * 16 + li) * K + k0 + lk);
+#pragma unroll
+        for (int rt = 0; rt < kRT; ++rt) {
+            const bf16x8 hv = *reinterpret_cast<const bf16x8*>(A + (rt * 16 + li) * LDA + k0 + lk);
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[ct], hv, acc[ct][rt], 0, 0, 0);
+        }
+    }
 }
 
-__global__ void mlp_powers_kernel(const float2* __restrict__ ybins, const float* __restrict__ r, int M, int64_t first,
-                                  int count, int64_t FN, float* __restrict__ v0) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    float p = 0.0f;
-    for (int m = 0; m < M; ++m) {
-        const float2 ym = ybins[(int64_t)i * M + m];
-        p += ym.x * ym.x + ym.y * ym.y;
+// H = bf16(GELU(acc + bias)) for this wave's columns: four consecutive
+// columns of one row per lane and block (one 8-byte LDS write)
+__device__ __forceinline__ void infer_store_hidden(const f32x4 (&acc)[4][kRT], const float* __restrict__ bias, bf16* H,
+                                                   int c0, int lane) {
+    const int li = lane & 15, cq = (lane >> 4) * 4;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int col = c0 + ct * 16 + cq;
+        const float4 b = *reinterpret_cast<const float4*>(bias + col);
+#pragma unroll
+        for (int rt = 0; rt < kRT; ++rt) {
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            const f32x4 v = acc[ct][rt];
+            const bf16x4 h = (bf16x4){(bf16)gelu(v[0] + b.x), (bf16)gelu(v[1] + b.y), (bf16)gelu(v[2] + b.z),
+                                      (bf16)gelu(v[3] + b.w)};
+            *reinterpret_cast<bf16x4*>(H + (rt * 16 + li) * kHP + col) = h;
+        }
     }
-    const float s = fmaxf(2.0f * p / (float)M, 1e-30f);
-    const float ri = fminf(fmaxf(r[i], 1e-6f), 1.0f - 1e-6f);
-    v0[first + i] = ri * s;
-    v0[FN + first + i] = (1.0f - ri) * s;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void mlp_infer_kernel(const float2* __restrict__ y, int F, int N, int M,
+                                                        const bf16* __restrict__ W0, const bf16* __restrict__ W1,
+                                                        const bf16* __restrict__ W2, const float* __restrict__ bias0,
+                                                        const float* __restrict__ bias1,
+                                                        const float* __restrict__ bias2, const float* __restrict__ w4,
+                                                        const float* __restrict__ b4, float* __restrict__ v0) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    InferShared& sh = *reinterpret_cast<InferShared*>(smem);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t FN = (int64_t)F * N;
+    const int64_t r0 = (int64_t)blockIdx.x * kTile;
+    if (tid < kTile) {
+        const int64_t bin = r0 + tid;
+        float feat[kKP];
+        float s = 0.0f;
+        if (bin < FN) {
+            const int f = (int)(bin / N);
+            const float2* yb = y + bin * M;
+            bin_features(yb, M, F > 1 ? (float)f / (float)(F - 1) : 0.0f, feat);
+            float p = 0.0f;
+            for (int m = 0; m < M; ++m) p += yb[m].x * yb[m].x + yb[m].y * yb[m].y;
+            s = fmaxf(2.0f * p / (float)M, 1e-30f);
+        } else {
+            for (int j = 0; j < kKP; ++j) feat[j] = 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < kKP; ++j) sh.X[tid * kXP + j] = (bf16)feat[j];
+        sh.sv[tid] = s;
+    }
+    __syncthreads();
+    const int c0 = w * 64;
+    f32x4 acc[4][kRT];
+    infer_layer<kKP, kXP>(sh.X, W0, c0, lane, acc);
+    infer_store_hidden(acc, bias0, sh.H, c0, lane);
+    __syncthreads();
+    infer_layer<kHidden, kHP>(sh.H, W1, c0, lane, acc);
+    __syncthreads();  // every wave has read H before it is overwritten
+    infer_store_hidden(acc, bias1, sh.H, c0, lane);
+    __syncthreads();
+    infer_layer<kHidden, kHP>(sh.H, W2, c0, lane, acc);
+    // output layer: z = sum_c GELU(pre3_c) w4_c, this wave's 64 columns per row
+    const int li = lane & 15, cq = (lane >> 4) * 4;
+    float part[kRT];
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt) part[rt] = 0.0f;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int col = c0 + ct * 16 + cq;
+        const float4 b = *reinterpret_cast<const float4*>(bias2 + col);
+        const float4 wc = *reinterpret_cast<const float4*>(w4 + col);
+#pragma unroll
+        for (int rt = 0; rt < kRT; ++rt) {
+            const f32x4 v = acc[ct][rt];
+            float x = part[rt];
+            x = fmaf(gelu(v[0] + b.x), wc.x, x);
+            x = fmaf(gelu(v[1] + b.y), wc.y, x);
+            x = fmaf(gelu(v[2] + b.z), wc.z, x);
+            x = fmaf(gelu(v[3] + b.w), wc.w, x);
+            part[rt] = x;
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt) {
+        float x = part[rt];
+        x += __shfl_xor(x, 16, 64);
+        x += __shfl_xor(x, 32, 64);
+        if (lane < 16) sh.zp[w][rt * 16 + li] = x;
+    }
+    __syncthreads();
+    if (tid < kTile) {
+        const int64_t bin = r0 + tid;
+        if (bin < FN) {
+            const float z = ((sh.zp[0][tid] + sh.zp[1][tid]) + (sh.zp[2][tid] + sh.zp[3][tid])) + b4[0];
+            const float r = 1.0f / (1.0f + expf(-z));
+            const float ri = fminf(fmaxf(r, 1e-6f), 1.0f - 1e-6f);
+            const float s = sh.sv[tid];
+            v0[bin] = ri * s;
+            v0[FN + bin] = (1.0f - ri) * s;
+        }
+    }
 }
 
 }  // namespace
@@ -290,8 +431,6 @@ struct fca_mlp {
     bf16 *D = nullptr, *DT = nullptr, *D2 = nullptr, *D2T = nullptr;
     float *dz = nullptr, *r = nullptr;
     double* loss_terms = nullptr;
-    float2* ybins = nullptr;
-    float* fpos = nullptr;
     int64_t step = 0;
     std::string err;
 };
@@ -312,7 +451,7 @@ bool mlp_alloc(P** p, size_t bytes) {
 
 void mlp_free(fca_mlp* m) {
     void* ptrs[] = {m->p, m->g, m->m1, m->m2, m->X, m->XT, m->D, m->DT, m->D2, m->D2T, m->dz, m->r,
-                    m->loss_terms, m->ybins, m->fpos};
+                    m->loss_terms};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (int l = 0; l < kLayers; ++l) {
@@ -342,7 +481,7 @@ hipError_t gemm(hipStream_t s, const GemmArgs& a) {
     return hipGetLastError();
 }
 
-// forward of n <= max_batch bins already gathered in ybins/fpos (or given)
+// forward of n <= max_batch bins (features, three hidden layers)
 hipError_t forward(fca_mlp* m, const float2* y, const float* fpos, int n) {
     mlp_features_kernel<<<(n + 255) / 256, 256, 0, m->stream>>>(y, fpos, n, m->M, m->X, m->XT, m->ldt);
     const bf16* in = m->X;
@@ -417,8 +556,7 @@ fca_status fca_mlp_create(int32_t M, uint64_t seed, int32_t max_batch, void* str
          mlp_alloc(&m->D, (size_t)max_batch * kHidden * 2) && mlp_alloc(&m->DT, (size_t)max_batch * kHidden * 2) &&
          mlp_alloc(&m->D2, (size_t)max_batch * kHidden * 2) && mlp_alloc(&m->D2T, (size_t)max_batch * kHidden * 2) &&
          mlp_alloc(&m->dz, (size_t)max_batch * 4) && mlp_alloc(&m->r, (size_t)max_batch * 4) &&
-         mlp_alloc(&m->loss_terms, (size_t)max_batch * 8) && mlp_alloc(&m->ybins, (size_t)max_batch * M * 8) &&
-         mlp_alloc(&m->fpos, (size_t)max_batch * 4);
+         mlp_alloc(&m->loss_terms, (size_t)max_batch * 8);
     if (!ok) {
         mlp_free(m);
         delete m;
@@ -570,17 +708,18 @@ fca_status fca_mlp_init_powers(fca_mlp* m, const float* y, int32_t F, int32_t N,
     if (!m || !y || !v0_out || F < 1 || N < 1) return FCA_E_ARG;
     const hipStream_t s = m->stream;
     const int64_t FN = (int64_t)F * N;
-    for (int64_t first = 0; first < FN; first += m->max_batch) {
-        const int cnt = (int)std::min<int64_t>(m->max_batch, FN - first);
-        mlp_gather_bins_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(reinterpret_cast<const float2*>(y), F, N, m->M, first,
-                                                                cnt, m->ybins, m->fpos);
-        MLP_HIP(m, hipGetLastError());
-        MLP_HIP(m, forward(m, m->ybins, m->fpos, cnt));
-        mlp_out_kernel<<<(cnt + 3) / 4, 256, 0, s>>>(m->pre[kLayers - 1], m->p + m->off_W[kLayers],
-                                                    m->p + m->off_b[kLayers], cnt, m->r, nullptr, nullptr, nullptr);
-        mlp_powers_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(m->ybins, m->r, m->M, first, cnt, FN, v0_out);
-        MLP_HIP(m, hipGetLastError());
+    const int64_t tiles = (FN + kTile - 1) / kTile;
+    if (tiles > INT32_MAX) {
+        m->err = "fca_mlp_init_powers: too many bins";
+        return FCA_E_ARG;
     }
+    static_assert(sizeof(InferShared) <= 160 * 1024, "LDS of the fused inference kernel");
+    MLP_HIP(m, hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_infer_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(InferShared)));
+    mlp_infer_kernel<<<(unsigned)tiles, 256, sizeof(InferShared), s>>>(
+        reinterpret_cast<const float2*>(y), F, N, m->M, m->Wb[0], m->Wb[1], m->Wb[2], m->p + m->off_b[0],
+        m->p + m->off_b[1], m->p + m->off_b[2], m->p + m->off_W[kLayers], m->p + m->off_b[kLayers], v0_out);
+    MLP_HIP(m, hipGetLastError());
     MLP_HIP(m, hipStreamSynchronize(s));
     return FCA_OK;
 }

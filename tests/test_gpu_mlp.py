@@ -131,3 +131,26 @@ def test_batched_start_choice_and_per_mixture_stop(fca):
         finally:
             fca.fca_destroy(lone)
         np.testing.assert_array_equal(np.asarray(hist[k]), ll.cpu().numpy()[0])
+
+
+@pytest.mark.parametrize("M,F,N", [(4, 33, 300), (2, 5, 61), (8, 17, 130)])
+def test_fused_learned_start_matches_forward_and_reference(fca, M, F, N):
+    """fca_mlp_init_powers (one fused kernel per mixture, tiles of 128 bins
+    with a ragged tail) against the training-path forward on the same bins
+    (same BF16 GEMMs; only the output-layer sum order differs) and against
+    the FP64 reference network."""
+    net = fca.Mlp(M, seed=7, max_batch=4096)
+    mx = synth.array_mixture(M, F, N, seed=300 + M, complex64=True)
+    y = torch.from_numpy(mx.y).cuda()
+    v0 = fca.fca_mlp_init_powers(net, y).cpu().numpy().astype(np.float64)
+    ybins = mx.y.reshape(F * N, M)
+    fpos = np.repeat(np.arange(F, dtype=np.float32) / max(F - 1, 1), N)
+    s = 2 * (np.abs(ybins.astype(np.complex128)) ** 2).sum(-1) / M
+    np.testing.assert_allclose((v0[0] + v0[1]).reshape(-1), s, rtol=1e-5)
+    r_gpu = v0[0].reshape(-1) / (v0[0] + v0[1]).reshape(-1)
+    r_fwd = np.concatenate([fca.fca_mlp_forward(net, ybins[i:i + 4096], fpos[i:i + 4096]).cpu().numpy()
+                            for i in range(0, F * N, 4096)]).astype(np.float64)
+    np.testing.assert_allclose(r_gpu, np.clip(r_fwd, 1e-6, 1 - 1e-6), atol=2e-5)
+    p = ref.bf16_round(fca.fca_mlp_get_params(net))
+    want, _ = ref.forward(p, ref.features(ybins, fpos))
+    np.testing.assert_allclose(r_gpu, want, atol=2e-2)
