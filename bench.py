@@ -36,7 +36,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "em_kernel_array_m4_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1805_06572_amd", "csrc", f)
-                  for f in ("fca_kernels.hip", "fca_device.h", "fca_internal.h")]
+                  for f in ("fca_em.h", "fca_em_nt256.hip", "fca_device.h", "fca_internal.h")]
 
 
 def flop_per_update(M: int) -> int:

@@ -210,18 +210,32 @@ __global__ void mlp_out_back_kernel(const float* __restrict__ pre3, const float*
 }
 
 // grad of w4 and b4: dw4[o] = sum_b dz[b] GELU(pre3[b][o]); db4 = sum_b dz[b].
-// Fixed-order per-thread sums, one block.
-__global__ void mlp_out_grad_kernel(const float* __restrict__ pre3, const float* __restrict__ dz, int n,
-                                    float* __restrict__ gw4, float* __restrict__ gb4) {
+// Two fixed-order stages: block c sums rows [kOgRows c, kOgRows (c + 1)) into
+// part[c][0..256] (entry 256: the dz sum), then one block sums the blocks.
+constexpr int kOgRows = 64;
+__global__ void mlp_out_grad_part_kernel(const float* __restrict__ pre3, const float* __restrict__ dz, int n,
+                                         float* __restrict__ part) {
     const int o = threadIdx.x;  // 256 threads
-    float s = 0.0f;
-    for (int b = 0; b < n; ++b) s += dz[b] * gelu(pre3[(int64_t)b * kHidden + o]);
-    gw4[o] = s;
-    if (o == 0) {
-        float t = 0.0f;
-        for (int b = 0; b < n; ++b) t += dz[b];
-        gb4[0] = t;
+    const int b0 = blockIdx.x * kOgRows, b1 = min(n, b0 + kOgRows);
+    float s = 0.0f, t = 0.0f;
+    for (int b = b0; b < b1; ++b) {
+        s += dz[b] * gelu(pre3[(int64_t)b * kHidden + o]);
+        t += dz[b];
     }
+    part[(int64_t)blockIdx.x * (kHidden + 1) + o] = s;
+    if (o == 0) part[(int64_t)blockIdx.x * (kHidden + 1) + kHidden] = t;
+}
+
+__global__ void mlp_out_grad_sum_kernel(const float* __restrict__ part, int nblk, float* __restrict__ gw4,
+                                        float* __restrict__ gb4) {
+    const int o = threadIdx.x;  // 256 threads
+    float s = 0.0f, t = 0.0f;
+    for (int c = 0; c < nblk; ++c) {
+        s += part[(int64_t)c * (kHidden + 1) + o];
+        if (o == 0) t += part[(int64_t)c * (kHidden + 1) + kHidden];
+    }
+    gw4[o] = s;
+    if (o == 0) gb4[0] = t;
 }
 
 // bias gradients: gb[o] = sum_b d[o][b] from the transposed bf16 layout [256][ldt]
@@ -430,6 +444,7 @@ struct fca_mlp {
     bf16 *H[kLayers] = {}, *HT[kLayers] = {};
     bf16 *D = nullptr, *DT = nullptr, *D2 = nullptr, *D2T = nullptr;
     float *dz = nullptr, *r = nullptr;
+    float* ogpart = nullptr;  // [max_batch / 64 + 1][257] partial sums of the output-layer gradient
     double* loss_terms = nullptr;
     int64_t step = 0;
     std::string err;
@@ -450,7 +465,7 @@ bool mlp_alloc(P** p, size_t bytes) {
 }
 
 void mlp_free(fca_mlp* m) {
-    void* ptrs[] = {m->p, m->g, m->m1, m->m2, m->X, m->XT, m->D, m->DT, m->D2, m->D2T, m->dz, m->r,
+    void* ptrs[] = {m->p, m->g, m->m1, m->m2, m->X, m->XT, m->D, m->DT, m->D2, m->D2T, m->dz, m->r, m->ogpart,
                     m->loss_terms};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -556,6 +571,7 @@ fca_status fca_mlp_create(int32_t M, uint64_t seed, int32_t max_batch, void* str
          mlp_alloc(&m->D, (size_t)max_batch * kHidden * 2) && mlp_alloc(&m->DT, (size_t)max_batch * kHidden * 2) &&
          mlp_alloc(&m->D2, (size_t)max_batch * kHidden * 2) && mlp_alloc(&m->D2T, (size_t)max_batch * kHidden * 2) &&
          mlp_alloc(&m->dz, (size_t)max_batch * 4) && mlp_alloc(&m->r, (size_t)max_batch * 4) &&
+         mlp_alloc(&m->ogpart, (size_t)(max_batch / kOgRows + 1) * (kHidden + 1) * 4) &&
          mlp_alloc(&m->loss_terms, (size_t)max_batch * 8);
     if (!ok) {
         mlp_free(m);
@@ -640,8 +656,9 @@ fca_status fca_mlp_backward(fca_mlp* m, const float* y, const float* fpos, const
     const float* w4 = m->p + m->off_W[kLayers];
     mlp_out_kernel<<<(n + 3) / 4, 256, 0, s>>>(m->pre[kLayers - 1], w4, m->p + m->off_b[kLayers], n, m->r, target,
                                                m->dz, m->loss_terms);
-    mlp_out_grad_kernel<<<1, 256, 0, s>>>(m->pre[kLayers - 1], m->dz, n, m->g + m->off_W[kLayers],
-                                          m->g + m->off_b[kLayers]);
+    const int ogb = (n + kOgRows - 1) / kOgRows;
+    mlp_out_grad_part_kernel<<<ogb, 256, 0, s>>>(m->pre[kLayers - 1], m->dz, n, m->ogpart);
+    mlp_out_grad_sum_kernel<<<1, 256, 0, s>>>(m->ogpart, ogb, m->g + m->off_W[kLayers], m->g + m->off_b[kLayers]);
     mlp_out_back_kernel<<<(unsigned)(((int64_t)n * kHidden + 255) / 256), 256, 0, s>>>(m->pre[kLayers - 1], w4, m->dz,
                                                                                       n, m->D, m->DT, m->ldt);
     MLP_HIP(m, hipGetLastError());
