@@ -394,7 +394,7 @@ def run_time_to_target(args):
             if learned:
                 chosen, _, _ = learned_init.choose_starts(net, ctx, ys)
             t2 = time.perf_counter()
-            iters, hist = schedule.run_batch(ctx, 2 * L, 2, stop)
+            iters, hist = schedule.run_batch(ctx, 2 * L, (16, 8, 4, 2), stop)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
             fca.fca_destroy(ctx)
@@ -426,8 +426,8 @@ def run_time_to_target(args):
                     "batched_plain": sum(i is not None for i in bp_hits),
                     "batched_learned": sum(i is not None for i in bl_hits)},
         "learned_start_chosen": int(np.sum(chosen)), "stop_rule": "reached target, or LL rise below 1e-6 of "
-                                                                   "the total (converged elsewhere), checked every "
-                                                                   "2 iterations",
+                                                                   "the total (converged elsewhere), checked after "
+                                                                   "16, 24, 28 and then every 2 iterations",
         "mlp_train_s": train_s, "mlp_train_steps": args.train_steps,
         "mlp_heldout_bce": bce, "constant_predictor_bce": bce_const}
     return rec

@@ -12,10 +12,13 @@ import numpy as np
 from . import fca
 
 
-def run_batch(ctx, max_iters: int, chunk: int, stop):
+def run_batch(ctx, max_iters: int, chunk, stop):
     """Run until every mixture is stopped or has had max_iters iterations.
 
-    stop(b, ll) -> bool is asked after every chunk with the log-likelihood
+    chunk: iterations per fca_em_step call, an int or a sequence of ints whose
+    last entry repeats (e.g. (16, 8, 4, 2): few calls while no mixture can be
+    done yet, fine steps later). stop(b, ll) -> bool is asked after every
+    chunk with the log-likelihood
     history ll = [LL(theta^(0)), ..., LL(theta^(l-1))] of each still-active
     mixture b after l iterations (the parameters then stand at theta^(l), at
     least as likely by the monotonicity of EM).
@@ -24,8 +27,11 @@ def run_batch(ctx, max_iters: int, chunk: int, stop):
     hist = [[] for _ in range(B)]
     iters = np.zeros(B, dtype=np.int64)
     active = np.ones(B, dtype=bool)
+    chunks = [int(chunk)] if np.isscalar(chunk) else [int(c) for c in chunk]
+    call = 0
     while active.any():
-        k = int(min(chunk, max_iters - iters[active].max()))
+        k = int(min(chunks[min(call, len(chunks) - 1)], max_iters - iters[active].max()))
+        call += 1
         if k <= 0:
             break
         ll, _, _ = fca.fca_em_step(ctx, k, want_R=False, want_v=False, allow_flags=True)

@@ -154,3 +154,21 @@ def test_fused_learned_start_matches_forward_and_reference(fca, M, F, N):
     p = ref.bf16_round(fca.fca_mlp_get_params(net))
     want, _ = ref.forward(p, ref.features(ybins, fpos))
     np.testing.assert_allclose(r_gpu, want, atol=2e-2)
+
+
+def test_run_batch_chunk_schedule(fca):
+    """A chunk sequence gives the same histories as single steps; the stop
+    decision is taken at chunk boundaries only."""
+    from paper_1805_06572_amd import schedule
+    ys = [torch.from_numpy(synth.random_mixture(2, 4, 120 + 30 * k, 80 + k).y).cuda() for k in range(2)]
+    a = fca.fca_init_batch(ys, prec=fca.FCA_FP64)
+    b = fca.fca_init_batch(ys, prec=fca.FCA_FP64)
+    try:
+        it_a, h_a = schedule.run_batch(a, 11, (4, 2, 1), lambda k, ll: len(ll) >= 7 + k)
+        it_b, h_b = schedule.run_batch(b, 11, 1, lambda k, ll: False)
+    finally:
+        fca.fca_destroy(a)
+        fca.fca_destroy(b)
+    assert list(it_a) == [7, 8] and list(it_b) == [11, 11]
+    for k in range(2):
+        np.testing.assert_array_equal(h_a[k], h_b[k][:len(h_a[k])])
