@@ -67,6 +67,7 @@ struct fca_ctx {
     void* v_init = nullptr;
     double2* R_init = nullptr;
     double2* P = nullptr;
+    double2* Pinv = nullptr;  // P^-1 per problem (for the separation)
     double* lam = nullptr;
     double* logdet = nullptr;
     int* flags = nullptr;
@@ -159,7 +160,7 @@ fca_status dev_alloc(fca_ctx* c, P** p, size_t bytes) {
 }
 
 void free_ctx_memory(fca_ctx* c) {
-    void* dev[] = {c->y, c->v, c->v_init, c->R_init, c->P, c->lam, c->logdet, c->flags, c->ll,
+    void* dev[] = {c->y, c->v, c->v_init, c->R_init, c->P, c->Pinv, c->lam, c->logdet, c->flags, c->ll,
                    c->ll_tot, c->fsum, c->R_stage, c->probs, c->x_off, c->probs_act};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -387,6 +388,7 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     if (any_v0) FCA_TRY(dev_alloc(c, &c->v_init, v_tot * c->rsz));
     FCA_TRY(dev_alloc(c, &c->R_init, R_tot * sizeof(double2)));
     FCA_TRY(dev_alloc(c, &c->P, (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2)));
+    FCA_TRY(dev_alloc(c, &c->Pinv, (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2)));
     FCA_TRY(dev_alloc(c, &c->lam, (size_t)c->nprob * kMaxM * sizeof(double)));
     FCA_TRY(dev_alloc(c, &c->logdet, (size_t)c->nprob * sizeof(double)));
     FCA_TRY(dev_alloc(c, &c->flags, (size_t)c->nprob * sizeof(int)));
@@ -702,14 +704,16 @@ fca_status enqueue_ll_out(fca_ctx* c, int rows, int total, int done, double* log
     return FCA_OK;
 }
 
-// R_j(f) of every mixture into a device batch array (eq. recoverS).
-fca_status enqueue_R_out(fca_ctx* c, double2* R_dev, hipStream_t s) {
+// R_j(f) of every mixture into a device batch array (eq. recoverS); with
+// keep_pinv the inverses P^-1 are stored for a following separation.
+fca_status enqueue_R_out(fca_ctx* c, double2* R_dev, hipStream_t s, bool keep_pinv = false) {
     for (int b = 0; b < c->B; ++b) {
         const MixInfo& mi = c->mix[b];
         const int64_t mm = (int64_t)mi.M * mi.M;
         double2* dst = R_dev + mi.out_R;
-        FCA_HIP(c, launch_recover_R(mi.M, c->F, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM,
-                                    c->lam + (int64_t)mi.pid0 * kMaxM, dst, dst + (int64_t)c->F * mm, s));
+        FCA_HIP(c, launch_pinv(mi.M, c->F, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM, c->lam + (int64_t)mi.pid0 * kMaxM,
+                               keep_pinv ? c->Pinv + (int64_t)mi.pid0 * kMaxM * kMaxM : nullptr, dst,
+                               dst + (int64_t)c->F * mm, s));
     }
     return FCA_OK;
 }
@@ -724,10 +728,14 @@ fca_status enqueue_v_out(fca_ctx* c, void* v_out, hipStream_t s) {
     return FCA_OK;
 }
 
-fca_status enqueue_separate(fca_ctx* c, void* x_dev, hipStream_t s) {
+fca_status enqueue_separate(fca_ctx* c, void* x_dev, hipStream_t s, bool have_pinv = false) {
+    for (const MixInfo& mi : c->mix)
+        if (!have_pinv)
+            FCA_HIP(c, launch_pinv(mi.M, c->F, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM, c->lam + (int64_t)mi.pid0 * kMaxM,
+                               c->Pinv + (int64_t)mi.pid0 * kMaxM * kMaxM, nullptr, nullptr, s));
     for (const Group& g : c->groups)
         FCA_HIP(c, launch_separate(g.M, c->fp64, c->probs + g.first, g.count, g.max_n, c->y, c->v, c->P, c->lam,
-                                   x_dev, c->x_off + 2 * (int64_t)g.first, s));
+                                   c->Pinv, x_dev, c->x_off + 2 * (int64_t)g.first, s));
     return FCA_OK;
 }
 
@@ -836,10 +844,15 @@ fca_status fca_separate(fca_ctx* c, void* x_out) {
         if (st != FCA_OK) return st;
     }
     hipError_t e = hipSuccess;
-    for (const Group& g : c->groups) {
-        e = launch_separate(g.M, c->fp64, c->probs + g.first, g.count, g.max_n, c->y, c->v, c->P, c->lam, dst,
-                            c->x_off + 2 * (int64_t)g.first, s);
+    for (const MixInfo& mi : c->mix) {
+        e = launch_pinv(mi.M, c->F, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM, c->lam + (int64_t)mi.pid0 * kMaxM,
+                        c->Pinv + (int64_t)mi.pid0 * kMaxM * kMaxM, nullptr, nullptr, s);
         if (e != hipSuccess) break;
+    }
+    for (const Group& g : c->groups) {
+        if (e != hipSuccess) break;
+        e = launch_separate(g.M, c->fp64, c->probs + g.first, g.count, g.max_n, c->y, c->v, c->P, c->lam, c->Pinv,
+                            dst, c->x_off + 2 * (int64_t)g.first, s);
     }
     if (e == hipSuccess && !dev) e = hipMemcpyAsync(x_out, dst, total * c->esz, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1075,9 +1088,9 @@ fca_status fca_graph_capture(fca_ctx* c, int32_t iters, int32_t with_reset, doub
             done += chunk;
         } while (done < iters);
         fca_status r = FCA_OK;
-        if (R_out) r = enqueue_R_out(c, reinterpret_cast<double2*>(R_out), s);
+        if (R_out) r = enqueue_R_out(c, reinterpret_cast<double2*>(R_out), s, x_out != nullptr);
         if (r == FCA_OK && v_out) r = enqueue_v_out(c, v_out, s);
-        if (r == FCA_OK && x_out) r = enqueue_separate(c, x_out, s);
+        if (r == FCA_OK && x_out) r = enqueue_separate(c, x_out, s, R_out != nullptr);
         return r;
     };
     st = body();

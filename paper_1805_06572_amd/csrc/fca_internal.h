@@ -92,8 +92,15 @@ hipError_t launch_ll_reduce(const double* ll, int64_t ll_stride, int iters, int 
 hipError_t launch_recover_R(int M, int count, const double2* P, const double* lam, double2* R1,
                             double2* R2, hipStream_t s);
 
+// P^-1 of `count` problems (one wavefront each; stride kMaxM^2 like P) and,
+// when R1 != NULL, R2 = (P P^H)^-1, R1 = P^-H Lambda P^-1 ([count][M][M]).
+// Pinv may be NULL.
+hipError_t launch_pinv(int M, int count, const double2* P, const double* lam, double2* Pinv, double2* R1,
+                       double2* R2, hipStream_t s);
+
+// MMSE images; Pinv holds P^-1 of every problem (launch_pinv).
 hipError_t launch_separate(int M, bool fp64, const EmProblem* probs, int count, int max_n,
                            const void* y, const void* v, const double2* P, const double* lam,
-                           void* x, const int64_t* x_off, hipStream_t s);
+                           const double2* Pinv, void* x, const int64_t* x_off, hipStream_t s);
 
 }  // namespace fca

@@ -268,58 +268,112 @@ hipError_t launch_ll_reduce(const double* ll, int64_t ll_stride, int iters, int 
     return hipGetLastError();
 }
 
-// R2 = (P P^H)^-1 = P^-H P^-1 and R1 = P^-H Lambda P^-1 (eq. recoverS with
-// S~1 = Lambda, S~2 = I in the current eigenbasis). One thread per problem.
+// P^-1 of M x M complex matrices by Gauss-Jordan elimination with partial
+// pivoting, one wavefront per matrix (four per workgroup): lane (r, c) =
+// (lane / 8, lane % 8) holds entry (r, c) of the working matrix A (initially
+// P) and of X (initially I); each step exchanges them through LDS. The pivot
+// choice is made identically by every lane from the same LDS values, so the
+// control flow stays uniform. Optional outputs: Pinv (stride kMaxM^2 per
+// problem, like P) and R2 = (P P^H)^-1 = X^H X, R1 = P^-H Lambda P^-1 =
+// X^H Lambda X (eq. recoverS with S~1 = Lambda, S~2 = I in the current
+// eigenbasis), [count][M][M].
 template <int M>
-__global__ void recover_R_kernel(int count, const double2* __restrict__ P, const double* __restrict__ lam,
-                                 double2* __restrict__ R1, double2* __restrict__ R2) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void pinv_kernel(int count, const double2* __restrict__ P,
+                                                   const double* __restrict__ lam, double2* __restrict__ Pinv,
+                                                   double2* __restrict__ R1, double2* __restrict__ R2) {
+    __shared__ double2 sA[4][64], sX[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + w;  // problem of this wave (wave-uniform)
     if (i >= count) return;
-    double2 X[M][M];
-    invert<M>(P + (int64_t)i * kMaxM * kMaxM, X);
-    const double* l = lam + (int64_t)i * kMaxM;
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-#pragma unroll
-        for (int b = 0; b < M; ++b) {
+    const int r = lane >> 3, c = lane & 7;
+    const bool in = r < M && c < M;
+    double2* A = sA[w];
+    double2* X = sX[w];
+    const int64_t base = (int64_t)i * kMaxM * kMaxM;
+    double2 a = in ? P[base + r * M + c] : make_double2(0.0, 0.0);
+    double2 x = make_double2((in && r == c) ? 1.0 : 0.0, 0.0);
+#pragma unroll 1
+    for (int j = 0; j < M; ++j) {
+        A[lane] = a;
+        X[lane] = x;
+        wave_lds_sync();
+        int p = j;
+        double best = cabs2(A[j * 8 + j]);
+        for (int q = j + 1; q < M; ++q) {
+            const double mag = cabs2(A[q * 8 + j]);
+            if (mag > best) {
+                best = mag;
+                p = q;
+            }
+        }
+        const int rr = (r == j) ? p : (r == p ? j : r);  // this lane's row after swapping rows j and p
+        const double2 piv = A[p * 8 + j];
+        const double inv = 1.0 / cabs2(piv);
+        const double2 pinv = make_double2(piv.x * inv, -piv.y * inv);
+        const double2 prA = cmul(A[p * 8 + c], pinv), prX = cmul(X[p * 8 + c], pinv);  // new row j
+        if (r == j) {
+            a = prA;
+            x = prX;
+        } else {
+            const double2 f = A[rr * 8 + j];
+            a = csub(A[rr * 8 + c], cmul(f, prA));
+            x = csub(X[rr * 8 + c], cmul(f, prX));
+        }
+        wave_lds_sync();  // every lane has read this step's matrix before the next step writes
+    }
+    if (Pinv && in) Pinv[base + r * M + c] = x;
+    if (R1) {
+        X[lane] = x;
+        wave_lds_sync();
+        if (in) {
+            const double* l = lam + (int64_t)i * kMaxM;
             double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
 #pragma unroll
             for (int k = 0; k < M; ++k) {
-                const double2 t = cmulc(X[k][b], X[k][a]);  // conj(X_ka) X_kb
+                const double2 t = cmulc(X[k * 8 + c], X[k * 8 + r]);  // conj(X_kr) X_kc
                 s2 = cadd(s2, t);
                 s1 = cadd(s1, cscale(l[k], t));
             }
-            if (a == b) { s1.y = 0.0; s2.y = 0.0; }
-            R1[(int64_t)i * M * M + a * M + b] = s1;
-            R2[(int64_t)i * M * M + a * M + b] = s2;
+            if (r == c) {
+                s1.y = 0.0;
+                s2.y = 0.0;
+            }
+            R1[(int64_t)i * M * M + r * M + c] = s1;
+            R2[(int64_t)i * M * M + r * M + c] = s2;
         }
     }
 }
 
-hipError_t launch_recover_R(int M, int count, const double2* P, const double* lam, double2* R1,
-                            double2* R2, hipStream_t s) {
+hipError_t launch_pinv(int M, int count, const double2* P, const double* lam, double2* Pinv, double2* R1,
+                       double2* R2, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    const unsigned g = (count + 63) / 64;
+    const unsigned g = (count + 3) / 4;
     switch (M) {
-#define FCA_REC_CASE(MM_) \
-    case MM_: recover_R_kernel<MM_><<<g, 64, 0, s>>>(count, P, lam, R1, R2); break;
-        FCA_REC_CASE(1) FCA_REC_CASE(2) FCA_REC_CASE(3) FCA_REC_CASE(4)
-        FCA_REC_CASE(5) FCA_REC_CASE(6) FCA_REC_CASE(7) FCA_REC_CASE(8)
-#undef FCA_REC_CASE
+#define FCA_PINV_CASE(MM_) \
+    case MM_: pinv_kernel<MM_><<<g, 256, 0, s>>>(count, P, lam, Pinv, R1, R2); break;
+        FCA_PINV_CASE(1) FCA_PINV_CASE(2) FCA_PINV_CASE(3) FCA_PINV_CASE(4)
+        FCA_PINV_CASE(5) FCA_PINV_CASE(6) FCA_PINV_CASE(7) FCA_PINV_CASE(8)
+#undef FCA_PINV_CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+hipError_t launch_recover_R(int M, int count, const double2* P, const double* lam, double2* R1,
+                            double2* R2, hipStream_t s) {
+    return launch_pinv(M, count, P, lam, nullptr, R1, R2, s);
+}
+
 // ============================================================== MMSE separation
 // x1 = P^-H mu~1 with mu~1_i = v1 lam_i y~_i / d_i (eq. MMSEtilde and
 // Algorithm 1, step 11), x2 = y - x1 (eq. MMSE: mu1 + mu2 = y). Grid
-// (frame blocks, problems); P^-H in FP64 once per workgroup.
+// (frame blocks, problems); P^-1 comes precomputed (pinv_kernel).
 template <int M, typename T>
 __global__ __launch_bounds__(256) void separate_kernel(const EmProblem* __restrict__ probs,
                                                        const typename Vec2<T>::type* __restrict__ y,
                                                        const T* __restrict__ v, const double2* __restrict__ Pg,
                                                        const double* __restrict__ lamg,
+                                                       const double2* __restrict__ Pinv,
                                                        typename Vec2<T>::type* __restrict__ x,
                                                        const int64_t* __restrict__ x_off) {
     using T2 = typename Vec2<T>::type;
@@ -331,17 +385,12 @@ __global__ __launch_bounds__(256) void separate_kernel(const EmProblem* __restri
     if ((int)blockIdx.x * 256 >= pr.n) return;
     const int tid = threadIdx.x;
     const int64_t pbase = (int64_t)pr.pid * kMaxM * kMaxM;
-    if (tid < M * M) sP[tid] = Pg[pbase + tid];
-    if (tid < M) sLam[tid] = lamg[(int64_t)pr.pid * kMaxM + tid];
-    __syncthreads();
-    if (tid == 0) {
-        double2 X[M][M];
-        invert<M>(sP, X);
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-#pragma unroll
-            for (int b = 0; b < M; ++b) sQ[a * M + b] = cconj(X[b][a]);
+    if (tid < M * M) {
+        sP[tid] = Pg[pbase + tid];
+        const int a = tid / M, b = tid % M;
+        sQ[tid] = cconj(Pinv[pbase + b * M + a]);
     }
+    if (tid < M) sLam[tid] = lamg[(int64_t)pr.pid * kMaxM + tid];
     __syncthreads();
     const int n = blockIdx.x * 256 + tid;
     if (n >= pr.n) return;
@@ -387,7 +436,7 @@ __global__ __launch_bounds__(256) void separate_kernel(const EmProblem* __restri
 }
 
 hipError_t launch_separate(int M, bool fp64, const EmProblem* probs, int count, int max_n, const void* y,
-                           const void* v, const double2* P, const double* lam, void* x,
+                           const void* v, const double2* P, const double* lam, const double2* Pinv, void* x,
                            const int64_t* x_off, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     const dim3 grid((max_n + 255) / 256, count);
@@ -396,10 +445,10 @@ hipError_t launch_separate(int M, bool fp64, const EmProblem* probs, int count, 
     case MM_:                                                                                                    \
         if (fp64)                                                                                                \
             separate_kernel<MM_, double><<<grid, 256, 0, s>>>(probs, static_cast<const double2*>(y),              \
-                static_cast<const double*>(v), P, lam, static_cast<double2*>(x), x_off);                         \
+                static_cast<const double*>(v), P, lam, Pinv, static_cast<double2*>(x), x_off);                         \
         else                                                                                                     \
             separate_kernel<MM_, float><<<grid, 256, 0, s>>>(probs, static_cast<const float2*>(y),                \
-                static_cast<const float*>(v), P, lam, static_cast<float2*>(x), x_off);                           \
+                static_cast<const float*>(v), P, lam, Pinv, static_cast<float2*>(x), x_off);                           \
         break;
         FCA_SEP_CASE(1) FCA_SEP_CASE(2) FCA_SEP_CASE(3) FCA_SEP_CASE(4)
         FCA_SEP_CASE(5) FCA_SEP_CASE(6) FCA_SEP_CASE(7) FCA_SEP_CASE(8)
