@@ -92,7 +92,7 @@ def test_fp64_random_workload_all_bins(fca):
 ])
 def test_fp64_shapes(fca, M, F, N, iters):
     mx = synth.random_mixture(M, F, N, 100 + M + N)
-    check_fp64(fca, mx.y, iters, tol=1e-9)
+    check_fp64(fca, mx.y, iters, tol=1e-10)
 
 
 def test_fp64_user_start(fca):
@@ -179,8 +179,8 @@ def test_large_workload_subsample(fca):
     Ss, vs, lls, ofl = oracle.em(ys, S0s, v0s, 30, threads=16)
     gll64, gR64, gv64, gflags64, _ = run_gpu(fca, ys, fca.FCA_FP64, 30, separate=False)
     assert not gflags64.any() and not ofl.any()
-    assert per_freq_rel(gv64, vs, (-1,)).max() < 1e-9
-    assert per_freq_rel(gR64, Ss, (-2, -1)).max() < 1e-9
+    assert per_freq_rel(gv64, vs, (-1,)).max() < 1e-10
+    assert per_freq_rel(gR64, Ss, (-2, -1)).max() < 1e-10
     np.testing.assert_allclose(gll64, lls[:30].sum(1), rtol=1e-10)
 
 
@@ -507,10 +507,10 @@ def test_conventional_kernel_matches_oracle(fca, M, F, N, iters):
         x = fca.fca_separate(ctx)[0].cpu().numpy()
     finally:
         fca.fca_destroy(ctx)
-    assert per_freq_rel(gv[0].cpu().numpy(), v, (-1,)).max() < 1e-9
-    assert per_freq_rel(gR[0].cpu().numpy(), S, (-2, -1)).max() < 1e-9
+    assert per_freq_rel(gv[0].cpu().numpy(), v, (-1,)).max() < 1e-10
+    assert per_freq_rel(gR[0].cpu().numpy(), S, (-2, -1)).max() < 1e-10
     np.testing.assert_allclose(gll.cpu().numpy()[0], ll[:iters].sum(1), rtol=1e-10)
-    assert per_freq_rel(x, oracle.mmse(mx.y, S, v), (-2, -1)).max() < 1e-9
+    assert per_freq_rel(x, oracle.mmse(mx.y, S, v), (-2, -1)).max() < 1e-10
 
 
 def test_fastfca_and_conventional_kernels_interleave(fca):
@@ -528,8 +528,8 @@ def test_fastfca_and_conventional_kernels_interleave(fca):
         fca.fca_destroy(ctx)
     gll = np.r_[l1.cpu().numpy()[0], l2.cpu().numpy()[0], l3.cpu().numpy()[0]]
     np.testing.assert_allclose(gll, ll[:8].sum(1), rtol=1e-10)
-    assert per_freq_rel(gv[0].cpu().numpy(), v, (-1,)).max() < 1e-9
-    assert per_freq_rel(gR[0].cpu().numpy(), S, (-2, -1)).max() < 1e-9
+    assert per_freq_rel(gv[0].cpu().numpy(), v, (-1,)).max() < 1e-10
+    assert per_freq_rel(gR[0].cpu().numpy(), S, (-2, -1)).max() < 1e-10
 
 
 def test_conventional_kernel_fp32_array_workload(fca, array_workload):

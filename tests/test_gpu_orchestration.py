@@ -64,8 +64,8 @@ def test_128_thread_shape_matches_oracle(fca):
         S0, v0 = oracle.default_init(mx.y)
         S, vo, llo, fl = oracle.em(mx.y, S0, v0, 6, threads=8)
         assert not fl.any()
-        assert rel(v[k].cpu().numpy(), vo, (-1,)).max() < 1e-9
-        assert rel(R[k].cpu().numpy(), S, (-2, -1)).max() < 1e-9
+        assert rel(v[k].cpu().numpy(), vo, (-1,)).max() < 1e-10
+        assert rel(R[k].cpu().numpy(), S, (-2, -1)).max() < 1e-10
         np.testing.assert_allclose(ll[k].cpu().numpy(), llo[:6].sum(1), rtol=1e-10)
 
 
@@ -92,8 +92,8 @@ def test_streamed_shape_for_every_group(fca, prec):
         for k, mx in enumerate(mxs):
             S0, v0 = oracle.default_init(mx.y)
             S, vo, llo, fl = oracle.em(mx.y, S0, v0, 6, threads=8)
-            assert rel(v[k].cpu().numpy(), vo, (-1,)).max() < 1e-9
-            assert rel(R[k].cpu().numpy(), S, (-2, -1)).max() < 1e-9
+            assert rel(v[k].cpu().numpy(), vo, (-1,)).max() < 1e-10
+            assert rel(R[k].cpu().numpy(), S, (-2, -1)).max() < 1e-10
             np.testing.assert_allclose(ll[k].cpu().numpy(), llo[:6].sum(1), rtol=1e-10)
     else:
         for k in range(len(ys)):
