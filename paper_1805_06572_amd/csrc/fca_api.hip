@@ -637,6 +637,24 @@ hipError_t launch_em(int M, bool fp64, int nt, int fpt, const EmProblem* probs, 
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y, void* v,
+                          double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride,
+                          int iters, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    switch (M) {
+#define FCA_CONV_CASE(MM_)                                                                                         \
+    case MM_:                                                                                                      \
+        return fp64 ? launch_conv_fpt<MM_, double>(fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, \
+                                                    iters, s)                                                      \
+                    : launch_conv_fpt<MM_, float>(fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride,   \
+                                                   iters, s);
+        FCA_CONV_CASE(1) FCA_CONV_CASE(2) FCA_CONV_CASE(3) FCA_CONV_CASE(4)
+        FCA_CONV_CASE(5) FCA_CONV_CASE(6) FCA_CONV_CASE(7) FCA_CONV_CASE(8)
+#undef FCA_CONV_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace fca
 
 namespace {

@@ -1,4 +1,4 @@
-// fca_conv.hip -- the conventional FCA EM (Section 2) on gfx950, the
+// fca_conv.h -- the conventional FCA EM (Section 2) on gfx950, the
 // frame-wise algorithm FastFCA replaces: per bin, the mixture covariance
 // v1 R1 + v2 R2 is factorised (Cholesky) and the E-step needs its solves and
 // matrix products (eqs. MMSE, postquadexp); the M-step is eqs. vupdate and
@@ -11,6 +11,10 @@
 // frequency) problem for all iterations of a call, frames resident in
 // registers (at most kMaxFrames), FP64 fixed-order workgroup sums, FP64
 // per-frequency inverses R_j^-1 (eq. vupdate uses the old R_j).
+// Instantiated by fca_conv_lo.hip (M <= 4) and fca_conv_m5.hip ..
+// fca_conv_m8.hip, so the slow compilations run in parallel.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include "fca_device.h"
@@ -356,7 +360,7 @@ __global__ __launch_bounds__(kEmThreads) void conv_em_kernel(
 }
 
 template <int M, typename T>
-static hipError_t launch_conv_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v, double2* P,
+hipError_t launch_conv_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v, double2* P,
                                   double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride, int iters,
                                   hipStream_t s) {
     using T2 = typename Vec2<T>::type;
@@ -370,24 +374,6 @@ static hipError_t launch_conv_fpt(int fpt, const EmProblem* probs, int count, co
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
-}
-
-hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y, void* v,
-                          double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride,
-                          int iters, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    switch (M) {
-#define FCA_CONV_CASE(MM_)                                                                                         \
-    case MM_:                                                                                                      \
-        return fp64 ? launch_conv_fpt<MM_, double>(fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, \
-                                                    iters, s)                                                      \
-                    : launch_conv_fpt<MM_, float>(fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride,   \
-                                                   iters, s);
-        FCA_CONV_CASE(1) FCA_CONV_CASE(2) FCA_CONV_CASE(3) FCA_CONV_CASE(4)
-        FCA_CONV_CASE(5) FCA_CONV_CASE(6) FCA_CONV_CASE(7) FCA_CONV_CASE(8)
-#undef FCA_CONV_CASE
-        default: return hipErrorInvalidValue;
-    }
 }
 
 }  // namespace fca

@@ -57,8 +57,15 @@ hipError_t launch_em(int M, bool fp64, int nt, int fpt, const EmProblem* probs, 
                      void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll,
                      int64_t ll_stride, int iters, hipStream_t s);
 
-// The conventional frame-wise EM (fca_conv.hip; resident frames only, fpt in
-// 1, 2, 4, 8, kEmThreads threads).
+// The conventional frame-wise EM (fca_conv.h; resident frames only, fpt in
+// 1, 2, 4, 8, kEmThreads threads): per (M, T) launcher, instantiated in
+// fca_conv_lo.hip and fca_conv_m5.hip .. fca_conv_m8.hip, and the dispatch
+// on M and precision (fca_api.hip).
+template <int M, typename T>
+hipError_t launch_conv_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v, double2* P,
+                           double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride, int iters,
+                           hipStream_t s);
+
 hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
                           void* v, double2* P, double* lam, double* logdet, int* flags, double* ll,
                           int64_t ll_stride, int iters, hipStream_t s);
