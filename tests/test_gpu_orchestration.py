@@ -182,3 +182,56 @@ def test_graph_with_inactive_mixture_and_stale_shape(fca):
     finally:
         fca.fca_destroy(ctx)
         fca.fca_destroy(ref)
+
+
+def test_invalid_arguments_are_rejected_and_leave_the_context_usable(fca):
+    """Host-side argument checks of the ABI: FCA_E_ARG (or FCA_E_STATE) and
+    no change to a live context."""
+    import ctypes
+    L = fca.lib()
+    mx = synth.random_mixture(2, 3, 40, 5)
+    y = torch.from_numpy(mx.y).to(DEV)
+
+    def init_status(**over):
+        p = fca.fca_problem(M=2, F=3, N=40, prec=fca.FCA_FP64, y=y.data_ptr(), y_stride_f=y.stride(0),
+                            y_stride_n=y.stride(1), y_stride_m=y.stride(2), R0=None, v0=None, stream=None)
+        for k, val in over.items():
+            setattr(p, k, val)
+        h = ctypes.c_void_p()
+        st = L.fca_init(ctypes.byref(p), ctypes.byref(h))
+        if h.value:
+            L.fca_destroy(h)
+        return st, h.value
+
+    st, h = init_status()
+    assert st == fca.FCA_OK and h is not None
+    for bad in ({"M": 0}, {"M": 9}, {"F": 0}, {"N": 0}, {"prec": 7}, {"y": None}, {"y_stride_n": -1}):
+        st, h = init_status(**bad)
+        assert st == fca.FCA_E_ARG and h is None, bad
+    with pytest.raises(fca.FcaError) as e:          # batch members must share F
+        fca.fca_init_batch([y, y[:2]], prec=fca.FCA_FP64)
+    assert e.value.status == fca.FCA_E_ARG
+
+    ctx = fca.fca_init(y, prec=fca.FCA_FP64)
+    try:
+        ll0, _, _ = fca.fca_em_step(ctx, 3, want_R=False, want_v=False)
+        fca.fca_reset(ctx)
+        h = ctx.handle
+        assert L.fca_em_step(h, -1, None, None, None) == fca.FCA_E_ARG
+        assert L.fca_set_start(h, 1, None, None) == fca.FCA_E_ARG
+        assert L.fca_set_active(h, -1, 0) == fca.FCA_E_ARG
+        assert L.fca_set_launch_shape(h, 5, 128, 0) == fca.FCA_E_ARG
+        assert L.fca_set_launch_shape(h, 0, 64, 0) == fca.FCA_E_ARG
+        assert L.fca_graph_launch(h, 1) == fca.FCA_E_STATE
+        host_ll = np.zeros((1, 3))
+        assert L.fca_graph_capture(h, 3, 1, host_ll.ctypes.data, None, None, None) == fca.FCA_E_ARG
+        assert L.fca_em_step(None, 1, None, None, None) == fca.FCA_E_ARG
+        host = np.zeros((1, 2, 2), np.complex128)
+        flags = np.zeros(1, np.int32)
+        lam = np.zeros(2)
+        assert L.fca_gevd(2, 1, host.ctypes.data, host.ctypes.data, host.ctypes.data, lam.ctypes.data,
+                          flags.ctypes.data, None) == fca.FCA_E_ARG
+        ll1, _, _ = fca.fca_em_step(ctx, 3, want_R=False, want_v=False)
+        assert torch.equal(ll0, ll1)
+    finally:
+        fca.fca_destroy(ctx)
