@@ -235,3 +235,43 @@ def test_invalid_arguments_are_rejected_and_leave_the_context_usable(fca):
         assert torch.equal(ll0, ll1)
     finally:
         fca.fca_destroy(ctx)
+
+
+def test_batched_workload_full_size_sampled_against_oracle(fca):
+    """The 64-mixture uneven batch of the benchmark (same draws, autotuned
+    shapes, concurrent groups, captured step), 50 iterations: for one mixture
+    of each microphone count, four frequencies against the oracle run from
+    the same plain start (computed from the whole mixture)."""
+    rng = np.random.default_rng(2)
+    B, F, L = 64, 513, 50
+    Ns = rng.integers(200, 2001, size=B)
+    Ms = rng.choice([2, 4, 8], size=B)
+    gen = [synth.array_mixture_device(int(Ms[b]), F, int(Ns[b]), seed=1000 + b) for b in range(B)]
+    ys = [g[0] for g in gen]
+    ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+    try:
+        fca.fca_autotune(ctx, 3)
+        g = fca.fca_graph_capture(ctx, L, with_reset=True)
+        fca.fca_graph_launch(g, 1, allow_flags=True)
+        ll_gpu = g.loglik.cpu().numpy()
+        flags = fca.fca_status_per_freq(ctx)
+        v_off = np.cumsum([0] + [2 * F * int(n) for n in Ns])
+        checked = 0
+        for M in (2, 4, 8):
+            b = int(np.nonzero(Ms == M)[0][0])
+            N = int(Ns[b])
+            y = ys[b].cpu().numpy().astype(np.complex128)
+            kappa = synth.condition_numbers(gen[b][2])
+            idx = np.nonzero(kappa <= 1e3)[0]
+            idx = idx[np.linspace(0, len(idx) - 1, 4).round().astype(int)]
+            S0, v0 = oracle.default_init(y)
+            S, v, ll, fl = oracle.em(np.ascontiguousarray(y[idx]), np.ascontiguousarray(S0[:, idx]),
+                                     np.ascontiguousarray(v0[:, idx]), L, threads=8)
+            gv = g.v[v_off[b]:v_off[b + 1]].view(2, F, N)[:, idx].double().cpu().numpy()
+            ok = (fl == 0) & (flags[b, idx] == 0)
+            assert rel(gv, v, (-1,))[:, ok].max() < 1e-4, (M, rel(gv, v, (-1,)))
+            checked += int(ok.sum())
+            assert np.all(np.isfinite(ll_gpu[b])) and np.all(np.diff(ll_gpu[b]) > -1e-4 * np.abs(ll_gpu[b][1:]))
+        assert checked >= 10
+    finally:
+        fca.fca_destroy(ctx)
