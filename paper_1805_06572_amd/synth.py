@@ -220,12 +220,15 @@ def array_mixture_device(M: int, F: int, N: int, seed: int, device="cuda:0", ar1
     for j in range(2):
         if ar1:
             mu, var, rho = -1.9635100260214235, np.pi ** 2 / 2.0, 0.9
-            e = torch.randn((F, N), generator=g, device=device) * float(np.sqrt(var * (1 - rho * rho)))
-            lv = torch.empty((F, N), device=device)
-            lv[:, 0] = mu + float(np.sqrt(var)) * torch.randn((F,), generator=g, device=device)
-            for n in range(1, N):
-                lv[:, n] = mu + rho * (lv[:, n - 1] - mu) + e[:, n]
-            v = torch.exp(lv)
+            # x_n = rho x_(n-1) + e_n, x_0 stationary: a doubling scan over n
+            # (x_n <- x_n + rho^s x_(n-s) for s = 1, 2, 4, ...)
+            x = torch.randn((F, N), generator=g, device=device) * float(np.sqrt(var * (1 - rho * rho)))
+            x[:, 0] = float(np.sqrt(var)) * torch.randn((F,), generator=g, device=device)
+            s = 1
+            while s < N:
+                x = torch.cat([x[:, :s], x[:, s:] + float(rho ** s) * x[:, :-s]], dim=1)
+                s *= 2
+            v = torch.exp(mu + x)
         else:
             v = torch._standard_gamma(torch.full((F, N), 0.5, device=device), generator=g)
         z = torch.complex(torch.randn((F, N, M), generator=g, device=device),
