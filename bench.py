@@ -338,10 +338,7 @@ def run_time_to_target(args):
     from paper_1805_06572_amd import fca, learned_init, schedule, synth
 
     M, F, N, K, L = 4, 513, 1000, args.mixtures, args.iters
-    t0 = time.perf_counter()
-    net, losses = learned_init.train(M=M, F=F, steps=args.train_steps, batch=8192, seed=0)
-    train_s = time.perf_counter() - t0
-    bce, bce_const = learned_init.evaluate(net, n=65536, M=M, F=F)
+    widths = [int(h) for h in args.hidden.split(",")]
     ys = [synth.array_mixture_device(M, F, N, seed=3000 + k, ar1=True)[0] for k in range(K)]
     ys64 = [y.to(torch.complex128) for y in ys]
     torch.cuda.synchronize()
@@ -382,16 +379,17 @@ def run_time_to_target(args):
     def stop(b, ll):
         return hit_rule(b, ll) or conv_rule(b, ll)
 
-    def batched(learned):
+    def batched(net):
         """Wall time of one batched FP32 run from context-ready to every
-        mixture stopped (warm: the same run once before, untimed)."""
+        mixture stopped, with the learned start of `net` (or the plain start
+        if None); warm: the same run once before, untimed."""
         res = None
         for rep in range(2):
             ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             chosen = None
-            if learned:
+            if net is not None:
                 chosen, _, _ = learned_init.choose_starts(net, ctx, ys)
             t2 = time.perf_counter()
             iters, hist = schedule.run_batch(ctx, 2 * L, (16, 8, 4, 2), stop)
@@ -401,35 +399,47 @@ def run_time_to_target(args):
             res = ((t3 - t1) * 1e3, (t2 - t1) * 1e3, iters, hist, chosen)
         return res
 
-    bp_ms, _, bp_iters, bp_hist, _ = batched(False)
-    bl_ms, bl_init_ms, bl_iters, bl_hist, chosen = batched(True)
-    bl_hits = [first_hit(h, thr[k]) for k, h in enumerate(bl_hist)]
+    bp_ms, _, bp_iters, bp_hist, _ = batched(None)
     bp_hits = [first_hit(h, thr[k]) for k, h in enumerate(bp_hist)]
-    rec = base_record(args, K * F * N * float(np.mean(bl_iters)) / (bl_ms * 1e-3), bl_ms,
+    learned = {}
+    for H in widths:
+        t0 = time.perf_counter()
+        net, _ = learned_init.train(M=M, F=F, steps=args.train_steps, batch=8192, seed=0, hidden=H)
+        train_s = time.perf_counter() - t0
+        bce, bce_const = learned_init.evaluate(net, n=65536, M=M, F=F)
+        bl_ms, bl_init_ms, bl_iters, bl_hist, chosen = batched(net)
+        bl_hits = [first_hit(h, thr[k]) for k, h in enumerate(bl_hist)]
+        learned[H] = {
+            "hidden": H, "batched_learned_start_fp32_ms": bl_ms, "learned_start_and_fallback_ms": bl_init_ms,
+            "speedup_vs_plain_fp64": plain64_ms / bl_ms, "speedup_vs_plain_fp32": plain32_ms / bl_ms,
+            "speedup_of_learned_start_in_batch": bp_ms / bl_ms,
+            "mean_iterations_run": float(np.mean(bl_iters)),
+            "iterations_to_target": bl_hits, "reached": sum(i is not None for i in bl_hits),
+            "learned_start_chosen": int(np.sum(chosen)),
+            "mlp_train_s": train_s, "mlp_train_steps": args.train_steps,
+            "mlp_heldout_bce": bce, "constant_predictor_bce": bce_const}
+        net.close()
+    head = learned[widths[0]]
+    bl_ms = head["batched_learned_start_fp32_ms"]
+    rec = base_record(args, K * F * N * head["mean_iterations_run"] / (bl_ms * 1e-3), bl_ms,
                       {"workload": f"time to target: {K} held-out array mixtures (AR(1) log-powers), M={M}, "
                                    f"F={F}, N={N}; target = LL of plain FastFCA (FP64, plain start) after "
-                                   f"{L} iterations, reached at 99.9 % of its rise",
-                       "mixtures": K, "M": M, "F": F, "N": N, "iterations": L})
+                                   f"{L} iterations, reached at 99.9 % of its rise; learned start of hidden "
+                                   f"width {widths[0]}",
+                       "mixtures": K, "M": M, "F": F, "N": N, "iterations": L, "hidden": widths[0]})
     rec["steps"], rec["warmup"] = 1, 1
     rec["time_to_target"] = {
         "plain_fastfca_fp64_one_at_a_time_ms": plain64_ms,
         "plain_fastfca_fp32_one_at_a_time_ms": plain32_ms,
         "batched_plain_start_fp32_ms": bp_ms,
-        "batched_learned_start_fp32_ms": bl_ms,
-        "learned_start_and_fallback_ms": bl_init_ms,
-        "speedup_vs_plain_fp64": plain64_ms / bl_ms,
-        "speedup_vs_plain_fp32": plain32_ms / bl_ms,
-        "speedup_of_learned_start_in_batch": bp_ms / bl_ms,
+        "batched_plain_mean_iterations_run": float(np.mean(bp_iters)),
         "iterations_to_target": {"plain_fp64": plain64_its, "plain_fp32": plain32_its,
-                                 "batched_plain": bp_hits, "batched_learned": bl_hits},
+                                 "batched_plain": bp_hits},
         "reached": {"plain_fp32": sum(i is not None for i in plain32_its),
-                    "batched_plain": sum(i is not None for i in bp_hits),
-                    "batched_learned": sum(i is not None for i in bl_hits)},
-        "learned_start_chosen": int(np.sum(chosen)), "stop_rule": "reached target, or LL rise below 1e-6 of "
-                                                                   "the total (converged elsewhere), checked after "
-                                                                   "16, 24, 28 and then every 2 iterations",
-        "mlp_train_s": train_s, "mlp_train_steps": args.train_steps,
-        "mlp_heldout_bce": bce, "constant_predictor_bce": bce_const}
+                    "batched_plain": sum(i is not None for i in bp_hits)},
+        "learned": [learned[H] for H in widths],
+        "stop_rule": "reached target, or LL rise below 1e-6 of the total (converged elsewhere), checked after "
+                     "16, 24, 28 and then every 2 iterations"}
     return rec
 
 
@@ -445,6 +455,9 @@ def main():
     ap.add_argument("--N", type=int, default=1000)
     ap.add_argument("--mixtures", type=int, default=16)
     ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--hidden", default="64,256",
+                    help="time-to-target: hidden widths of the learned-start networks (the first one is the "
+                         "headline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="time the eager calls instead of the captured step")

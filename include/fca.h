@@ -243,23 +243,30 @@ fca_status fca_graph_launch(fca_ctx *c, int32_t count);
  * A per-bin MLP predicts r = v1 / (v1 + v2) from features of y(n,f):
  * log(|y_m|^2 + 1e-20) for each microphone, cos and sin of the phase of y_m
  * relative to microphone 1 (m = 2..M), and f / (F - 1) (IN = 3M - 1 values,
- * zero-padded to 32). Three hidden layers of width 256 with GELU (erf form),
- * one sigmoid output; BF16 weights and activations into MFMA, FP32
+ * zero-padded to 32). Three hidden layers of width H (64, 128 or 256) with
+ * GELU, one sigmoid output; BF16 weights and activations into MFMA, FP32
  * accumulation, FP32 master weights, AdamW; loss = mean binary cross-
  * entropy against soft targets. The learned start is
  * v_j^(0) = (r, 1 - r) * 2 ||y||^2 / M (r = 1/2 gives the plain start) and
- * reaches the EM only through fca_problem.v0.
+ * reaches the EM only through fca_problem.v0. The forward GELU is
+ * max(x, 0) - t P(t), t = min(|x|, 4), with P a fitted degree-7 polynomial
+ * (|error| <= 1.3e-4 against x Phi(x)); the backward uses the exact GELU's
+ * derivative. The network costs about 2 (32 H + 2 H^2 + H) flop and 3 H
+ * GELUs per bin: at M = 4 the EM spends about 500 flop per bin and
+ * iteration, so H = 256 costs as much as tens of EM iterations and H = 64
+ * about ten times less.
  * Parameter vector (fp32, flat): for each hidden layer l = 1..3 its weight
- * [256][in_l] (in_1 = 32, the padded input; in_2 = in_3 = 256) then its bias
- * [256]; then the output weight [256] and bias [1].
+ * [H][in_l] (in_1 = 32, the padded input; in_2 = in_3 = H) then its bias
+ * [H]; then the output weight [H] and bias [1].
  * Every array argument below is a DEVICE pointer unless marked host; y of
  * fca_mlp_forward/backward is [n][M] complex64, fpos/target/r are [n] float.
  * ------------------------------------------------------------------ */
 typedef struct fca_mlp fca_mlp;
 
 /* max_batch: largest n of one forward/backward call, a multiple of 64.
- * 2 <= M <= 8. Weights are initialised from seed. */
-fca_status fca_mlp_create(int32_t M, uint64_t seed, int32_t max_batch, void *stream, fca_mlp **out);
+ * 2 <= M <= 8; hidden (H) is 64, 128 or 256, else FCA_E_ARG. Weights are
+ * initialised from seed. All work runs on `stream`. */
+fca_status fca_mlp_create(int32_t M, int32_t hidden, uint64_t seed, int32_t max_batch, void *stream, fca_mlp **out);
 void fca_mlp_destroy(fca_mlp *m);
 int64_t fca_mlp_num_params(const fca_mlp *m);
 const char *fca_mlp_last_error(const fca_mlp *m);

@@ -2,33 +2,45 @@
 
 Only tests may import this module. It restates, in plain numpy, the network
 that the library's MLP kernels compute (the library's header documents it):
-features of a bin y in C^M, three hidden layers of width 256 with the erf
+features of a bin y in C^M, three hidden layers of width H with the erf
 form of GELU, a sigmoid output r, and the mean binary cross-entropy against
 soft targets, with its gradient by reverse-mode differentiation. Parameters
-use the library's flat layout (per hidden layer: weight [256][in] then bias
-[256], in = 32 padded inputs for the first layer; then output weight [256]
-and bias [1]).
+use the library's flat layout (per hidden layer: weight [H][in] then bias
+[H], in = 32 padded inputs for the first layer; then output weight [H] and
+bias [1]); H follows from the length, 2 H^2 + 36 H + 1.
 """
 from __future__ import annotations
 
 import numpy as np
 from scipy.special import erf
 
-HIDDEN = 256
 KP = 32
+
+
+def num_params(hidden: int) -> int:
+    return KP * hidden + hidden + 2 * (hidden * hidden + hidden) + hidden + 1
+
+
+def hidden_width(n_params: int) -> int:
+    """H with num_params(H) == n_params."""
+    h = int(round((-(KP + 4) + np.sqrt((KP + 4) ** 2 - 8 * (1 - n_params))) / 4))
+    if num_params(h) != n_params:
+        raise ValueError(f"{n_params} parameters fit no hidden width")
+    return h
 
 
 def unpack(params: np.ndarray):
     p = np.asarray(params, dtype=np.float64)
+    H = hidden_width(p.size)
     Ws, bs, o = [], [], 0
     for l in range(3):
-        fan = KP if l == 0 else HIDDEN
-        Ws.append(p[o:o + HIDDEN * fan].reshape(HIDDEN, fan))
-        o += HIDDEN * fan
-        bs.append(p[o:o + HIDDEN])
-        o += HIDDEN
-    w4 = p[o:o + HIDDEN]
-    o += HIDDEN
+        fan = KP if l == 0 else H
+        Ws.append(p[o:o + H * fan].reshape(H, fan))
+        o += H * fan
+        bs.append(p[o:o + H])
+        o += H
+    w4 = p[o:o + H]
+    o += H
     b4 = p[o]
     return Ws, bs, w4, b4
 

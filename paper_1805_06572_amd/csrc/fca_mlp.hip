@@ -6,13 +6,14 @@
 // through the v0 argument of fca_init.
 //
 // Network: x (IN = 3M - 1 features, zero-padded to KP = 32) -> 3 hidden
-// layers of width 256 with GELU (erf form) -> 1 logit -> sigmoid.
+// layers of width H (64, 128 or 256, chosen at creation) with GELU -> 1
+// logit -> sigmoid.
 // Features: log(|y_m|^2 + 1e-20) for each microphone, cos and sin of the
 // phase of y_m relative to microphone 1 (m = 2..M), and f / (F - 1).
 // Loss: mean binary cross-entropy with soft targets.
 //
-// Layouts: activations row-major [n][256] (bf16 copies also transposed
-// [256][n] for the weight-gradient GEMMs); weights like a linear layer,
+// Layouts: activations row-major [n][H] (bf16 copies also transposed
+// [H][n] for the weight-gradient GEMMs); weights like a linear layer,
 // W[out][in] (bf16 copies W and W^T). GEMM: C[m][c] = sum_k A[m][k] B[c][k]
 // with both operands K-contiguous.
 #include <hip/hip_runtime.h>
@@ -30,7 +31,7 @@
 
 namespace {
 
-constexpr int kHidden = 256;
+constexpr int kMaxHidden = 256;
 constexpr int kKP = 32;        // padded input width
 constexpr int kLayers = 3;     // hidden layers
 
@@ -39,7 +40,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7, far below the BF16
-// rounding the activations get): erf(a) = 1 - t (a1 + t (a2 + ... a5)) e^-a^2,
+// rounding the activations get; used by the GELU derivative): erf(a) = 1 - t (a1 + t (a2 + ... a5)) e^-a^2,
 // t = 1 / (1 + p a), a = |x|, odd extension.
 __device__ __forceinline__ float erf_as(float x) {
     const float a = fabsf(x);
@@ -51,32 +52,52 @@ __device__ __forceinline__ float erf_as(float x) {
     const float e = __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f);
     return copysignf(fmaf(-t * q, e, 1.0f), x);
 }
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
+// GELU(x) = x Phi(x) = max(x, 0) - t Phi(-t) with t = |x| (Phi: standard
+// normal CDF). The even tail t Phi(-t) is replaced by t P(t), P of degree 7,
+// fitted on [0, 4] by least squares with iteratively reweighted residuals,
+// and t is clamped to 4 (where t Phi(-t) = 1.3e-4): |error| <= 1.3e-4 on the
+// whole line in FP32, far below the BF16 rounding of the activations, and no
+// transcendental instruction (about half the VALU work of the erf form).
+// The backward uses the derivative of the exact GELU (erf_as).
+__device__ __forceinline__ float gelu(float x) {
+    const float t = fminf(fabsf(x), 4.0f);
+    float p = 4.867522875429131e-05f;
+    p = fmaf(p, t, -0.0014393035089597106f);
+    p = fmaf(p, t, 0.015238428488373756f);
+    p = fmaf(p, t, -0.07614787667989731f);
+    p = fmaf(p, t, 0.17618107795715332f);
+    p = fmaf(p, t, -0.08138523250818253f);
+    p = fmaf(p, t, -0.3706264793872833f);
+    p = fmaf(p, t, 0.49667835235595703f);
+    return fmaf(-t, p, fmaxf(x, 0.0f));
+}
 __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) +
            x * 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.5f * x * x * 1.4426950408889634f);
 }
 
 // ------------------------------------------------------------------ features
-// Features of one bin (zero-padded to kKP).
-__device__ __forceinline__ void bin_features(const float2* __restrict__ yb, int M, float fpos, float (&feat)[kKP]) {
-    for (int j = 0; j < kKP; ++j) feat[j] = 0.0f;
+// Features of one bin (zero-padded to kKP), stored as T (a local FP32 array
+// or a BF16 row in LDS).
+template <typename T>
+__device__ __forceinline__ void bin_features(const float2* __restrict__ yb, int M, float fpos, T* feat) {
+    for (int j = 0; j < kKP; ++j) feat[j] = (T)0.0f;
     const float2 y0 = yb[0];
     const float p0 = y0.x * y0.x + y0.y * y0.y;
     for (int m = 0; m < M; ++m) {
         const float2 ym = yb[m];
         const float pm = ym.x * ym.x + ym.y * ym.y;
-        feat[m] = logf(pm + 1e-20f);
+        feat[m] = (T)logf(pm + 1e-20f);
         if (m > 0) {
             // y_m conj(y_0) / (|y_m| |y_0|)
             const float den = sqrtf(pm * p0);
             const float cr = ym.x * y0.x + ym.y * y0.y, ci = ym.y * y0.x - ym.x * y0.y;
             const bool okd = den > 0.0f;
-            feat[M + 2 * (m - 1)] = okd ? cr / den : 0.0f;
-            feat[M + 2 * (m - 1) + 1] = okd ? ci / den : 0.0f;
+            feat[M + 2 * (m - 1)] = (T)(okd ? cr / den : 0.0f);
+            feat[M + 2 * (m - 1) + 1] = (T)(okd ? ci / den : 0.0f);
         }
     }
-    feat[3 * M - 2] = fpos;
+    feat[3 * M - 2] = (T)fpos;
 }
 
 __global__ void mlp_features_kernel(const float2* __restrict__ y, const float* __restrict__ fpos, int n, int M,
@@ -173,13 +194,13 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g) {
 // z = GELU(pre3) . w4 + b4, r = sigmoid(z); with targets: loss terms and
 // dz = (r - t) / n. One wave per row.
 __global__ void mlp_out_kernel(const float* __restrict__ pre3, const float* __restrict__ w4, const float* __restrict__ b4,
-                               int n, float* __restrict__ r_out, const float* __restrict__ target,
+                               int n, int hidden, float* __restrict__ r_out, const float* __restrict__ target,
                                float* __restrict__ dz, double* __restrict__ loss_terms) {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
     float s = 0.0f;
-    for (int o = lane; o < kHidden; o += 64) s += gelu(pre3[(int64_t)row * kHidden + o]) * w4[o];
+    for (int o = lane; o < hidden; o += 64) s += gelu(pre3[(int64_t)row * hidden + o]) * w4[o];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) {
@@ -199,11 +220,11 @@ __global__ void mlp_out_kernel(const float* __restrict__ pre3, const float* __re
 
 // dpre3[b][o] = dz[b] w4[o] GELU'(pre3[b][o]) (bf16, both layouts)
 __global__ void mlp_out_back_kernel(const float* __restrict__ pre3, const float* __restrict__ w4,
-                                    const float* __restrict__ dz, int n, bf16* __restrict__ d3, bf16* __restrict__ d3T,
-                                    int ldt) {
+                                    const float* __restrict__ dz, int n, int hidden, bf16* __restrict__ d3,
+                                    bf16* __restrict__ d3T, int ldt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)n * kHidden) return;
-    const int b = (int)(i / kHidden), o = (int)(i % kHidden);
+    if (i >= (int64_t)n * hidden) return;
+    const int b = (int)(i / hidden), o = (int)(i % hidden);
     const bf16 d = (bf16)(dz[b] * w4[o] * gelu_grad(pre3[i]));
     d3[i] = d;
     d3T[(int64_t)o * ldt + b] = d;
@@ -211,34 +232,35 @@ __global__ void mlp_out_back_kernel(const float* __restrict__ pre3, const float*
 
 // grad of w4 and b4: dw4[o] = sum_b dz[b] GELU(pre3[b][o]); db4 = sum_b dz[b].
 // Two fixed-order stages: block c sums rows [kOgRows c, kOgRows (c + 1)) into
-// part[c][0..256] (entry 256: the dz sum), then one block sums the blocks.
+// part[c][0..H] (entry H: the dz sum), then one block sums the blocks. One
+// thread per hidden unit (blockDim = H).
 constexpr int kOgRows = 64;
 __global__ void mlp_out_grad_part_kernel(const float* __restrict__ pre3, const float* __restrict__ dz, int n,
                                          float* __restrict__ part) {
-    const int o = threadIdx.x;  // 256 threads
+    const int o = threadIdx.x, hidden = blockDim.x;
     const int b0 = blockIdx.x * kOgRows, b1 = min(n, b0 + kOgRows);
     float s = 0.0f, t = 0.0f;
     for (int b = b0; b < b1; ++b) {
-        s += dz[b] * gelu(pre3[(int64_t)b * kHidden + o]);
+        s += dz[b] * gelu(pre3[(int64_t)b * hidden + o]);
         t += dz[b];
     }
-    part[(int64_t)blockIdx.x * (kHidden + 1) + o] = s;
-    if (o == 0) part[(int64_t)blockIdx.x * (kHidden + 1) + kHidden] = t;
+    part[(int64_t)blockIdx.x * (hidden + 1) + o] = s;
+    if (o == 0) part[(int64_t)blockIdx.x * (hidden + 1) + hidden] = t;
 }
 
 __global__ void mlp_out_grad_sum_kernel(const float* __restrict__ part, int nblk, float* __restrict__ gw4,
                                         float* __restrict__ gb4) {
-    const int o = threadIdx.x;  // 256 threads
+    const int o = threadIdx.x, hidden = blockDim.x;
     float s = 0.0f, t = 0.0f;
     for (int c = 0; c < nblk; ++c) {
-        s += part[(int64_t)c * (kHidden + 1) + o];
-        if (o == 0) t += part[(int64_t)c * (kHidden + 1) + kHidden];
+        s += part[(int64_t)c * (hidden + 1) + o];
+        if (o == 0) t += part[(int64_t)c * (hidden + 1) + hidden];
     }
     gw4[o] = s;
     if (o == 0) gb4[0] = t;
 }
 
-// bias gradients: gb[o] = sum_b d[o][b] from the transposed bf16 layout [256][ldt]
+// bias gradients: gb[o] = sum_b d[o][b] from the transposed bf16 layout [H][ldt]; one block per o
 __global__ void mlp_bias_grad_kernel(const bf16* __restrict__ dT, int n, int ldt, float* __restrict__ gb) {
     __shared__ float red[256];
     const int o = blockIdx.x;
@@ -283,55 +305,60 @@ __global__ void mlp_weight_copy_kernel(const float* __restrict__ W, int rows, in
 // f N + n: features -> three hidden layers (BF16 MFMA 16x16x32, FP32
 // accumulation) -> output layer -> sigmoid -> v0[j][f][n]. The activations of
 // the tile stay in LDS; the weights are read from L2. Wave w owns the output
-// columns 64 w .. 64 w + 63 of every layer for all rows of the tile (8 x 4
-// MFMA tiles). Same arithmetic as the training forward (features, bias,
-// GELU, BF16 rounding of the hidden activations, FP32 output layer) up to
-// the order of the output-layer sum.
-constexpr int kRT = 4;            // row tiles of 16 per wave
+// columns 16 CT w .. 16 CT (w + 1) - 1 of every layer (H = 64 CT) for all
+// rows of the tile (CT x kRT MFMA tiles). Same arithmetic as the training
+// forward (features, bias, GELU, BF16 rounding of the hidden activations,
+// FP32 output layer) up to the order of the output-layer sum.
+constexpr int kRT = 8;            // row tiles of 16 per wave
 constexpr int kTile = 16 * kRT;   // bins per workgroup
 constexpr int kXP = kKP + 8;      // LDS row pitch of the features (bf16)
-constexpr int kHP = kHidden + 8;  // LDS row pitch of the hidden activations (bf16)
 
+template <int H>
 struct InferShared {
+    static constexpr int kHP = H + 8;  // LDS row pitch of the hidden activations (bf16)
     bf16 X[kTile * kXP];
-    bf16 H[kTile * kHP];
+    bf16 Hs[kTile * kHP];
     float zp[4][kTile];
     float sv[kTile];
 };
 
-// out^T = W A^T for this wave's 64 output columns and the tile's 128 rows:
-// acc[ct][rt] is the 16 x 16 block (columns c0 + 16 ct.., rows 16 rt..), lane
-// l holding columns c0 + 16 ct + 4 (l / 16) + q, q = 0..3, of row 16 rt + l % 16
-// (the MFMA A operand is W, the B operand the activations, both K-contiguous).
-template <int K, int LDA>
+// out^T = W A^T for this wave's 16 CT output columns and the tile's kTile
+// rows: acc[ct][rt] is the 16 x 16 block (columns c0 + 16 ct.., rows
+// 16 rt..), lane l holding columns c0 + 16 ct + 4 (l / 16) + q, q = 0..3, of
+// row 16 rt + l % 16 (the MFMA A operand is W, the B operand the
+// activations, both K-contiguous).
+template <int K, int LDA, int CT>
 __device__ __forceinline__ void infer_layer(const bf16* __restrict__ A, const bf16* __restrict__ W, int c0, int lane,
-                                            f32x4 (&acc)[4][kRT]) {
+                                            f32x4 (&acc)[CT][kRT]) {
     const int li = lane & 15, lk = (lane >> 4) * 8;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
         for (int rt = 0; rt < kRT; ++rt) acc[ct][rt] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 wv[4];
+        bf16x8 wv[CT];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) wv[ct] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(c0 + ct * 16 + li) * K + k0 + lk);
+        for (int ct = 0; ct < CT; ++ct)
+            wv[ct] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(c0 + ct * 16 + li) * K + k0 + lk);
 #pragma unroll
         for (int rt = 0; rt < kRT; ++rt) {
             const bf16x8 hv = *reinterpret_cast<const bf16x8*>(A + (rt * 16 + li) * LDA + k0 + lk);
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[ct], hv, acc[ct][rt], 0, 0, 0);
+            for (int ct = 0; ct < CT; ++ct)
+                acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[ct], hv, acc[ct][rt], 0, 0, 0);
         }
     }
 }
 
 // H = bf16(GELU(acc + bias)) for this wave's columns: four consecutive
 // columns of one row per lane and block (one 8-byte LDS write)
-__device__ __forceinline__ void infer_store_hidden(const f32x4 (&acc)[4][kRT], const float* __restrict__ bias, bf16* H,
-                                                   int c0, int lane) {
+template <int CT, int LDH>
+__device__ __forceinline__ void infer_store_hidden(const f32x4 (&acc)[CT][kRT], const float* __restrict__ bias,
+                                                   bf16* Hs, int c0, int lane) {
     const int li = lane & 15, cq = (lane >> 4) * 4;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
+    for (int ct = 0; ct < CT; ++ct) {
         const int col = c0 + ct * 16 + cq;
         const float4 b = *reinterpret_cast<const float4*>(bias + col);
 #pragma unroll
@@ -340,58 +367,58 @@ __device__ __forceinline__ void infer_store_hidden(const f32x4 (&acc)[4][kRT], c
             const f32x4 v = acc[ct][rt];
             const bf16x4 h = (bf16x4){(bf16)gelu(v[0] + b.x), (bf16)gelu(v[1] + b.y), (bf16)gelu(v[2] + b.z),
                                       (bf16)gelu(v[3] + b.w)};
-            *reinterpret_cast<bf16x4*>(H + (rt * 16 + li) * kHP + col) = h;
+            *reinterpret_cast<bf16x4*>(Hs + (rt * 16 + li) * LDH + col) = h;
         }
     }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void mlp_infer_kernel(const float2* __restrict__ y, int F, int N, int M,
-                                                        const bf16* __restrict__ W0, const bf16* __restrict__ W1,
-                                                        const bf16* __restrict__ W2, const float* __restrict__ bias0,
-                                                        const float* __restrict__ bias1,
-                                                        const float* __restrict__ bias2, const float* __restrict__ w4,
-                                                        const float* __restrict__ b4, float* __restrict__ v0) {
+template <int H>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void mlp_infer_kernel(
+    const float2* __restrict__ y, int F, int N, int M, const bf16* __restrict__ W0, const bf16* __restrict__ W1,
+    const bf16* __restrict__ W2, const float* __restrict__ bias0, const float* __restrict__ bias1,
+    const float* __restrict__ bias2, const float* __restrict__ w4, const float* __restrict__ b4,
+    float* __restrict__ v0) {
+    constexpr int CT = H / 64;
+    using Sh = InferShared<H>;
     extern __shared__ __align__(16) unsigned char smem[];
-    InferShared& sh = *reinterpret_cast<InferShared*>(smem);
+    Sh& sh = *reinterpret_cast<Sh*>(smem);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t FN = (int64_t)F * N;
     const int64_t r0 = (int64_t)blockIdx.x * kTile;
     if (tid < kTile) {
         const int64_t bin = r0 + tid;
-        float feat[kKP];
+        bf16* xr = sh.X + tid * kXP;
         float s = 0.0f;
         if (bin < FN) {
             const int f = (int)(bin / N);
             const float2* yb = y + bin * M;
-            bin_features(yb, M, F > 1 ? (float)f / (float)(F - 1) : 0.0f, feat);
+            bin_features(yb, M, F > 1 ? (float)f / (float)(F - 1) : 0.0f, xr);
             float p = 0.0f;
             for (int m = 0; m < M; ++m) p += yb[m].x * yb[m].x + yb[m].y * yb[m].y;
             s = fmaxf(2.0f * p / (float)M, 1e-30f);
         } else {
-            for (int j = 0; j < kKP; ++j) feat[j] = 0.0f;
+            for (int j = 0; j < kKP; ++j) xr[j] = (bf16)0.0f;
         }
-#pragma unroll
-        for (int j = 0; j < kKP; ++j) sh.X[tid * kXP + j] = (bf16)feat[j];
         sh.sv[tid] = s;
     }
     __syncthreads();
-    const int c0 = w * 64;
-    f32x4 acc[4][kRT];
-    infer_layer<kKP, kXP>(sh.X, W0, c0, lane, acc);
-    infer_store_hidden(acc, bias0, sh.H, c0, lane);
+    const int c0 = w * 16 * CT;
+    f32x4 acc[CT][kRT];
+    infer_layer<kKP, kXP, CT>(sh.X, W0, c0, lane, acc);
+    infer_store_hidden<CT, Sh::kHP>(acc, bias0, sh.Hs, c0, lane);
     __syncthreads();
-    infer_layer<kHidden, kHP>(sh.H, W1, c0, lane, acc);
-    __syncthreads();  // every wave has read H before it is overwritten
-    infer_store_hidden(acc, bias1, sh.H, c0, lane);
+    infer_layer<H, Sh::kHP, CT>(sh.Hs, W1, c0, lane, acc);
+    __syncthreads();  // every wave has read Hs before it is overwritten
+    infer_store_hidden<CT, Sh::kHP>(acc, bias1, sh.Hs, c0, lane);
     __syncthreads();
-    infer_layer<kHidden, kHP>(sh.H, W2, c0, lane, acc);
-    // output layer: z = sum_c GELU(pre3_c) w4_c, this wave's 64 columns per row
+    infer_layer<H, Sh::kHP, CT>(sh.Hs, W2, c0, lane, acc);
+    // output layer: z = sum_c GELU(pre3_c) w4_c, this wave's columns per row
     const int li = lane & 15, cq = (lane >> 4) * 4;
     float part[kRT];
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) part[rt] = 0.0f;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
+    for (int ct = 0; ct < CT; ++ct) {
         const int col = c0 + ct * 16 + cq;
         const float4 b = *reinterpret_cast<const float4*>(bias2 + col);
         const float4 wc = *reinterpret_cast<const float4*>(w4 + col);
@@ -431,7 +458,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
 
 // ------------------------------------------------------------------ host side
 struct fca_mlp {
-    int M = 0, in_dim = 0, max_batch = 0, ldt = 0;
+    int M = 0, in_dim = 0, hidden = 0, max_batch = 0, ldt = 0;
     hipStream_t stream = nullptr;
     int64_t nparam = 0;
     // fp32 master parameters, gradients, Adam moments (one allocation each, flat)
@@ -444,7 +471,7 @@ struct fca_mlp {
     bf16 *H[kLayers] = {}, *HT[kLayers] = {};
     bf16 *D = nullptr, *DT = nullptr, *D2 = nullptr, *D2T = nullptr;
     float *dz = nullptr, *r = nullptr;
-    float* ogpart = nullptr;  // [max_batch / 64 + 1][257] partial sums of the output-layer gradient
+    float* ogpart = nullptr;  // [max_batch / 64 + 1][H + 1] partial sums of the output-layer gradient
     double* loss_terms = nullptr;
     int64_t step = 0;
     std::string err;
@@ -478,13 +505,13 @@ void mlp_free(fca_mlp* m) {
     }
 }
 
-int layer_in(int l) { return l == 0 ? kKP : kHidden; }
+int layer_in(const fca_mlp* m, int l) { return l == 0 ? kKP : m->hidden; }
 
 hipError_t refresh_weights(fca_mlp* m) {
     for (int l = 0; l < kLayers; ++l) {
-        const int64_t cnt = (int64_t)kHidden * layer_in(l);
-        mlp_weight_copy_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, m->stream>>>(m->p + m->off_W[l], kHidden,
-                                                                                      layer_in(l), m->Wb[l], m->WTb[l]);
+        const int64_t cnt = (int64_t)m->hidden * layer_in(m, l);
+        mlp_weight_copy_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, m->stream>>>(
+            m->p + m->off_W[l], m->hidden, layer_in(m, l), m->Wb[l], m->WTb[l]);
     }
     return hipGetLastError();
 }
@@ -505,10 +532,10 @@ hipError_t forward(fca_mlp* m, const float2* y, const float* fpos, int n) {
         a.A = in;
         a.B = m->Wb[l];
         a.rows = n;
-        a.cols = kHidden;
-        a.K = layer_in(l);
-        a.lda = layer_in(l);
-        a.ldb = layer_in(l);
+        a.cols = m->hidden;
+        a.K = layer_in(m, l);
+        a.lda = layer_in(m, l);
+        a.ldb = layer_in(m, l);
         a.bias = m->p + m->off_b[l];
         a.out_f32 = m->pre[l];
         a.out_bf = m->H[l];
@@ -519,6 +546,18 @@ hipError_t forward(fca_mlp* m, const float2* y, const float* fpos, int n) {
         in = m->H[l];
     }
     return hipSuccess;
+}
+
+template <int H>
+hipError_t launch_infer(const fca_mlp* m, const float* y, int F, int N, int64_t tiles, float* v0) {
+    static_assert(sizeof(InferShared<H>) <= 160 * 1024, "LDS of the fused inference kernel");
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_infer_kernel<H>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(InferShared<H>));
+    if (e != hipSuccess) return e;
+    mlp_infer_kernel<H><<<(unsigned)tiles, 256, sizeof(InferShared<H>), m->stream>>>(
+        reinterpret_cast<const float2*>(y), F, N, m->M, m->Wb[0], m->Wb[1], m->Wb[2], m->p + m->off_b[0],
+        m->p + m->off_b[1], m->p + m->off_b[2], m->p + m->off_W[kLayers], m->p + m->off_b[kLayers], v0);
+    return hipGetLastError();
 }
 
 #define MLP_HIP(m, call)                                                            \
@@ -534,16 +573,21 @@ hipError_t forward(fca_mlp* m, const float2* y, const float* fpos, int n) {
 
 extern "C" {
 
-fca_status fca_mlp_create(int32_t M, uint64_t seed, int32_t max_batch, void* stream, fca_mlp** out) {
+fca_status fca_mlp_create(int32_t M, int32_t hidden, uint64_t seed, int32_t max_batch, void* stream, fca_mlp** out) {
     if (!out) return FCA_E_ARG;
     *out = nullptr;
     if (M < 2 || M > fca::kMaxM || max_batch < 64 || max_batch % 64 != 0) {
         g_mlp_error = "fca_mlp_create: need 2 <= M <= 8 and max_batch a positive multiple of 64";
         return FCA_E_ARG;
     }
+    if (hidden != 64 && hidden != 128 && hidden != kMaxHidden) {
+        g_mlp_error = "fca_mlp_create: hidden width must be 64, 128 or 256";
+        return FCA_E_ARG;
+    }
     fca_mlp* m = new (std::nothrow) fca_mlp();
     if (!m) return FCA_E_NOMEM;
     m->M = M;
+    m->hidden = hidden;
     m->in_dim = 3 * M - 1;
     m->max_batch = max_batch;
     m->ldt = max_batch;
@@ -551,27 +595,27 @@ fca_status fca_mlp_create(int32_t M, uint64_t seed, int32_t max_batch, void* str
     int64_t o = 0;
     for (int l = 0; l < kLayers; ++l) {
         m->off_W[l] = o;
-        o += (int64_t)kHidden * layer_in(l);
+        o += (int64_t)hidden * layer_in(m, l);
         m->off_b[l] = o;
-        o += kHidden;
+        o += hidden;
     }
     m->off_W[kLayers] = o;
-    o += kHidden;
+    o += hidden;
     m->off_b[kLayers] = o;
     o += 1;
     m->nparam = o;
     bool ok = mlp_alloc(&m->p, o * 4) && mlp_alloc(&m->g, o * 4) && mlp_alloc(&m->m1, o * 4) &&
               mlp_alloc(&m->m2, o * 4);
     for (int l = 0; l < kLayers && ok; ++l)
-        ok = mlp_alloc(&m->Wb[l], (size_t)kHidden * layer_in(l) * 2) &&
-             mlp_alloc(&m->WTb[l], (size_t)kHidden * layer_in(l) * 2) &&
-             mlp_alloc(&m->pre[l], (size_t)max_batch * kHidden * 4) &&
-             mlp_alloc(&m->H[l], (size_t)max_batch * kHidden * 2) && mlp_alloc(&m->HT[l], (size_t)max_batch * kHidden * 2);
+        ok = mlp_alloc(&m->Wb[l], (size_t)hidden * layer_in(m, l) * 2) &&
+             mlp_alloc(&m->WTb[l], (size_t)hidden * layer_in(m, l) * 2) &&
+             mlp_alloc(&m->pre[l], (size_t)max_batch * hidden * 4) &&
+             mlp_alloc(&m->H[l], (size_t)max_batch * hidden * 2) && mlp_alloc(&m->HT[l], (size_t)max_batch * hidden * 2);
     ok = ok && mlp_alloc(&m->X, (size_t)max_batch * kKP * 2) && mlp_alloc(&m->XT, (size_t)max_batch * kKP * 2) &&
-         mlp_alloc(&m->D, (size_t)max_batch * kHidden * 2) && mlp_alloc(&m->DT, (size_t)max_batch * kHidden * 2) &&
-         mlp_alloc(&m->D2, (size_t)max_batch * kHidden * 2) && mlp_alloc(&m->D2T, (size_t)max_batch * kHidden * 2) &&
+         mlp_alloc(&m->D, (size_t)max_batch * hidden * 2) && mlp_alloc(&m->DT, (size_t)max_batch * hidden * 2) &&
+         mlp_alloc(&m->D2, (size_t)max_batch * hidden * 2) && mlp_alloc(&m->D2T, (size_t)max_batch * hidden * 2) &&
          mlp_alloc(&m->dz, (size_t)max_batch * 4) && mlp_alloc(&m->r, (size_t)max_batch * 4) &&
-         mlp_alloc(&m->ogpart, (size_t)(max_batch / kOgRows + 1) * (kHidden + 1) * 4) &&
+         mlp_alloc(&m->ogpart, (size_t)(max_batch / kOgRows + 1) * (hidden + 1) * 4) &&
          mlp_alloc(&m->loss_terms, (size_t)max_batch * 8);
     if (!ok) {
         mlp_free(m);
@@ -585,13 +629,13 @@ fca_status fca_mlp_create(int32_t M, uint64_t seed, int32_t max_batch, void* str
     std::mt19937_64 rng(seed);
     std::normal_distribution<float> nd(0.0f, 1.0f);
     for (int l = 0; l < kLayers; ++l) {
-        const int fan_in = l == 0 ? m->in_dim : kHidden;
+        const int fan_in = l == 0 ? m->in_dim : hidden;
         const float sd = std::sqrt(2.0f / fan_in);
-        for (int r = 0; r < kHidden; ++r)
-            for (int c = 0; c < layer_in(l); ++c)
-                h[m->off_W[l] + (int64_t)r * layer_in(l) + c] = (c < fan_in) ? sd * nd(rng) : 0.0f;
+        for (int r = 0; r < hidden; ++r)
+            for (int c = 0; c < layer_in(m, l); ++c)
+                h[m->off_W[l] + (int64_t)r * layer_in(m, l) + c] = (c < fan_in) ? sd * nd(rng) : 0.0f;
     }
-    for (int c = 0; c < kHidden; ++c) h[m->off_W[kLayers] + c] = std::sqrt(1.0f / kHidden) * nd(rng);
+    for (int c = 0; c < hidden; ++c) h[m->off_W[kLayers] + c] = std::sqrt(1.0f / hidden) * nd(rng);
     if (hipMemcpy(m->p, h.data(), o * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(m->m1, 0, o * 4) != hipSuccess || hipMemset(m->m2, 0, o * 4) != hipSuccess ||
         hipMemset(m->g, 0, o * 4) != hipSuccess || refresh_weights(m) != hipSuccess ||
@@ -639,7 +683,8 @@ fca_status fca_mlp_forward(fca_mlp* m, const float* y, const float* fpos, int32_
     }
     MLP_HIP(m, forward(m, reinterpret_cast<const float2*>(y), fpos, n));
     mlp_out_kernel<<<(n + 3) / 4, 256, 0, m->stream>>>(m->pre[kLayers - 1], m->p + m->off_W[kLayers],
-                                                      m->p + m->off_b[kLayers], n, r_out, nullptr, nullptr, nullptr);
+                                                      m->p + m->off_b[kLayers], n, m->hidden, r_out, nullptr, nullptr,
+                                                      nullptr);
     MLP_HIP(m, hipGetLastError());
     MLP_HIP(m, hipStreamSynchronize(m->stream));
     return FCA_OK;
@@ -654,13 +699,14 @@ fca_status fca_mlp_backward(fca_mlp* m, const float* y, const float* fpos, const
     const hipStream_t s = m->stream;
     MLP_HIP(m, forward(m, reinterpret_cast<const float2*>(y), fpos, n));
     const float* w4 = m->p + m->off_W[kLayers];
-    mlp_out_kernel<<<(n + 3) / 4, 256, 0, s>>>(m->pre[kLayers - 1], w4, m->p + m->off_b[kLayers], n, m->r, target,
+    const int hid = m->hidden;
+    mlp_out_kernel<<<(n + 3) / 4, 256, 0, s>>>(m->pre[kLayers - 1], w4, m->p + m->off_b[kLayers], n, hid, m->r, target,
                                                m->dz, m->loss_terms);
     const int ogb = (n + kOgRows - 1) / kOgRows;
-    mlp_out_grad_part_kernel<<<ogb, 256, 0, s>>>(m->pre[kLayers - 1], m->dz, n, m->ogpart);
-    mlp_out_grad_sum_kernel<<<1, 256, 0, s>>>(m->ogpart, ogb, m->g + m->off_W[kLayers], m->g + m->off_b[kLayers]);
-    mlp_out_back_kernel<<<(unsigned)(((int64_t)n * kHidden + 255) / 256), 256, 0, s>>>(m->pre[kLayers - 1], w4, m->dz,
-                                                                                      n, m->D, m->DT, m->ldt);
+    mlp_out_grad_part_kernel<<<ogb, hid, 0, s>>>(m->pre[kLayers - 1], m->dz, n, m->ogpart);
+    mlp_out_grad_sum_kernel<<<1, hid, 0, s>>>(m->ogpart, ogb, m->g + m->off_W[kLayers], m->g + m->off_b[kLayers]);
+    mlp_out_back_kernel<<<(unsigned)(((int64_t)n * hid + 255) / 256), 256, 0, s>>>(m->pre[kLayers - 1], w4, m->dz, n,
+                                                                                  hid, m->D, m->DT, m->ldt);
     MLP_HIP(m, hipGetLastError());
     bf16 *dcur = m->D, *dcurT = m->DT, *dnext = m->D2, *dnextT = m->D2T;
     for (int l = kLayers - 1; l >= 0; --l) {
@@ -668,14 +714,14 @@ fca_status fca_mlp_backward(fca_mlp* m, const float* y, const float* fpos, const
         GemmArgs gw{};
         gw.A = dcurT;
         gw.B = l > 0 ? m->HT[l - 1] : m->XT;
-        gw.rows = kHidden;
-        gw.cols = layer_in(l);
+        gw.rows = hid;
+        gw.cols = layer_in(m, l);
         gw.K = n;
         gw.lda = m->ldt;
         gw.ldb = m->ldt;
         gw.out_f32 = m->g + m->off_W[l];
         MLP_HIP(m, gemm<kEpiStore>(s, gw));
-        mlp_bias_grad_kernel<<<kHidden, 256, 0, s>>>(dcurT, n, m->ldt, m->g + m->off_b[l]);
+        mlp_bias_grad_kernel<<<hid, 256, 0, s>>>(dcurT, n, m->ldt, m->g + m->off_b[l]);
         MLP_HIP(m, hipGetLastError());
         if (l > 0) {
             // d_prev[b][i] = (sum_o d[b][o] W[o][i]) GELU'(pre_prev[b][i])  (B = W^T)
@@ -683,10 +729,10 @@ fca_status fca_mlp_backward(fca_mlp* m, const float* y, const float* fpos, const
             gd.A = dcur;
             gd.B = m->WTb[l];
             gd.rows = n;
-            gd.cols = layer_in(l);
-            gd.K = kHidden;
-            gd.lda = kHidden;
-            gd.ldb = kHidden;
+            gd.cols = layer_in(m, l);
+            gd.K = hid;
+            gd.lda = hid;
+            gd.ldb = hid;
             gd.pre = m->pre[l - 1];
             gd.out_bf = dnext;
             gd.out_bfT = dnextT;
@@ -730,13 +776,13 @@ fca_status fca_mlp_init_powers(fca_mlp* m, const float* y, int32_t F, int32_t N,
         m->err = "fca_mlp_init_powers: too many bins";
         return FCA_E_ARG;
     }
-    static_assert(sizeof(InferShared) <= 160 * 1024, "LDS of the fused inference kernel");
-    MLP_HIP(m, hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_infer_kernel),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(InferShared)));
-    mlp_infer_kernel<<<(unsigned)tiles, 256, sizeof(InferShared), s>>>(
-        reinterpret_cast<const float2*>(y), F, N, m->M, m->Wb[0], m->Wb[1], m->Wb[2], m->p + m->off_b[0],
-        m->p + m->off_b[1], m->p + m->off_b[2], m->p + m->off_W[kLayers], m->p + m->off_b[kLayers], v0_out);
-    MLP_HIP(m, hipGetLastError());
+    hipError_t e;
+    switch (m->hidden) {
+        case 64: e = launch_infer<64>(m, y, F, N, tiles, v0_out); break;
+        case 128: e = launch_infer<128>(m, y, F, N, tiles, v0_out); break;
+        default: e = launch_infer<kMaxHidden>(m, y, F, N, tiles, v0_out); break;
+    }
+    MLP_HIP(m, e);
     MLP_HIP(m, hipStreamSynchronize(s));
     return FCA_OK;
 }

@@ -85,7 +85,7 @@ def lib() -> ctypes.CDLL:
         L.fca_autotune.argtypes = [vp, i32]
         L.fca_graph_capture.argtypes = [vp, i32, i32, vp, vp, vp, vp]
         L.fca_graph_launch.argtypes = [vp, i32]
-        L.fca_mlp_create.argtypes = [i32, ctypes.c_uint64, i32, vp, ctypes.POINTER(vp)]
+        L.fca_mlp_create.argtypes = [i32, i32, ctypes.c_uint64, i32, vp, ctypes.POINTER(vp)]
         L.fca_mlp_destroy.argtypes = [vp]
         L.fca_mlp_destroy.restype = None
         L.fca_mlp_num_params.argtypes = [vp]
@@ -377,12 +377,13 @@ def fca_graph_launch(graph: Graph, count: int = 1, allow_flags=False):
 class Mlp:
     """Handle of an fca_mlp (per-bin network predicting v1 / (v1 + v2))."""
 
-    def __init__(self, M: int, seed: int = 0, max_batch: int = 8192, device=None):
+    def __init__(self, M: int, seed: int = 0, max_batch: int = 8192, device=None, hidden: int = 256):
         self.device = torch.device(device or "cuda:0")
         self.M = M
+        self.hidden = hidden
         self.max_batch = max_batch
         h = ctypes.c_void_p()
-        st = lib().fca_mlp_create(M, seed, max_batch, _stream_handle(self.device), ctypes.byref(h))
+        st = lib().fca_mlp_create(M, hidden, seed, max_batch, _stream_handle(self.device), ctypes.byref(h))
         if st != FCA_OK:
             raise FcaError(st, lib().fca_mlp_last_error(None).decode())
         self.handle = h.value
@@ -404,8 +405,8 @@ class Mlp:
             pass
 
 
-def fca_mlp_create(M: int, seed: int = 0, max_batch: int = 8192) -> Mlp:
-    return Mlp(M, seed, max_batch)
+def fca_mlp_create(M: int, seed: int = 0, max_batch: int = 8192, hidden: int = 256) -> Mlp:
+    return Mlp(M, seed, max_batch, hidden=hidden)
 
 
 def fca_mlp_destroy(m: Mlp):

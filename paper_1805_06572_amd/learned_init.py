@@ -15,9 +15,10 @@ from . import fca, synth
 
 
 def train(M: int = 4, F: int = 513, steps: int = 400, batch: int = 8192, lr: float = 1e-3,
-          weight_decay: float = 1e-4, seed: int = 0, chunk_steps: int = 50, log=None):
-    """Train a network for M microphones; returns (Mlp, list of batch losses)."""
-    net = fca.Mlp(M, seed=seed, max_batch=batch)
+          weight_decay: float = 1e-4, seed: int = 0, chunk_steps: int = 50, log=None, hidden: int = 256):
+    """Train a network of hidden width `hidden` for M microphones; returns
+    (Mlp, list of batch losses)."""
+    net = fca.Mlp(M, seed=seed, max_batch=batch, hidden=hidden)
     rng = np.random.default_rng(10_000 + seed)
     losses = []
     step = 0

@@ -24,23 +24,25 @@ def fca():
     return mod
 
 
-def blocks(p):
-    """Split a flat parameter vector into its named blocks."""
+def blocks(p, H):
+    """Split a flat parameter vector (hidden width H) into its named blocks."""
     out, o = {}, 0
     for l in range(3):
-        fan = 32 if l == 0 else 256
-        out[f"W{l + 1}"] = p[o:o + 256 * fan]
-        o += 256 * fan
-        out[f"b{l + 1}"] = p[o:o + 256]
-        o += 256
-    out["w4"] = p[o:o + 256]
-    out["b4"] = p[o + 256:o + 257]
+        fan = 32 if l == 0 else H
+        out[f"W{l + 1}"] = p[o:o + H * fan]
+        o += H * fan
+        out[f"b{l + 1}"] = p[o:o + H]
+        o += H
+    out["w4"] = p[o:o + H]
+    out["b4"] = p[o + H:o + H + 1]
+    assert o + H + 1 == p.size
     return out
 
 
-@pytest.mark.parametrize("M", [2, 4, 8])
-def test_forward_matches_reference(fca, M):
-    net = fca.Mlp(M, seed=3, max_batch=1024)
+@pytest.mark.parametrize("M,H", [(2, 256), (4, 256), (8, 256), (4, 64), (8, 128)])
+def test_forward_matches_reference(fca, M, H):
+    net = fca.Mlp(M, seed=3, max_batch=1024, hidden=H)
+    assert net.num_params == ref.num_params(H)
     rng = np.random.default_rng(M)
     y, fpos, r = synth.array_bins(1000, M, 513, rng)
     got = fca.fca_mlp_forward(net, y, fpos).cpu().numpy()
@@ -50,22 +52,28 @@ def test_forward_matches_reference(fca, M):
     assert np.corrcoef(got, want)[0, 1] > 0.99
 
 
-def test_backward_matches_reference(fca):
+@pytest.mark.parametrize("H", [256, 64])
+def test_backward_matches_reference(fca, H):
     M = 4
-    net = fca.Mlp(M, seed=5, max_batch=2048)
+    net = fca.Mlp(M, seed=5, max_batch=2048, hidden=H)
     rng = np.random.default_rng(11)
     y, fpos, r = synth.array_bins(1024, M, 513, rng)
     loss, g = fca.fca_mlp_backward(net, y, fpos, r, want_grads=True)
     p = ref.bf16_round(fca.fca_mlp_get_params(net))
     want_loss, want_g = ref.loss_and_grad(p, ref.features(y, fpos), r.astype(np.float64))
     assert abs(loss - want_loss) < 1e-2 * abs(want_loss)
-    gb, wb = blocks(g.astype(np.float64)), blocks(want_g)
+    gb, wb = blocks(g.astype(np.float64), H), blocks(want_g, H)
     for name in gb:
         err = np.linalg.norm(gb[name] - wb[name]) / max(np.linalg.norm(wb[name]), 1e-30)
         assert err < 5e-2, (name, err)
     # the padded input columns of the first layer get no gradient
-    W1 = gb["W1"].reshape(256, 32)
+    W1 = gb["W1"].reshape(H, 32)
     assert np.all(W1[:, 3 * M - 1:] == 0)
+
+
+def test_invalid_hidden_width_is_rejected(fca):
+    with pytest.raises(fca.FcaError, match="hidden width"):
+        fca.Mlp(4, hidden=96, max_batch=256)
 
 
 def test_parameters_round_trip(fca):
@@ -133,13 +141,14 @@ def test_batched_start_choice_and_per_mixture_stop(fca):
         np.testing.assert_array_equal(np.asarray(hist[k]), ll.cpu().numpy()[0])
 
 
-@pytest.mark.parametrize("M,F,N", [(4, 33, 300), (2, 5, 61), (8, 17, 130)])
-def test_fused_learned_start_matches_forward_and_reference(fca, M, F, N):
+@pytest.mark.parametrize("M,F,N,H", [(4, 33, 300, 256), (2, 5, 61, 256), (8, 17, 130, 256), (4, 33, 300, 64),
+                                     (8, 17, 130, 64), (3, 9, 77, 128)])
+def test_fused_learned_start_matches_forward_and_reference(fca, M, F, N, H):
     """fca_mlp_init_powers (one fused kernel per mixture, tiles of 128 bins
     with a ragged tail) against the training-path forward on the same bins
     (same BF16 GEMMs; only the output-layer sum order differs) and against
     the FP64 reference network."""
-    net = fca.Mlp(M, seed=7, max_batch=4096)
+    net = fca.Mlp(M, seed=7, max_batch=4096, hidden=H)
     mx = synth.array_mixture(M, F, N, seed=300 + M, complex64=True)
     y = torch.from_numpy(mx.y).cuda()
     v0 = fca.fca_mlp_init_powers(net, y).cpu().numpy().astype(np.float64)

@@ -4,21 +4,24 @@ map on a hand-checked bin."""
 from __future__ import annotations
 
 import numpy as np
+import pytest
 
 from oracle import mlp
 from paper_1805_06572_amd import synth
 
 
-def small_params(rng):
-    n_par = 256 * 32 + 256 + 2 * (256 * 256 + 256) + 256 + 1
+def small_params(rng, H=256):
+    n_par = H * 32 + H + 2 * (H * H + H) + H + 1
     p = rng.standard_normal(n_par) * 0.05
     Ws, bs, w4, b4 = mlp.unpack(p)
+    assert [W.shape for W in Ws] == [(H, 32), (H, H), (H, H)] and w4.shape == (H,)
     return p
 
 
-def test_gradient_matches_finite_differences():
+@pytest.mark.parametrize("H", [256, 64])
+def test_gradient_matches_finite_differences(H):
     rng = np.random.default_rng(0)
-    p = small_params(rng)
+    p = small_params(rng, H)
     y, fpos, r = synth.array_bins(16, 4, 513, rng)
     X = mlp.features(y, fpos)
     L, g = mlp.loss_and_grad(p, X, r.astype(np.float64))
@@ -54,3 +57,10 @@ def test_bf16_rounding_is_nearest_even():
     b = mlp.bf16_round(a)
     np.testing.assert_array_equal(b[:3], [1.0, 1.0, 1.0 + 2 ** -6])
     assert abs(b[3] - 3.140625) < 1e-7
+
+
+def test_parameter_count_names_one_width():
+    for H in (64, 128, 256):
+        assert mlp.hidden_width(mlp.num_params(H)) == H
+    with pytest.raises(ValueError):
+        mlp.hidden_width(mlp.num_params(64) + 1)
