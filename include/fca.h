@@ -283,7 +283,10 @@ fca_status fca_mlp_backward(fca_mlp *m, const float *y, const float *fpos, const
 /* one AdamW step with the last gradient (bias-corrected moments) */
 fca_status fca_mlp_adamw(fca_mlp *m, float lr, float beta1, float beta2, float eps, float weight_decay);
 /* learned start for a mixture y [F][N][M] complex64 (contiguous, device):
- * v0_out [2][F][N] float (device), usable as fca_problem.v0 */
+ * v0_out [2][F][N] float (device), usable as fca_problem.v0. One fused
+ * kernel, enqueued on the network's stream without waiting: v0_out is
+ * complete in that stream's order (a context created on the same stream
+ * may take it at once; other users synchronise first). */
 fca_status fca_mlp_init_powers(fca_mlp *m, const float *y, int32_t F, int32_t N, float *v0_out);
 
 #ifdef __cplusplus

@@ -769,7 +769,6 @@ fca_status fca_mlp_adamw(fca_mlp* m, float lr, float beta1, float beta2, float e
 
 fca_status fca_mlp_init_powers(fca_mlp* m, const float* y, int32_t F, int32_t N, float* v0_out) {
     if (!m || !y || !v0_out || F < 1 || N < 1) return FCA_E_ARG;
-    const hipStream_t s = m->stream;
     const int64_t FN = (int64_t)F * N;
     const int64_t tiles = (FN + kTile - 1) / kTile;
     if (tiles > INT32_MAX) {
@@ -783,7 +782,6 @@ fca_status fca_mlp_init_powers(fca_mlp* m, const float* y, int32_t F, int32_t N,
         default: e = launch_infer<kMaxHidden>(m, y, F, N, tiles, v0_out); break;
     }
     MLP_HIP(m, e);
-    MLP_HIP(m, hipStreamSynchronize(s));
     return FCA_OK;
 }
 

@@ -383,7 +383,8 @@ class Mlp:
         self.hidden = hidden
         self.max_batch = max_batch
         h = ctypes.c_void_p()
-        st = lib().fca_mlp_create(M, hidden, seed, max_batch, _stream_handle(self.device), ctypes.byref(h))
+        self.stream = _stream_handle(self.device)
+        st = lib().fca_mlp_create(M, hidden, seed, max_batch, self.stream, ctypes.byref(h))
         if st != FCA_OK:
             raise FcaError(st, lib().fca_mlp_last_error(None).decode())
         self.handle = h.value
@@ -470,4 +471,6 @@ def fca_mlp_init_powers(m: Mlp, y) -> torch.Tensor:
     F, N, M = y.shape
     v0 = torch.empty((2, F, N), dtype=torch.float32, device=y.device)
     m._check(lib().fca_mlp_init_powers(m.handle, y.data_ptr(), F, N, v0.data_ptr()))
+    if torch.cuda.current_stream(y.device).cuda_stream != m.stream:
+        torch.cuda.synchronize(y.device)  # the kernel ran on the network's stream
     return v0
