@@ -282,13 +282,28 @@ def run_large(args):
     del gen
     torch.cuda.synchronize()
     run = Runner(fca, ys, L, fca.FCA_FP32_BULK)
+    learned = None
+    if args.learned_large:
+        # learned start per mixture (M=8 network of width 64), kept where the
+        # EM rates it above the plain start at iteration 0
+        from paper_1805_06572_amd import learned_init
+        t0 = time.perf_counter()
+        net, _ = learned_init.train(M=M, F=F, steps=args.train_steps // 2, batch=8192, seed=0, hidden=64)
+        train_s = time.perf_counter() - t0
+        chosen, ll_p, ll_l = learned_init.choose_starts(net, run.ctx, ys)
+        v0_mix0 = fca.fca_mlp_init_powers(net, ys[0]) if chosen[0] else None
+        net.close()
+        learned = {"hidden": 64, "train_steps": args.train_steps // 2, "train_s": train_s,
+                   "learned_start_chosen": int(chosen.sum()),
+                   "ll0_gain_where_chosen": float((ll_l - ll_p)[chosen].sum())}
     ms_step, em_ms = run.timed(args.steps, args.warmup)
     flags = fca.fca_status_per_freq(run.ctx)
     run_R, run_v = run.R, run.v
     run.close()
     updates = B * F * N * L
     rec = base_record(args, updates / (ms_step * 1e-3), ms_step,
-                      {"workload": f"{B} array mixtures, M={M}, F={F}, N={N}, {L} EM iterations, plain start "
+                      {"workload": f"{B} array mixtures, M={M}, F={F}, N={N}, {L} EM iterations, "
+                                   f"{'learned start with plain fallback' if learned else 'plain start'} "
                                    "(frames streamed from memory every pass)",
                        "mixtures": B, "M": M, "F": F, "N": N, "iterations": L,
                        "precision": "f32 per-bin arithmetic; f64 eigendecomposition and sums"})
@@ -297,6 +312,8 @@ def run_large(args):
                                      "em_stream_kernel (frames re-read every iteration)")
     rec["roofline"]["hbm_frac"] = rec["roofline"]["hbm_equivalent_GBps"] / PEAK_HBM_GBS
     rec["flagged_frequencies"] = int((flags != 0).sum())
+    if learned:
+        rec["learned_start"] = learned
     # error against the FP64 oracle on a subsample: mixture 0, 8 evenly spaced
     # frequencies (each frequency is an independent EM problem), same start and
     # iteration count; the oracle run is also the CPU baseline
@@ -305,6 +322,8 @@ def run_large(args):
     idx = np.linspace(0, F - 1, 8).round().astype(int)
     y64 = np.ascontiguousarray(ys[0].cpu().numpy().astype(np.complex128)[idx])
     S0, v0 = oracle.default_init(y64)
+    if learned and v0_mix0 is not None:
+        v0 = np.ascontiguousarray(v0_mix0.cpu().numpy().astype(np.float64)[:, idx])
     cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
     t0 = time.perf_counter()
     S, v, ll, oflags = oracle.em(y64, S0, v0, L, threads=cores)
@@ -318,7 +337,8 @@ def run_large(args):
     kappa = synth.condition_numbers(R_true0[:, idx])
     good = kappa <= 1e3
     rec["oracle_error_subsample"] = {
-        "sample": f"mixture 0, frequencies {idx.tolist()}, all {N} frames, {L} iterations, same plain start",
+        "sample": f"mixture 0, frequencies {idx.tolist()}, all {N} frames, {L} iterations, same start "
+                  f"({'learned' if learned and v0_mix0 is not None else 'plain'})",
         "kappa_R_true": [float(k) for k in kappa],
         "v_rel_err": [float(e) for e in ev], "R_rel_err": [float(e) for e in eR],
         "v_rel_err_max_kappa_le_1e3": float(ev[good].max()) if good.any() else None,
@@ -453,8 +473,10 @@ def main():
     ap.add_argument("--M", type=int, default=4)
     ap.add_argument("--F", type=int, default=513)
     ap.add_argument("--N", type=int, default=1000)
-    ap.add_argument("--mixtures", type=int, default=16)
+    ap.add_argument("--mixtures", type=int, default=256, help="time-to-target: held-out mixtures")
     ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--plain-large", dest="learned_large", action="store_false",
+                    help="large workload: plain start only (no learned start)")
     ap.add_argument("--hidden", default="64,256",
                     help="time-to-target: hidden widths of the learned-start networks (the first one is the "
                          "headline)")
