@@ -138,10 +138,19 @@ __device__ __forceinline__ void em_bin_front(const T (&yr)[M], const T (&yi)[M],
         quad = fma(e[i], r[i], quad);
     }
     T logd = T(0);
+    if constexpr (sizeof(T) == 4) {
+        // sum of the hardware log2 of each d_i (normal positive floats), one
+        // scaling by ln 2
+        float l2 = 0.0f;
 #pragma unroll
-    for (int i = 0; i < M; i += 2) {
-        const T pd = (i + 1 < M) ? d[i] * d[i + 1] : d[i];
-        logd += MT::log(pd);
+        for (int i = 0; i < M; ++i) l2 += __builtin_amdgcn_logf(d[i]);
+        logd = l2 * 0.69314718055994531f;
+    } else {
+#pragma unroll
+        for (int i = 0; i < M; i += 2) {
+            const T pd = (i + 1 < M) ? d[i] * d[i + 1] : d[i];
+            logd += MT::log(pd);
+        }
     }
     // v1' = (v1/M) sum r_i (v1 lam_i e_i r_i + v2), v2' = (v2/M) sum r_i (v2 e_i r_i + v1 lam_i)
     T s1 = T(0), s2 = T(0);
