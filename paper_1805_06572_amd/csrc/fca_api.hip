@@ -36,6 +36,7 @@ struct MixInfo {
     int64_t out_x;    // complex elements into a batch x_out
     int pid0;         // first problem index (b * F)
     bool has_v0;
+    bool R_default;   // R_init holds the plain start (no launch needed to restore it)
 };
 
 // A launch group: problems of equal M and frames-per-thread class (fpt for
@@ -74,6 +75,8 @@ struct fca_ctx {
     double* ll = nullptr;
     double* ll_tot = nullptr;
     double* ll_host = nullptr;  // pinned
+    int* flag_sum = nullptr;       // device: OR of the flags, first NOT_PD, first NONFINITE
+    int* flag_sum_host = nullptr;  // pinned copy
     double* fsum = nullptr;
     double2* R_stage = nullptr;
     EmProblem* probs = nullptr;
@@ -85,7 +88,8 @@ struct fca_ctx {
     // the problems of active mixtures only (probs_act, groups_act; used by the
     // EM calls while some mixture is inactive), rebuilt lazily.
     std::vector<EmProblem> table;
-    std::vector<EmProblem> table_act;
+    EmProblem* table_act = nullptr;  // pinned host staging of probs_act (nprob entries)
+    hipEvent_t table_ev = nullptr;   // the last upload from table_act
     EmProblem* probs_act = nullptr;
     std::vector<Group> groups_act;
     std::vector<char> active;
@@ -161,10 +165,13 @@ fca_status dev_alloc(fca_ctx* c, P** p, size_t bytes) {
 
 void free_ctx_memory(fca_ctx* c) {
     void* dev[] = {c->y, c->v, c->v_init, c->R_init, c->P, c->Pinv, c->lam, c->logdet, c->flags, c->ll,
-                   c->ll_tot, c->fsum, c->R_stage, c->probs, c->x_off, c->probs_act};
+                   c->ll_tot, c->fsum, c->R_stage, c->probs, c->x_off, c->probs_act, c->flag_sum};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->ll_host) (void)hipHostFree(c->ll_host);
+    if (c->flag_sum_host) (void)hipHostFree(c->flag_sum_host);
+    if (c->table_act) (void)hipHostFree(c->table_act);
+    if (c->table_ev) (void)hipEventDestroy(c->table_ev);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -275,47 +282,50 @@ fca_status refresh_active(fca_ctx* c) {
     c->shape_version += 1;
     c->all_active = std::all_of(c->active.begin(), c->active.end(), [](char a) { return a != 0; });
     if (c->all_active) return FCA_OK;
-    c->table_act.clear();
+    FCA_HIP(c, hipEventSynchronize(c->table_ev));  // the previous upload has read the staging buffer
     c->groups_act.clear();
+    int n = 0;
     for (const Group& g : c->groups) {
         Group ga = g;
-        ga.first = (int)c->table_act.size();
+        ga.first = n;
         ga.count = 0;
         ga.max_n = 0;
         for (int i = g.first; i < g.first + g.count; ++i) {
             const EmProblem& e = c->table[i];
             if (!c->active[e.pid / c->F]) continue;
-            c->table_act.push_back(e);
+            c->table_act[n++] = e;
             ga.count += 1;
             ga.max_n = std::max(ga.max_n, (int)e.n);
         }
         if (ga.count) c->groups_act.push_back(ga);
     }
-    if (!c->table_act.empty())
-        FCA_HIP(c, hipMemcpyAsync(c->probs_act, c->table_act.data(), c->table_act.size() * sizeof(EmProblem),
-                                  hipMemcpyHostToDevice, c->stream));
+    if (n) {
+        FCA_HIP(c, hipMemcpyAsync(c->probs_act, c->table_act, (size_t)n * sizeof(EmProblem), hipMemcpyHostToDevice,
+                                  c->stream));
+        FCA_HIP(c, hipEventRecord(c->table_ev, c->stream));
+    }
     return FCA_OK;
 }
 
+// Waits for the stream; FCA_E_NOT_PD (first such problem named) if any
+// problem lost positive definiteness, else FCA_E_NONFINITE if any produced a
+// non-finite value. The flags are summarised on the device (three ints
+// cross to the host).
 fca_status check_flags(fca_ctx* c) {
     const hipStream_t s = c->stream;
-    FCA_HIP(c, hipMemcpyAsync(c->flags_host.data(), c->flags, sizeof(int) * c->nprob,
-                              hipMemcpyDeviceToHost, s));
+    FCA_HIP(c, launch_flag_summary(c->flags, c->nprob, c->flag_sum, s));
+    FCA_HIP(c, hipMemcpyAsync(c->flag_sum_host, c->flag_sum, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     FCA_HIP(c, hipStreamSynchronize(s));
-    fca_status st = FCA_OK;
-    for (int i = 0; i < c->nprob; ++i) {
-        const int f = c->flags_host[i];
-        if (f & kFlagNotPD) {
-            if (st == FCA_OK) set_err(c, "mixture %d, frequency %d lost positive definiteness", i / c->F, i % c->F);
-            st = FCA_E_NOT_PD;
-            break;
-        }
-        if ((f & kFlagNonFinite) && st == FCA_OK) {
-            set_err(c, "mixture %d, frequency %d produced a non-finite value", i / c->F, i % c->F);
-            st = FCA_E_NONFINITE;
-        }
+    const int np = c->flag_sum_host[1], nf = c->flag_sum_host[2];
+    if (np < c->nprob) {
+        set_err(c, "mixture %d, frequency %d lost positive definiteness", np / c->F, np % c->F);
+        return FCA_E_NOT_PD;
     }
-    return st;
+    if (nf < c->nprob) {
+        set_err(c, "mixture %d, frequency %d produced a non-finite value", nf / c->F, nf % c->F);
+        return FCA_E_NONFINITE;
+    }
+    return FCA_OK;
 }
 
 fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
@@ -399,12 +409,33 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     FCA_TRY(dev_alloc(c, &c->probs, (size_t)c->nprob * sizeof(EmProblem)));
     FCA_TRY(dev_alloc(c, &c->probs_act, (size_t)c->nprob * sizeof(EmProblem)));
     FCA_TRY(dev_alloc(c, &c->x_off, (size_t)c->nprob * 2 * sizeof(int64_t)));
+    FCA_TRY(dev_alloc(c, &c->flag_sum, 3 * sizeof(int)));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->ll_host), (size_t)kLChunk * B * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         c->ll_host = nullptr;
         set_err(c, "hipHostMalloc failed");
         FCA_TRY(FCA_E_NOMEM);
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->flag_sum_host), 3 * sizeof(int), hipHostMallocDefault) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        c->flag_sum_host = nullptr;
+        set_err(c, "hipHostMalloc failed");
+        FCA_TRY(FCA_E_NOMEM);
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->table_act), (size_t)c->nprob * sizeof(EmProblem),
+                      hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        c->table_act = nullptr;
+        set_err(c, "hipHostMalloc failed");
+        FCA_TRY(FCA_E_NOMEM);
+    }
+    if (hipEventCreateWithFlags(&c->table_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        c->table_ev = nullptr;
+        set_err(c, "hipEventCreate failed");
+        FCA_TRY(FCA_E_DEVICE);
     }
     auto hipcall = [&](hipError_t e, const char* what) -> fca_status {
         if (e == hipSuccess) return FCA_OK;
@@ -482,6 +513,7 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
         FCA_TRY(ks);
 
         double2* Rb = c->R_init + mi.R_base;
+        mi.R_default = p.R0 == nullptr;
         if (p.R0) {
             FCA_TRY(hipcall(hipMemcpyAsync(Rb, p.R0, 2ull * c->F * mi.M * mi.M * sizeof(double2),
                                            hipMemcpyDefault, s), "hipMemcpyAsync(R0)"));
@@ -569,8 +601,10 @@ fca_status fca_set_start(fca_ctx* c, int32_t b, const double* R0, const void* v0
         }
         if (st != FCA_OK) return st;
         FCA_HIP(c, hipMemcpyAsync(Rb, c->R_stage, rbytes, hipMemcpyDeviceToDevice, s));
-    } else {
+        mi.R_default = false;
+    } else if (!mi.R_default) {
         FCA_HIP(c, launch_default_R(mi.M, c->F, Rb, s));
+        mi.R_default = true;
     }
     if (v0) {
         if (!c->v_init) {

@@ -74,6 +74,10 @@ hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int
 // p[i] = val for count 32-bit words (a kernel, not a memset: graph-capturable).
 hipError_t launch_fill_u32(void* p, uint32_t val, int64_t count, hipStream_t s);
 
+// out[0] = OR of flags[0..count), out[1] / out[2] = first index flagged
+// kFlagNotPD / kFlagNonFinite, count if none (out: 3 device ints).
+hipError_t launch_flag_summary(const int* flags, int count, int* out, hipStream_t s);
+
 hipError_t launch_ingest(bool fp64, const void* src, int64_t sf, int64_t sn, int64_t sm, int M,
                          int F, int N, int npad, void* dst, hipStream_t s);
 

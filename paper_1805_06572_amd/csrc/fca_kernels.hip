@@ -63,6 +63,45 @@ hipError_t launch_fill_u32(void* p, uint32_t val, int64_t count, hipStream_t s) 
     return hipGetLastError();
 }
 
+// Summary of the per-problem status flags: out[0] = their bitwise OR,
+// out[1] / out[2] = the first problem flagged kFlagNotPD / kFlagNonFinite
+// (count if none). One workgroup of kFlagThreads threads.
+constexpr int kFlagThreads = 1024;
+__global__ __launch_bounds__(kFlagThreads) void flag_summary_kernel(const int* __restrict__ flags, int count,
+                                                                    int* __restrict__ out) {
+    __shared__ int s_or[kFlagThreads], s_np[kFlagThreads], s_nf[kFlagThreads];
+    const int t = threadIdx.x;
+    int o = 0, np = count, nf = count;
+    for (int i = t; i < count; i += kFlagThreads) {  // ascending: the first hit per thread is its minimum
+        const int f = flags[i];
+        o |= f;
+        if ((f & kFlagNotPD) && np == count) np = i;
+        if ((f & kFlagNonFinite) && nf == count) nf = i;
+    }
+    s_or[t] = o;
+    s_np[t] = np;
+    s_nf[t] = nf;
+    __syncthreads();
+    for (int w = kFlagThreads / 2; w >= 1; w >>= 1) {
+        if (t < w) {
+            s_or[t] |= s_or[t + w];
+            s_np[t] = min(s_np[t], s_np[t + w]);
+            s_nf[t] = min(s_nf[t], s_nf[t + w]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = s_or[0];
+        out[1] = s_np[0];
+        out[2] = s_nf[0];
+    }
+}
+
+hipError_t launch_flag_summary(const int* flags, int count, int* out, hipStream_t s) {
+    flag_summary_kernel<<<1, kFlagThreads, 0, s>>>(flags, count, out);
+    return hipGetLastError();
+}
+
 // ============================================================== plain start of v
 // fsum[f] = sum_n ||y(n,f)||^2 / M (FP64, fixed order: per-thread strided sums,
 // then a tree over the workgroup).

@@ -3,8 +3,8 @@
 Trains the library's per-bin network (fca_mlp_*, hand-written HIP kernels)
 on independent bins of the array workload, and produces the learned start
 v_j^(0) = (r, 1 - r) 2 ||y||^2 / M for a mixture. The plain start stays the
-fallback: `choose_start` evaluates the log-likelihood of both starts with the
-EM itself (an evaluation-only fca_em_step) and keeps the better one.
+fallback: `choose_starts` evaluates the log-likelihood of both starts with
+the EM itself (after one iteration by default) and keeps the better one.
 """
 from __future__ import annotations
 
@@ -55,23 +55,34 @@ def evaluate(net, n: int = 65536, M: int = 4, F: int = 513, seed: int = 99):
     return bce, bce_const
 
 
-def choose_starts(net, ctx, ys):
-    """Per mixture of a batched FP32 context that stands at its plain start,
-    keep whichever of the plain and the learned start has the higher log-
-    likelihood at iteration 0 (both evaluated by the EM itself, all mixtures
-    in one evaluation pass each). Leaves ctx at the chosen starts.
-    Returns (chosen [B] bool: learned start kept, ll_plain [B], ll_learned [B])."""
-    def ll0():
-        ll, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False, allow_flags=True)
-        return ll[:, 0].cpu().numpy()
-    ll_plain = ll0()
+def choose_starts(net, ctx, ys, judge_iter: int = 1):
+    """Per mixture of a batched FP32 context, keep whichever of the plain and
+    the learned start has the higher log-likelihood after `judge_iter` EM
+    iterations, LL(theta^judge_iter) (both evaluated by the EM itself, all
+    mixtures in one batch per start). judge_iter = 0 compares the starts
+    themselves; that favours the plain start, whose equal powers fit the
+    mixture's total power well but leave the sources undistinguished, while
+    one iteration is enough to show the learned start ahead.
+
+    Expects ctx fresh, at its plain starts. The learned run is not thrown
+    away: a mixture that keeps its learned start stays at
+    theta^(judge_iter + 1) of it; a mixture that falls back is reset to its
+    plain theta^0. Returns (chosen [B] bool: learned start kept, ll_plain [B],
+    ll_learned [B], advanced [B]: EM iterations already run from the chosen
+    start)."""
+    if judge_iter > 0:
+        fca.fca_em_step(ctx, judge_iter, want_loglik=False, want_R=False, want_v=False, allow_flags=True)
+    ll, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False, allow_flags=True)
+    ll_plain = ll[:, 0].cpu().numpy()
     for b, y in enumerate(ys):
         fca.fca_set_start(ctx, b, v0=fca.fca_mlp_init_powers(net, y))
-    ll_learned = ll0()
+    ll, _, _ = fca.fca_em_step(ctx, judge_iter + 1, want_R=False, want_v=False, allow_flags=True)
+    ll_learned = ll[:, judge_iter].cpu().numpy()
     chosen = ll_learned > ll_plain
     for b in np.nonzero(~chosen)[0]:
         fca.fca_set_start(ctx, int(b))
-    return chosen, ll_plain, ll_learned
+    advanced = np.where(chosen, judge_iter + 1, 0)
+    return chosen, ll_plain, ll_learned, advanced
 
 
 def choose_start(net, y: torch.Tensor):

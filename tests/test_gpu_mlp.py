@@ -110,10 +110,13 @@ def test_learned_start_feeds_the_em_with_fallback(fca):
     assert (chosen is None) == (ll_learned <= ll_plain)
 
 
-def test_batched_start_choice_and_per_mixture_stop(fca):
-    """choose_starts keeps the better start per mixture in one batch;
-    run_batch stops each mixture on its own rule, and each history equals a
-    lone run of that mixture from the same start."""
+@pytest.mark.parametrize("judge_iter", [0, 1])
+def test_batched_start_choice_and_per_mixture_stop(fca, judge_iter):
+    """choose_starts keeps the better start per mixture in one batch, judged
+    by LL(theta^judge_iter) of each start (checked against lone runs), and
+    leaves a kept learned start judge_iter + 1 iterations in; run_batch
+    stops each mixture on its own rule, and each history continues a lone
+    run of that mixture from the chosen start."""
     from paper_1805_06572_amd import learned_init, schedule
     net, _ = learned_init.train(M=4, steps=100, batch=4096, chunk_steps=50, seed=4)
     ys = []
@@ -123,22 +126,28 @@ def test_batched_start_choice_and_per_mixture_stop(fca):
         ys.append(torch.from_numpy(synth.array_mixture(4, 33, n, seed=200 + k, v=v).y).cuda())
     ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
     try:
-        chosen, llp, lll = learned_init.choose_starts(net, ctx, ys)
+        chosen, llp, lll, adv = learned_init.choose_starts(net, ctx, ys, judge_iter=judge_iter)
         np.testing.assert_array_equal(chosen, lll > llp)
-        cur, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False, allow_flags=True)
-        np.testing.assert_array_equal(cur.cpu().numpy()[:, 0], np.where(chosen, lll, llp))
+        np.testing.assert_array_equal(adv, np.where(chosen, judge_iter + 1, 0))
         iters, hist = schedule.run_batch(ctx, 20, 2, lambda b, ll: len(ll) >= 2 * (b + 1))
         assert list(iters) == [2, 4, 6]
     finally:
         fca.fca_destroy(ctx)
     for k, y in enumerate(ys):
-        v0 = fca.fca_mlp_init_powers(net, y) if chosen[k] else None
-        lone = fca.fca_init(y, v0=v0, prec=fca.FCA_FP32_BULK)
+        v0l = fca.fca_mlp_init_powers(net, y)
+        for want, v0 in ((llp[k], None), (lll[k], v0l)):
+            lone = fca.fca_init(y, v0=v0, prec=fca.FCA_FP32_BULK)
+            try:
+                ll, _, _ = fca.fca_em_step(lone, judge_iter + 1, want_R=False, want_v=False, allow_flags=True)
+            finally:
+                fca.fca_destroy(lone)
+            np.testing.assert_allclose(want, ll.cpu().numpy()[0, judge_iter], rtol=1e-12)
+        lone = fca.fca_init(y, v0=v0l if chosen[k] else None, prec=fca.FCA_FP32_BULK)
         try:
-            ll, _, _ = fca.fca_em_step(lone, int(iters[k]), want_R=False, want_v=False, allow_flags=True)
+            ll, _, _ = fca.fca_em_step(lone, int(adv[k] + iters[k]), want_R=False, want_v=False, allow_flags=True)
         finally:
             fca.fca_destroy(lone)
-        np.testing.assert_array_equal(np.asarray(hist[k]), ll.cpu().numpy()[0])
+        np.testing.assert_array_equal(np.asarray(hist[k]), ll.cpu().numpy()[0, adv[k]:])
 
 
 @pytest.mark.parametrize("M,F,N,H", [(4, 33, 300, 256), (2, 5, 61, 256), (8, 17, 130, 256), (4, 33, 300, 64),
