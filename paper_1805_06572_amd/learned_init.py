@@ -70,10 +70,11 @@ def choose_starts(net, ctx, ys, judge_iter: int = 1):
     plain theta^0. Returns (chosen [B] bool: learned start kept, ll_plain [B],
     ll_learned [B], advanced [B]: EM iterations already run from the chosen
     start)."""
-    if judge_iter > 0:
-        fca.fca_em_step(ctx, judge_iter, want_loglik=False, want_R=False, want_v=False, allow_flags=True)
-    ll, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False, allow_flags=True)
-    ll_plain = ll[:, 0].cpu().numpy()
+    # LL(theta^j) is computed in the pass of iteration j + 1 (j = 0: an
+    # evaluation-only pass)
+    ll, _, _ = fca.fca_em_step(ctx, judge_iter + 1 if judge_iter > 0 else 0, want_R=False, want_v=False,
+                               allow_flags=True)
+    ll_plain = ll[:, judge_iter].cpu().numpy()
     for b, y in enumerate(ys):
         fca.fca_set_start(ctx, b, v0=fca.fca_mlp_init_powers(net, y))
     ll, _, _ = fca.fca_em_step(ctx, judge_iter + 1, want_R=False, want_v=False, allow_flags=True)

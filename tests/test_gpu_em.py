@@ -95,6 +95,28 @@ def test_fp64_shapes(fca, M, F, N, iters):
     check_fp64(fca, mx.y, iters, tol=1e-10)
 
 
+@pytest.mark.parametrize("case", ["silent", "one_bin"])
+def test_fp64_degenerate_mixtures(fca, case):
+    """A silent mixture (y = 0: the plain-start floor is 1 and the powers
+    decay) and a mixture with one nonzero bin (powers down to 1e-16), against
+    the oracle from the same start; the MMSE images of a silent mixture are 0."""
+    y = np.zeros((3, 70, 2), np.complex128)
+    if case == "one_bin":
+        y[1, 3, 0] = 1.0
+    S0, v0 = oracle.default_init(y)
+    S, v, ll, flags = oracle.em(y, S0, v0, 5, threads=8)
+    assert not flags.any()
+    gll, gR, gv, gflags, gx = run_gpu(fca, y, fca.FCA_FP64, 5)
+    assert not gflags.any()
+    assert per_freq_rel(gv, v, (-1,)).max() < 1e-10
+    assert per_freq_rel(gR, S, (-2, -1)).max() < 1e-10
+    np.testing.assert_allclose(gll, ll[:5].sum(1), rtol=1e-10)
+    x = oracle.mmse(y, S, v)
+    np.testing.assert_allclose(gx, x, rtol=1e-10, atol=1e-14)
+    if case == "silent":
+        assert not np.any(gx)
+
+
 def test_fp64_user_start(fca):
     """Caller-supplied R0 and v0 (the generator's truth scaled)."""
     mx = synth.random_mixture(3, 6, 120, 12)
