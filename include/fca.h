@@ -288,6 +288,15 @@ fca_status fca_mlp_adamw(fca_mlp *m, float lr, float beta1, float beta2, float e
  * complete in that stream's order (a context created on the same stream
  * may take it at once; other users synchronise first). */
 fca_status fca_mlp_init_powers(fca_mlp *m, const float *y, int32_t F, int32_t N, float *v0_out);
+/* the same for `count` mixtures in one launch (a fixed number of bins per
+ * workgroup, so many small mixtures fill the GPU as one large one does):
+ * ys[i] (device, [F][Ns[i]][M] complex64) gives v0s[i] (device,
+ * [2][F][Ns[i]] float). ys, Ns and v0s are host arrays of length count; the
+ * call copies them, so they may be reused once it returns. Enqueued on the
+ * network's stream like fca_mlp_init_powers; FCA_E_ARG on count < 1, F < 1,
+ * a null buffer or Ns[i] < 1. */
+fca_status fca_mlp_init_powers_batch(fca_mlp *m, int32_t count, const float *const *ys, int32_t F,
+                                     const int32_t *Ns, float *const *v0s);
 
 #ifdef __cplusplus
 }

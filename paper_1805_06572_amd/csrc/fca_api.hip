@@ -513,7 +513,7 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
         FCA_TRY(ks);
 
         double2* Rb = c->R_init + mi.R_base;
-        mi.R_default = p.R0 == nullptr;
+        c->mix[b].R_default = p.R0 == nullptr;
         if (p.R0) {
             FCA_TRY(hipcall(hipMemcpyAsync(Rb, p.R0, 2ull * c->F * mi.M * mi.M * sizeof(double2),
                                            hipMemcpyDefault, s), "hipMemcpyAsync(R0)"));

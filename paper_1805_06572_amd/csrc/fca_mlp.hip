@@ -18,6 +18,7 @@
 // with both operands K-contiguous.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdint>
@@ -372,19 +373,38 @@ __device__ __forceinline__ void infer_store_hidden(const f32x4 (&acc)[CT][kRT], 
     }
 }
 
+// One mixture of a fused-inference launch: its tiles are [tile0, tile0 +
+// ceil(F N / kTile)) of the grid.
+struct InferJob {
+    const float2* y;  // [F][N][M]
+    float* v0;        // [2][F][N]
+    int64_t tile0;
+    int F, N;
+};
+
 template <int H>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void mlp_infer_kernel(
-    const float2* __restrict__ y, int F, int N, int M, const bf16* __restrict__ W0, const bf16* __restrict__ W1,
+    const InferJob* __restrict__ jobs, int njobs, int M, const bf16* __restrict__ W0, const bf16* __restrict__ W1,
     const bf16* __restrict__ W2, const float* __restrict__ bias0, const float* __restrict__ bias1,
-    const float* __restrict__ bias2, const float* __restrict__ w4, const float* __restrict__ b4,
-    float* __restrict__ v0) {
+    const float* __restrict__ bias2, const float* __restrict__ w4, const float* __restrict__ b4) {
     constexpr int CT = H / 64;
     using Sh = InferShared<H>;
     extern __shared__ __align__(16) unsigned char smem[];
     Sh& sh = *reinterpret_cast<Sh*>(smem);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // the job owning this tile: the last one with tile0 <= blockIdx.x
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile0 <= (int64_t)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const InferJob job = jobs[lo];
+    const float2* __restrict__ y = job.y;
+    float* __restrict__ v0 = job.v0;
+    const int F = job.F, N = job.N;
     const int64_t FN = (int64_t)F * N;
-    const int64_t r0 = (int64_t)blockIdx.x * kTile;
+    const int64_t r0 = ((int64_t)blockIdx.x - job.tile0) * kTile;
     if (tid < kTile) {
         const int64_t bin = r0 + tid;
         bf16* xr = sh.X + tid * kXP;
@@ -473,6 +493,11 @@ struct fca_mlp {
     float *dz = nullptr, *r = nullptr;
     float* ogpart = nullptr;  // [max_batch / 64 + 1][H + 1] partial sums of the output-layer gradient
     double* loss_terms = nullptr;
+    // fused-inference job tables (grown on demand): pinned staging, device copy
+    InferJob* jobs_host = nullptr;
+    InferJob* jobs_dev = nullptr;
+    int jobs_cap = 0;
+    hipEvent_t jobs_ev = nullptr;  // the last upload from jobs_host
     int64_t step = 0;
     std::string err;
 };
@@ -493,9 +518,11 @@ bool mlp_alloc(P** p, size_t bytes) {
 
 void mlp_free(fca_mlp* m) {
     void* ptrs[] = {m->p, m->g, m->m1, m->m2, m->X, m->XT, m->D, m->DT, m->D2, m->D2T, m->dz, m->r, m->ogpart,
-                    m->loss_terms};
+                    m->loss_terms, m->jobs_dev};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    if (m->jobs_host) (void)hipHostFree(m->jobs_host);
+    if (m->jobs_ev) (void)hipEventDestroy(m->jobs_ev);
     for (int l = 0; l < kLayers; ++l) {
         if (m->Wb[l]) (void)hipFree(m->Wb[l]);
         if (m->WTb[l]) (void)hipFree(m->WTb[l]);
@@ -549,14 +576,14 @@ hipError_t forward(fca_mlp* m, const float2* y, const float* fpos, int n) {
 }
 
 template <int H>
-hipError_t launch_infer(const fca_mlp* m, const float* y, int F, int N, int64_t tiles, float* v0) {
+hipError_t launch_infer(const fca_mlp* m, const InferJob* jobs, int njobs, int64_t tiles, hipStream_t s) {
     static_assert(sizeof(InferShared<H>) <= 160 * 1024, "LDS of the fused inference kernel");
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_infer_kernel<H>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(InferShared<H>));
     if (e != hipSuccess) return e;
-    mlp_infer_kernel<H><<<(unsigned)tiles, 256, sizeof(InferShared<H>), m->stream>>>(
-        reinterpret_cast<const float2*>(y), F, N, m->M, m->Wb[0], m->Wb[1], m->Wb[2], m->p + m->off_b[0],
-        m->p + m->off_b[1], m->p + m->off_b[2], m->p + m->off_W[kLayers], m->p + m->off_b[kLayers], v0);
+    mlp_infer_kernel<H><<<(unsigned)tiles, 256, sizeof(InferShared<H>), s>>>(
+        jobs, njobs, m->M, m->Wb[0], m->Wb[1], m->Wb[2], m->p + m->off_b[0], m->p + m->off_b[1], m->p + m->off_b[2],
+        m->p + m->off_W[kLayers], m->p + m->off_b[kLayers]);
     return hipGetLastError();
 }
 
@@ -767,22 +794,70 @@ fca_status fca_mlp_adamw(fca_mlp* m, float lr, float beta1, float beta2, float e
     return FCA_OK;
 }
 
-fca_status fca_mlp_init_powers(fca_mlp* m, const float* y, int32_t F, int32_t N, float* v0_out) {
-    if (!m || !y || !v0_out || F < 1 || N < 1) return FCA_E_ARG;
-    const int64_t FN = (int64_t)F * N;
-    const int64_t tiles = (FN + kTile - 1) / kTile;
-    if (tiles > INT32_MAX) {
-        m->err = "fca_mlp_init_powers: too many bins";
+fca_status fca_mlp_init_powers_batch(fca_mlp* m, int32_t count, const float* const* ys, int32_t F,
+                                     const int32_t* Ns, float* const* v0s) {
+    if (!m) return FCA_E_ARG;
+    if (count < 1 || !ys || !Ns || !v0s || F < 1) {
+        m->err = "fca_mlp_init_powers_batch: need count >= 1, F >= 1 and the three arrays";
         return FCA_E_ARG;
     }
+    for (int i = 0; i < count; ++i)
+        if (!ys[i] || !v0s[i] || Ns[i] < 1) {
+            m->err = "fca_mlp_init_powers_batch: mixture " + std::to_string(i) + " has a null buffer or N < 1";
+            return FCA_E_ARG;
+        }
+    const hipStream_t s = m->stream;
+    if (count > m->jobs_cap) {
+        // the previous upload must have left the staging buffer before it is replaced
+        if (m->jobs_ev) MLP_HIP(m, hipEventSynchronize(m->jobs_ev));
+        if (m->jobs_host) (void)hipHostFree(m->jobs_host);
+        if (m->jobs_dev) {
+            MLP_HIP(m, hipStreamSynchronize(s));  // earlier launches may still read the old table
+            (void)hipFree(m->jobs_dev);
+        }
+        m->jobs_host = nullptr;
+        m->jobs_dev = nullptr;
+        m->jobs_cap = 0;
+        const int cap = std::max(count, 64);
+        if (hipHostMalloc(reinterpret_cast<void**>(&m->jobs_host), (size_t)cap * sizeof(InferJob),
+                          hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            m->jobs_host = nullptr;
+            m->err = "fca_mlp_init_powers_batch: pinned allocation failed";
+            return FCA_E_NOMEM;
+        }
+        if (!mlp_alloc(&m->jobs_dev, (size_t)cap * sizeof(InferJob))) {
+            m->err = "fca_mlp_init_powers_batch: device allocation failed";
+            return FCA_E_NOMEM;
+        }
+        m->jobs_cap = cap;
+    }
+    if (!m->jobs_ev) MLP_HIP(m, hipEventCreateWithFlags(&m->jobs_ev, hipEventDisableTiming));
+    MLP_HIP(m, hipEventSynchronize(m->jobs_ev));  // the previous upload has read the staging buffer
+    int64_t tiles = 0;
+    for (int i = 0; i < count; ++i) {
+        m->jobs_host[i] = InferJob{reinterpret_cast<const float2*>(ys[i]), v0s[i], tiles, F, Ns[i]};
+        tiles += ((int64_t)F * Ns[i] + kTile - 1) / kTile;
+    }
+    if (tiles > INT32_MAX) {
+        m->err = "fca_mlp_init_powers_batch: too many bins";
+        return FCA_E_ARG;
+    }
+    MLP_HIP(m, hipMemcpyAsync(m->jobs_dev, m->jobs_host, (size_t)count * sizeof(InferJob), hipMemcpyHostToDevice, s));
+    MLP_HIP(m, hipEventRecord(m->jobs_ev, s));
     hipError_t e;
     switch (m->hidden) {
-        case 64: e = launch_infer<64>(m, y, F, N, tiles, v0_out); break;
-        case 128: e = launch_infer<128>(m, y, F, N, tiles, v0_out); break;
-        default: e = launch_infer<kMaxHidden>(m, y, F, N, tiles, v0_out); break;
+        case 64: e = launch_infer<64>(m, m->jobs_dev, count, tiles, s); break;
+        case 128: e = launch_infer<128>(m, m->jobs_dev, count, tiles, s); break;
+        default: e = launch_infer<kMaxHidden>(m, m->jobs_dev, count, tiles, s); break;
     }
     MLP_HIP(m, e);
     return FCA_OK;
+}
+
+fca_status fca_mlp_init_powers(fca_mlp* m, const float* y, int32_t F, int32_t N, float* v0_out) {
+    if (!m || !y || !v0_out || F < 1 || N < 1) return FCA_E_ARG;
+    return fca_mlp_init_powers_batch(m, 1, &y, F, &N, &v0_out);
 }
 
 }  // extern "C"

@@ -37,7 +37,7 @@ EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set
             "fca_launch_groups", "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch",
             "fca_mlp_create", "fca_mlp_destroy", "fca_mlp_num_params", "fca_mlp_last_error",
             "fca_mlp_get_params", "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward",
-            "fca_mlp_adamw", "fca_mlp_init_powers"]
+            "fca_mlp_adamw", "fca_mlp_init_powers", "fca_mlp_init_powers_batch"]
 
 
 class fca_problem(ctypes.Structure):
@@ -99,11 +99,13 @@ def lib() -> ctypes.CDLL:
         L.fca_mlp_adamw.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float]
         L.fca_mlp_init_powers.argtypes = [vp, vp, i32, i32, vp]
+        L.fca_mlp_init_powers_batch.argtypes = [vp, i32, ctypes.POINTER(vp), i32, ctypes.POINTER(i32),
+                                                ctypes.POINTER(vp)]
         for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set_active", "fca_em_step", "fca_conv_em_step", "fca_separate",
                      "fca_status_per_freq", "fca_gevd", "fca_timing", "fca_launch_groups",
                      "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch", "fca_mlp_create", "fca_mlp_get_params",
                      "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward", "fca_mlp_adamw",
-                     "fca_mlp_init_powers"):
+                     "fca_mlp_init_powers", "fca_mlp_init_powers_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -474,3 +476,26 @@ def fca_mlp_init_powers(m: Mlp, y) -> torch.Tensor:
     if torch.cuda.current_stream(y.device).cuda_stream != m.stream:
         torch.cuda.synchronize(y.device)  # the kernel ran on the network's stream
     return v0
+
+
+def fca_mlp_init_powers_batch(m: Mlp, ys) -> list:
+    """Learned starts of several mixtures (each y [F, N_b, M] complex64, one F)
+    in one launch: list of v0 [2, F, N_b] float32 views of one device buffer."""
+    ys = [_dev(y, torch.complex64) for y in ys]
+    F, M = ys[0].shape[0], ys[0].shape[2]
+    if any(y.shape[0] != F or y.shape[2] != M for y in ys):
+        raise ValueError("fca_mlp_init_powers_batch: every mixture needs the same F and M")
+    Ns = [int(y.shape[1]) for y in ys]
+    buf = torch.empty(sum(2 * F * n for n in Ns), dtype=torch.float32, device=ys[0].device)
+    v0s, o = [], 0
+    for n in Ns:
+        v0s.append(buf[o:o + 2 * F * n].view(2, F, n))
+        o += 2 * F * n
+    k = len(ys)
+    yp = (ctypes.c_void_p * k)(*[y.data_ptr() for y in ys])
+    vp_ = (ctypes.c_void_p * k)(*[v.data_ptr() for v in v0s])
+    nn = (ctypes.c_int32 * k)(*Ns)
+    m._check(lib().fca_mlp_init_powers_batch(m.handle, k, yp, F, nn, vp_))
+    if torch.cuda.current_stream(ys[0].device).cuda_stream != m.stream:
+        torch.cuda.synchronize(ys[0].device)
+    return v0s

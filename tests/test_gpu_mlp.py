@@ -174,6 +174,21 @@ def test_fused_learned_start_matches_forward_and_reference(fca, M, F, N, H):
     np.testing.assert_allclose(r_gpu, want, atol=2e-2)
 
 
+@pytest.mark.parametrize("H", [64, 256])
+def test_batched_inference_equals_single_mixture_calls(fca, H):
+    """fca_mlp_init_powers_batch (one launch over mixtures of uneven N,
+    including ragged tiles and a one-frame mixture) gives bitwise the
+    per-mixture results."""
+    net = fca.Mlp(4, seed=9, max_batch=256, hidden=H)
+    ys = [torch.from_numpy(synth.array_mixture(4, 17, n, seed=500 + n, complex64=True).y).cuda()
+          for n in (130, 1, 64, 257)]
+    got = fca.fca_mlp_init_powers_batch(net, ys)
+    for y, g in zip(ys, got):
+        np.testing.assert_array_equal(g.cpu().numpy(), fca.fca_mlp_init_powers(net, y).cpu().numpy())
+    with pytest.raises(ValueError):
+        fca.fca_mlp_init_powers_batch(net, [ys[0], ys[0][:5]])
+
+
 def test_run_batch_chunk_schedule(fca):
     """A chunk sequence gives the same histories as single steps; the stop
     decision is taken at chunk boundaries only."""
