@@ -282,6 +282,15 @@ fca_status fca_mlp_backward(fca_mlp *m, const float *y, const float *fpos, const
                             double *loss, float *grads_out);
 /* one AdamW step with the last gradient (bias-corrected moments) */
 fca_status fca_mlp_adamw(fca_mlp *m, float lr, float beta1, float beta2, float eps, float weight_decay);
+/* Learned starts straight from the mixtures a context already holds: for
+ * each listed mixture (mixtures = NULL: mixtures 0..count-1) the network's
+ * v_j^(0) becomes its stored start (as fca_set_start with that v0 and the
+ * plain R would make it), and the mixture is reset to it and made active.
+ * One inference launch reads the context's copy of y and writes the stored
+ * and the working powers; enqueued on the context's stream (after the
+ * network's stream). FCA_E_ARG for an FP64 context, a mixture index out of
+ * range or a mixture whose M differs from the network's. */
+fca_status fca_set_learned_starts(fca_ctx *c, fca_mlp *m, int32_t count, const int32_t *mixtures);
 /* learned start for a mixture y [F][N][M] complex64 (contiguous, device):
  * v0_out [2][F][N] float (device), usable as fca_problem.v0. One fused
  * kernel, enqueued on the network's stream without waiting: v0_out is

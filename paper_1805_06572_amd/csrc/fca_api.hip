@@ -216,9 +216,22 @@ fca_status validate(const fca_problem* p, int b, const fca_problem* p0) {
     return FCA_OK;
 }
 
+// The basis of the initial values of mixture b: the FP64 GEVD of
+// (R1^(0), R2^(0)) read from R (R_init of the mixture unless a staged copy
+// is given). Enqueued only.
+fca_status reset_basis(fca_ctx* c, int b, const double2* R, hipStream_t s) {
+    const MixInfo& mi = c->mix[b];
+    const int64_t mm = (int64_t)mi.M * mi.M;
+    const double2* R1 = R ? R : c->R_init + mi.R_base;
+    const double2* R2 = R1 + (int64_t)c->F * mm;
+    FCA_HIP(c, launch_gevd(mi.M, c->F, R1, R2, mm, mm, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM,
+                           kMaxM * kMaxM, c->lam + (int64_t)mi.pid0 * kMaxM, kMaxM,
+                           c->logdet + mi.pid0, c->flags + mi.pid0, s));
+    return FCA_OK;
+}
+
 // Initial values (Algorithm 1, step 1) of mixture b: v^(0) from v_init or the
-// plain start, then the FP64 GEVD of (R1^(0), R2^(0)) read from R (R_init of
-// the mixture unless a staged copy is given). Enqueued only.
+// plain start, then the basis (reset_basis). Enqueued only.
 fca_status reset_mixture(fca_ctx* c, int b, const double2* R, hipStream_t s) {
     const MixInfo& mi = c->mix[b];
     char* v = static_cast<char*>(c->v) + mi.v_base * c->rsz;
@@ -231,12 +244,18 @@ fca_status reset_mixture(fca_ctx* c, int b, const double2* R, hipStream_t s) {
         FCA_HIP(c, launch_power_sums(c->fp64, yb, mi.M, c->F, mi.N, mi.npad, fs, s));
         FCA_HIP(c, launch_default_v(c->fp64, yb, fs, mi.M, c->F, mi.N, mi.npad, v, s));
     }
-    const int64_t mm = (int64_t)mi.M * mi.M;
-    const double2* R1 = R ? R : c->R_init + mi.R_base;
-    const double2* R2 = R1 + (int64_t)c->F * mm;
-    FCA_HIP(c, launch_gevd(mi.M, c->F, R1, R2, mm, mm, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM,
-                           kMaxM * kMaxM, c->lam + (int64_t)mi.pid0 * kMaxM, kMaxM,
-                           c->logdet + mi.pid0, c->flags + mi.pid0, s));
+    return reset_basis(c, b, R, s);
+}
+
+// The stored initial powers, allocated on first use. In FP32 contexts the
+// buffer starts as ones, so that the padding frames of a mixture whose
+// start is written frame by frame (fca_set_learned_starts) hold 1 as the EM
+// kernels expect; fca_set_start and fca_init write whole rows.
+fca_status ensure_v_init(fca_ctx* c) {
+    if (c->v_init) return FCA_OK;
+    fca_status st = dev_alloc(c, &c->v_init, c->v_tot * c->rsz);
+    if (st != FCA_OK) return st;
+    if (!c->fp64) FCA_HIP(c, launch_fill_u32(c->v_init, 0x3F800000u, c->v_tot, c->stream));  // 1.0f
     return FCA_OK;
 }
 
@@ -395,7 +414,7 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     c->v_tot = v_tot;
     c->active.assign(B, 1);
     FCA_TRY(dev_alloc(c, &c->v, 2 * v_tot * c->rsz));
-    if (any_v0) FCA_TRY(dev_alloc(c, &c->v_init, v_tot * c->rsz));
+    if (any_v0) FCA_TRY(ensure_v_init(c));
     FCA_TRY(dev_alloc(c, &c->R_init, R_tot * sizeof(double2)));
     FCA_TRY(dev_alloc(c, &c->P, (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2)));
     FCA_TRY(dev_alloc(c, &c->Pinv, (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2)));
@@ -607,10 +626,8 @@ fca_status fca_set_start(fca_ctx* c, int32_t b, const double* R0, const void* v0
         mi.R_default = true;
     }
     if (v0) {
-        if (!c->v_init) {
-            fca_status st = dev_alloc(c, &c->v_init, c->v_tot * c->rsz);
-            if (st != FCA_OK) return st;
-        }
+        fca_status st0 = ensure_v_init(c);
+        if (st0 != FCA_OK) return st0;
         const size_t vbytes = 2ull * c->F * mi.N * c->rsz;
         const void* vsrc = v0;
         void* vtmp = nullptr;
@@ -641,6 +658,70 @@ fca_status fca_set_start(fca_ctx* c, int32_t b, const double* R0, const void* v0
         c->active[b] = 1;
         c->act_dirty = true;
     }
+    return FCA_OK;
+}
+
+fca_status fca_set_learned_starts(fca_ctx* c, fca_mlp* m, int32_t count, const int32_t* mixtures) {
+    if (!c) return FCA_E_ARG;
+    if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
+    if (!m) { set_err(c, "fca_set_learned_starts: no network"); return FCA_E_ARG; }
+    if (c->fp64) { set_err(c, "fca_set_learned_starts: needs an FP32-bulk context"); return FCA_E_ARG; }
+    if (count < 1 || count > c->B) {
+        set_err(c, "fca_set_learned_starts: count %d outside 1..%d", count, c->B);
+        return FCA_E_ARG;
+    }
+    std::vector<int> list(count);
+    for (int i = 0; i < count; ++i) {
+        const int b = mixtures ? mixtures[i] : i;
+        if (b < 0 || b >= c->B) {
+            set_err(c, "fca_set_learned_starts: mixture %d outside 0..%d", b, c->B - 1);
+            return FCA_E_ARG;
+        }
+        if (c->mix[b].M != mlp_microphones(m)) {
+            set_err(c, "fca_set_learned_starts: mixture %d has M = %d, the network M = %d", b, c->mix[b].M,
+                    mlp_microphones(m));
+            return FCA_E_ARG;
+        }
+        list[i] = b;
+    }
+    const hipStream_t s = c->stream;
+    {
+        fca_status st = ensure_v_init(c);
+        if (st != FCA_OK) return st;
+    }
+    // one inference launch writes v_init and v of every listed mixture
+    std::vector<MlpInferJob> jobs(count);
+    for (int i = 0; i < count; ++i) {
+        const MixInfo& mi = c->mix[list[i]];
+        const int64_t np = mi.npad;
+        jobs[i] = MlpInferJob{reinterpret_cast<const float2*>(c->y) + mi.y_base,
+                              static_cast<float*>(c->v_init) + mi.v_base,
+                              static_cast<float*>(c->v) + mi.v_base,
+                              (int64_t)mi.M * np, 1, np, (int64_t)c->F * np, np, 0, c->F, mi.N};
+    }
+    const char* err = nullptr;
+    const hipError_t e = mlp_infer_jobs(m, jobs.data(), count, s, &err);
+    if (err) {
+        set_err(c, "fca_set_learned_starts: %s", err);
+        return e == hipErrorOutOfMemory ? FCA_E_NOMEM : FCA_E_ARG;
+    }
+    FCA_HIP(c, e);
+    for (int b : list) {
+        MixInfo& mi = c->mix[b];
+        if (!mi.R_default) {
+            FCA_HIP(c, launch_default_R(mi.M, c->F, c->R_init + mi.R_base, s));
+            mi.R_default = true;
+        }
+        mi.has_v0 = true;
+        fca_status st = reset_basis(c, b, nullptr, s);
+        if (st != FCA_OK) return st;
+        FCA_HIP(c, launch_fill_u32(c->flags + mi.pid0, 0u, c->F, s));
+        if (!c->active[b]) {
+            c->active[b] = 1;
+            c->act_dirty = true;
+        }
+    }
+    c->shape_version += 1;  // a captured reset would compute the old kind of start
     return FCA_OK;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fca.h"
+
 namespace fca {
 
 // Per-frequency status bits (the FCA_FLAG_* values of fca.h).
@@ -73,6 +75,23 @@ hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int
 // Support kernels (fca_kernels.hip).
 // p[i] = val for count 32-bit words (a kernel, not a memset: graph-capturable).
 hipError_t launch_fill_u32(void* p, uint32_t val, int64_t count, hipStream_t s);
+
+// One mixture of a fused learned-start inference (fca_mlp.hip): y element
+// (f, n, microphone m) at y[f y_sf + n y_sn + m y_sm] (complex64); v_j(n,f)
+// written to out[j o_sj + f o_sf + n] and, if out2 is not null, to out2 at
+// the same offset. Its workgroups are [tile0, tile0 + ceil(F N / 128)).
+struct MlpInferJob {
+    const float2* y;
+    float* out;
+    float* out2;
+    int64_t y_sf, y_sn, y_sm, o_sj, o_sf;
+    int64_t tile0;
+    int F, N;
+};
+// Enqueues the fused inference of network m for `count` jobs (host array,
+// tile0 filled in here) on stream s, after the network's own stream.
+hipError_t mlp_infer_jobs(fca_mlp* m, MlpInferJob* jobs, int count, hipStream_t s, const char** err);
+int mlp_microphones(const fca_mlp* m);
 
 // out[0] = OR of flags[0..count), out[1] / out[2] = first index flagged
 // kFlagNotPD / kFlagNonFinite, count if none (out: 3 device ints).

@@ -79,14 +79,14 @@ __device__ __forceinline__ float gelu_grad(float x) {
 
 // ------------------------------------------------------------------ features
 // Features of one bin (zero-padded to kKP), stored as T (a local FP32 array
-// or a BF16 row in LDS).
+// or a BF16 row in LDS); microphone m of the bin at yb[m * sm].
 template <typename T>
-__device__ __forceinline__ void bin_features(const float2* __restrict__ yb, int M, float fpos, T* feat) {
+__device__ __forceinline__ void bin_features(const float2* __restrict__ yb, int64_t sm, int M, float fpos, T* feat) {
     for (int j = 0; j < kKP; ++j) feat[j] = (T)0.0f;
     const float2 y0 = yb[0];
     const float p0 = y0.x * y0.x + y0.y * y0.y;
     for (int m = 0; m < M; ++m) {
-        const float2 ym = yb[m];
+        const float2 ym = yb[m * sm];
         const float pm = ym.x * ym.x + ym.y * ym.y;
         feat[m] = (T)logf(pm + 1e-20f);
         if (m > 0) {
@@ -106,7 +106,7 @@ __global__ void mlp_features_kernel(const float2* __restrict__ y, const float* _
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
     float feat[kKP];
-    bin_features(y + (int64_t)b * M, M, fpos[b], feat);
+    bin_features(y + (int64_t)b * M, 1, M, fpos[b], feat);
     for (int j = 0; j < kKP; ++j) {
         const bf16 h = (bf16)feat[j];
         X[(int64_t)b * kKP + j] = h;
@@ -373,14 +373,7 @@ __device__ __forceinline__ void infer_store_hidden(const f32x4 (&acc)[CT][kRT], 
     }
 }
 
-// One mixture of a fused-inference launch: its tiles are [tile0, tile0 +
-// ceil(F N / kTile)) of the grid.
-struct InferJob {
-    const float2* y;  // [F][N][M]
-    float* v0;        // [2][F][N]
-    int64_t tile0;
-    int F, N;
-};
+using InferJob = fca::MlpInferJob;
 
 template <int H>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void mlp_infer_kernel(
@@ -400,8 +393,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
         else hi = mid - 1;
     }
     const InferJob job = jobs[lo];
-    const float2* __restrict__ y = job.y;
-    float* __restrict__ v0 = job.v0;
     const int F = job.F, N = job.N;
     const int64_t FN = (int64_t)F * N;
     const int64_t r0 = ((int64_t)blockIdx.x - job.tile0) * kTile;
@@ -410,11 +401,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
         bf16* xr = sh.X + tid * kXP;
         float s = 0.0f;
         if (bin < FN) {
-            const int f = (int)(bin / N);
-            const float2* yb = y + bin * M;
-            bin_features(yb, M, F > 1 ? (float)f / (float)(F - 1) : 0.0f, xr);
+            const int f = (int)(bin / N), n = (int)(bin - (int64_t)f * N);
+            const float2* yb = job.y + f * job.y_sf + n * job.y_sn;
+            bin_features(yb, job.y_sm, M, F > 1 ? (float)f / (float)(F - 1) : 0.0f, xr);
             float p = 0.0f;
-            for (int m = 0; m < M; ++m) p += yb[m].x * yb[m].x + yb[m].y * yb[m].y;
+            for (int m = 0; m < M; ++m) {
+                const float2 ym = yb[m * job.y_sm];
+                p += ym.x * ym.x + ym.y * ym.y;
+            }
             s = fmaxf(2.0f * p / (float)M, 1e-30f);
         } else {
             for (int j = 0; j < kKP; ++j) xr[j] = (bf16)0.0f;
@@ -468,8 +462,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
             const float r = 1.0f / (1.0f + expf(-z));
             const float ri = fminf(fmaxf(r, 1e-6f), 1.0f - 1e-6f);
             const float s = sh.sv[tid];
-            v0[bin] = ri * s;
-            v0[FN + bin] = (1.0f - ri) * s;
+            const int f = (int)(bin / N), n = (int)(bin - (int64_t)f * N);
+            const int64_t o = f * job.o_sf + n;
+            job.out[o] = ri * s;
+            job.out[job.o_sj + o] = (1.0f - ri) * s;
+            if (job.out2) {
+                job.out2[o] = ri * s;
+                job.out2[job.o_sj + o] = (1.0f - ri) * s;
+            }
         }
     }
 }
@@ -497,7 +497,8 @@ struct fca_mlp {
     InferJob* jobs_host = nullptr;
     InferJob* jobs_dev = nullptr;
     int jobs_cap = 0;
-    hipEvent_t jobs_ev = nullptr;  // the last upload from jobs_host
+    hipEvent_t jobs_ev = nullptr;       // the last upload from jobs_host
+    hipEvent_t jobs_done_ev = nullptr;  // the last launch that reads jobs_dev
     int64_t step = 0;
     std::string err;
 };
@@ -523,6 +524,7 @@ void mlp_free(fca_mlp* m) {
         if (q) (void)hipFree(q);
     if (m->jobs_host) (void)hipHostFree(m->jobs_host);
     if (m->jobs_ev) (void)hipEventDestroy(m->jobs_ev);
+    if (m->jobs_done_ev) (void)hipEventDestroy(m->jobs_done_ev);
     for (int l = 0; l < kLayers; ++l) {
         if (m->Wb[l]) (void)hipFree(m->Wb[l]);
         if (m->WTb[l]) (void)hipFree(m->WTb[l]);
@@ -801,55 +803,21 @@ fca_status fca_mlp_init_powers_batch(fca_mlp* m, int32_t count, const float* con
         m->err = "fca_mlp_init_powers_batch: need count >= 1, F >= 1 and the three arrays";
         return FCA_E_ARG;
     }
-    for (int i = 0; i < count; ++i)
+    std::vector<fca::MlpInferJob> jobs(count);
+    for (int i = 0; i < count; ++i) {
         if (!ys[i] || !v0s[i] || Ns[i] < 1) {
             m->err = "fca_mlp_init_powers_batch: mixture " + std::to_string(i) + " has a null buffer or N < 1";
             return FCA_E_ARG;
         }
-    const hipStream_t s = m->stream;
-    if (count > m->jobs_cap) {
-        // the previous upload must have left the staging buffer before it is replaced
-        if (m->jobs_ev) MLP_HIP(m, hipEventSynchronize(m->jobs_ev));
-        if (m->jobs_host) (void)hipHostFree(m->jobs_host);
-        if (m->jobs_dev) {
-            MLP_HIP(m, hipStreamSynchronize(s));  // earlier launches may still read the old table
-            (void)hipFree(m->jobs_dev);
-        }
-        m->jobs_host = nullptr;
-        m->jobs_dev = nullptr;
-        m->jobs_cap = 0;
-        const int cap = std::max(count, 64);
-        if (hipHostMalloc(reinterpret_cast<void**>(&m->jobs_host), (size_t)cap * sizeof(InferJob),
-                          hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            m->jobs_host = nullptr;
-            m->err = "fca_mlp_init_powers_batch: pinned allocation failed";
-            return FCA_E_NOMEM;
-        }
-        if (!mlp_alloc(&m->jobs_dev, (size_t)cap * sizeof(InferJob))) {
-            m->err = "fca_mlp_init_powers_batch: device allocation failed";
-            return FCA_E_NOMEM;
-        }
-        m->jobs_cap = cap;
+        const int64_t N = Ns[i];
+        jobs[i] = fca::MlpInferJob{reinterpret_cast<const float2*>(ys[i]), v0s[i], nullptr, N * m->M, m->M, 1,
+                                   (int64_t)F * N, N, 0, F, Ns[i]};
     }
-    if (!m->jobs_ev) MLP_HIP(m, hipEventCreateWithFlags(&m->jobs_ev, hipEventDisableTiming));
-    MLP_HIP(m, hipEventSynchronize(m->jobs_ev));  // the previous upload has read the staging buffer
-    int64_t tiles = 0;
-    for (int i = 0; i < count; ++i) {
-        m->jobs_host[i] = InferJob{reinterpret_cast<const float2*>(ys[i]), v0s[i], tiles, F, Ns[i]};
-        tiles += ((int64_t)F * Ns[i] + kTile - 1) / kTile;
-    }
-    if (tiles > INT32_MAX) {
-        m->err = "fca_mlp_init_powers_batch: too many bins";
-        return FCA_E_ARG;
-    }
-    MLP_HIP(m, hipMemcpyAsync(m->jobs_dev, m->jobs_host, (size_t)count * sizeof(InferJob), hipMemcpyHostToDevice, s));
-    MLP_HIP(m, hipEventRecord(m->jobs_ev, s));
-    hipError_t e;
-    switch (m->hidden) {
-        case 64: e = launch_infer<64>(m, m->jobs_dev, count, tiles, s); break;
-        case 128: e = launch_infer<128>(m, m->jobs_dev, count, tiles, s); break;
-        default: e = launch_infer<kMaxHidden>(m, m->jobs_dev, count, tiles, s); break;
+    const char* err = nullptr;
+    const hipError_t e = fca::mlp_infer_jobs(m, jobs.data(), count, m->stream, &err);
+    if (err) {
+        m->err = err;
+        return e == hipErrorOutOfMemory ? FCA_E_NOMEM : FCA_E_ARG;
     }
     MLP_HIP(m, e);
     return FCA_OK;
@@ -861,3 +829,67 @@ fca_status fca_mlp_init_powers(fca_mlp* m, const float* y, int32_t F, int32_t N,
 }
 
 }  // extern "C"
+
+namespace fca {
+
+int mlp_microphones(const fca_mlp* m) { return m ? m->M : 0; }
+
+hipError_t mlp_infer_jobs(fca_mlp* m, MlpInferJob* jobs, int count, hipStream_t s, const char** err) {
+    *err = nullptr;
+    int64_t tiles = 0;
+    for (int i = 0; i < count; ++i) {
+        jobs[i].tile0 = tiles;
+        tiles += ((int64_t)jobs[i].F * jobs[i].N + kTile - 1) / kTile;
+    }
+    if (tiles > INT32_MAX) {
+        *err = "learned-start inference: too many bins in one call";
+        return hipErrorInvalidValue;
+    }
+    hipError_t e;
+    if (!m->jobs_ev && (e = hipEventCreateWithFlags(&m->jobs_ev, hipEventDisableTiming)) != hipSuccess) return e;
+    if (!m->jobs_done_ev && (e = hipEventCreateWithFlags(&m->jobs_done_ev, hipEventDisableTiming)) != hipSuccess)
+        return e;
+    if (count > m->jobs_cap) {
+        // nothing may still read the old tables
+        if ((e = hipEventSynchronize(m->jobs_done_ev)) != hipSuccess) return e;
+        if (m->jobs_host) (void)hipHostFree(m->jobs_host);
+        if (m->jobs_dev) (void)hipFree(m->jobs_dev);
+        m->jobs_host = nullptr;
+        m->jobs_dev = nullptr;
+        m->jobs_cap = 0;
+        const int cap = std::max(count, 64);
+        if (hipHostMalloc(reinterpret_cast<void**>(&m->jobs_host), (size_t)cap * sizeof(MlpInferJob),
+                          hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            m->jobs_host = nullptr;
+            *err = "learned-start inference: pinned allocation failed";
+            return hipErrorOutOfMemory;
+        }
+        if (!mlp_alloc(&m->jobs_dev, (size_t)cap * sizeof(MlpInferJob))) {
+            *err = "learned-start inference: device allocation failed";
+            return hipErrorOutOfMemory;
+        }
+        m->jobs_cap = cap;
+    }
+    if ((e = hipEventSynchronize(m->jobs_ev)) != hipSuccess) return e;  // the staging buffer is free
+    memcpy(m->jobs_host, jobs, (size_t)count * sizeof(MlpInferJob));
+    // the weights come from the network's stream; the table from the last
+    // launch that read it, possibly on another stream
+    if (s != m->stream) {
+        if ((e = hipStreamSynchronize(m->stream)) != hipSuccess) return e;
+    }
+    if ((e = hipStreamWaitEvent(s, m->jobs_done_ev, 0)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(m->jobs_dev, m->jobs_host, (size_t)count * sizeof(MlpInferJob), hipMemcpyHostToDevice,
+                            s)) != hipSuccess)
+        return e;
+    if ((e = hipEventRecord(m->jobs_ev, s)) != hipSuccess) return e;
+    switch (m->hidden) {
+        case 64: e = launch_infer<64>(m, m->jobs_dev, count, tiles, s); break;
+        case 128: e = launch_infer<128>(m, m->jobs_dev, count, tiles, s); break;
+        default: e = launch_infer<kMaxHidden>(m, m->jobs_dev, count, tiles, s); break;
+    }
+    if (e != hipSuccess) return e;
+    return hipEventRecord(m->jobs_done_ev, s);
+}
+
+}  // namespace fca

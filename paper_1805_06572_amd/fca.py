@@ -37,7 +37,7 @@ EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set
             "fca_launch_groups", "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch",
             "fca_mlp_create", "fca_mlp_destroy", "fca_mlp_num_params", "fca_mlp_last_error",
             "fca_mlp_get_params", "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward",
-            "fca_mlp_adamw", "fca_mlp_init_powers", "fca_mlp_init_powers_batch"]
+            "fca_mlp_adamw", "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts"]
 
 
 class fca_problem(ctypes.Structure):
@@ -101,11 +101,12 @@ def lib() -> ctypes.CDLL:
         L.fca_mlp_init_powers.argtypes = [vp, vp, i32, i32, vp]
         L.fca_mlp_init_powers_batch.argtypes = [vp, i32, ctypes.POINTER(vp), i32, ctypes.POINTER(i32),
                                                 ctypes.POINTER(vp)]
+        L.fca_set_learned_starts.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
         for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set_active", "fca_em_step", "fca_conv_em_step", "fca_separate",
                      "fca_status_per_freq", "fca_gevd", "fca_timing", "fca_launch_groups",
                      "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch", "fca_mlp_create", "fca_mlp_get_params",
                      "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward", "fca_mlp_adamw",
-                     "fca_mlp_init_powers", "fca_mlp_init_powers_batch"):
+                     "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -499,3 +500,15 @@ def fca_mlp_init_powers_batch(m: Mlp, ys) -> list:
     if torch.cuda.current_stream(ys[0].device).cuda_stream != m.stream:
         torch.cuda.synchronize(ys[0].device)
     return v0s
+
+
+def fca_set_learned_starts(ctx: Ctx, m: Mlp, mixtures=None):
+    """Learned starts from the mixtures the (FP32) context holds, for the
+    listed mixtures (default: all), in one inference launch; each is reset
+    to its new start and made active."""
+    if mixtures is None:
+        n, arr = ctx.B, None
+    else:
+        mixtures = [int(b) for b in mixtures]
+        n, arr = len(mixtures), (ctypes.c_int32 * len(mixtures))(*mixtures)
+    _check(lib().fca_set_learned_starts(ctx.handle, m.handle, n, arr), ctx)

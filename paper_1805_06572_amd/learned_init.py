@@ -75,8 +75,7 @@ def choose_starts(net, ctx, ys, judge_iter: int = 1):
     ll, _, _ = fca.fca_em_step(ctx, judge_iter + 1 if judge_iter > 0 else 0, want_R=False, want_v=False,
                                allow_flags=True)
     ll_plain = ll[:, judge_iter].cpu().numpy()
-    for b, v0 in enumerate(fca.fca_mlp_init_powers_batch(net, ys)):
-        fca.fca_set_start(ctx, b, v0=v0)
+    fca.fca_set_learned_starts(ctx, net)
     ll, _, _ = fca.fca_em_step(ctx, judge_iter + 1, want_R=False, want_v=False, allow_flags=True)
     ll_learned = ll[:, judge_iter].cpu().numpy()
     chosen = ll_learned > ll_plain

@@ -189,6 +189,55 @@ def test_batched_inference_equals_single_mixture_calls(fca, H):
         fca.fca_mlp_init_powers_batch(net, [ys[0], ys[0][:5]])
 
 
+def test_learned_starts_from_the_context_equal_set_start(fca):
+    """fca_set_learned_starts (inference on the context's own copy of y,
+    strided, writing the stored and working powers) gives the same EM run as
+    fca_set_start with fca_mlp_init_powers, bitwise; a subset of mixtures
+    keeps the others' starts; an FP64 context and a mismatched M are refused."""
+    net = fca.Mlp(4, seed=9, max_batch=256, hidden=64)
+    ys = [torch.from_numpy(synth.array_mixture(4, 9, n, seed=700 + n, complex64=True).y).cuda()
+          for n in (70, 129, 1)]
+    a = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+    b = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+    try:
+        fca.fca_em_step(a, 2, want_R=False, want_v=False, allow_flags=True)   # not at theta^0 any more
+        fca.fca_set_learned_starts(a, net, [0, 2])
+        for k in (0, 2):
+            fca.fca_set_start(b, k, v0=fca.fca_mlp_init_powers(net, ys[k]))
+        la, _, va = fca.fca_em_step(a, 3, want_R=False, allow_flags=True)
+        lb, _, vb = fca.fca_em_step(b, 3, want_R=False, allow_flags=True)
+        np.testing.assert_array_equal(la.cpu().numpy()[[0, 2]], lb.cpu().numpy()[[0, 2]])
+        for k in (0, 2):
+            np.testing.assert_array_equal(va[k].cpu().numpy(), vb[k].cpu().numpy())
+        # mixture 1 was not listed: it continues its own run (5 iterations in)
+        lone = fca.fca_init(ys[1], prec=fca.FCA_FP32_BULK)
+        try:
+            ll, _, _ = fca.fca_em_step(lone, 5, want_R=False, want_v=False, allow_flags=True)
+        finally:
+            fca.fca_destroy(lone)
+        np.testing.assert_array_equal(la.cpu().numpy()[1], ll.cpu().numpy()[0, 2:])
+        # after fca_reset every listed mixture is back at its learned start
+        fca.fca_reset(a)
+        lr, _, _ = fca.fca_em_step(a, 3, want_R=False, want_v=False, allow_flags=True)
+        np.testing.assert_array_equal(lr.cpu().numpy()[[0, 2]], lb.cpu().numpy()[[0, 2]])
+        with pytest.raises(fca.FcaError):
+            fca.fca_set_learned_starts(a, net, [3])
+    finally:
+        fca.fca_destroy(a)
+        fca.fca_destroy(b)
+    c64 = fca.fca_init(ys[0].to(torch.complex128), prec=fca.FCA_FP64)
+    c8 = fca.fca_init(torch.from_numpy(synth.array_mixture(2, 9, 30, seed=1, complex64=True).y).cuda(),
+                      prec=fca.FCA_FP32_BULK)
+    try:
+        with pytest.raises(fca.FcaError, match="FP32"):
+            fca.fca_set_learned_starts(c64, net)
+        with pytest.raises(fca.FcaError, match="M = 2"):
+            fca.fca_set_learned_starts(c8, net)
+    finally:
+        fca.fca_destroy(c64)
+        fca.fca_destroy(c8)
+
+
 def test_run_batch_chunk_schedule(fca):
     """A chunk sequence gives the same histories as single steps; the stop
     decision is taken at chunk boundaries only."""
