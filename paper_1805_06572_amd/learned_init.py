@@ -70,11 +70,12 @@ def choose_starts(net, ctx, ys, judge_iter: int = 1):
     plain theta^0. Returns (chosen [B] bool: learned start kept, ll_plain [B],
     ll_learned [B], advanced [B]: EM iterations already run from the chosen
     start)."""
-    # LL(theta^j) is computed in the pass of iteration j + 1 (j = 0: an
-    # evaluation-only pass)
-    ll, _, _ = fca.fca_em_step(ctx, judge_iter + 1 if judge_iter > 0 else 0, want_R=False, want_v=False,
-                               allow_flags=True)
-    ll_plain = ll[:, judge_iter].cpu().numpy()
+    # the plain run is thrown away: j iterations, then an evaluation-only pass
+    # for LL(theta^j)
+    if judge_iter > 0:
+        fca.fca_em_step(ctx, judge_iter, want_loglik=False, want_R=False, want_v=False, allow_flags=True)
+    ll, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False, allow_flags=True)
+    ll_plain = ll[:, 0].cpu().numpy()
     fca.fca_set_learned_starts(ctx, net)
     ll, _, _ = fca.fca_em_step(ctx, judge_iter + 1, want_R=False, want_v=False, allow_flags=True)
     ll_learned = ll[:, judge_iter].cpu().numpy()
