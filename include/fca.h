@@ -249,8 +249,8 @@ fca_status fca_graph_launch(fca_ctx *c, int32_t count);
  * entropy against soft targets. The learned start is
  * v_j^(0) = (r, 1 - r) * 2 ||y||^2 / M (r = 1/2 gives the plain start) and
  * reaches the EM only through fca_problem.v0. The forward GELU is
- * max(x, 0) - t P(t), t = min(|x|, 4), with P a fitted degree-7 polynomial
- * (|error| <= 1.3e-4 against x Phi(x)); the backward uses the exact GELU's
+ * max(x, 0) - t P(t), t = min(|x|, 4), with P a fitted degree-6 polynomial
+ * (|error| <= 2.1e-4 against x Phi(x)); the backward uses the exact GELU's
  * derivative. The network costs about 2 (32 H + 2 H^2 + H) flop and 3 H
  * GELUs per bin: at M = 4 the EM spends about 500 flop per bin and
  * iteration, so H = 256 costs as much as tens of EM iterations and H = 64

@@ -1,7 +1,7 @@
 """Fit of the polynomial GELU used by the MLP kernels (fca_mlp.hip).
 
 GELU(x) = x Phi(x) = max(x, 0) - t Phi(-t), t = |x|. The even tail
-t Phi(-t) is approximated by t P(t) with P of degree 7 on [0, T], T = 4,
+t Phi(-t) is approximated by t P(t) with P of degree 6 on [0, T], T = 4,
 and t is clamped to T beyond it (the tail is 1.3e-4 there). The fit is a
 weighted least-squares fit of t P(t) on a dense grid whose weights are
 raised where the residual is large (iteratively reweighted, which drives it
@@ -13,7 +13,7 @@ from __future__ import annotations
 import numpy as np
 from scipy.special import erfc
 
-T, DEG = 4.0, 7
+T, DEG = 4.0, 6
 
 
 def fit(T: float = T, deg: int = DEG, rounds: int = 60) -> np.ndarray:

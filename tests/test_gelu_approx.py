@@ -1,7 +1,7 @@
 """The MLP kernels' polynomial GELU, read from the kernel source, against
 the exact GELU x Phi(x) (scipy's erfc) on the whole line, evaluated in the
 kernel's FP32 order. Pins the constants: a dropped or mistyped coefficient,
-a wrong clamp or a sign error breaks the 1.3e-4 bound."""
+a wrong clamp or a sign error breaks the 2.1e-4 bound."""
 from __future__ import annotations
 
 import os
@@ -35,16 +35,16 @@ def gelu_f32(x, T, c):
 
 def test_kernel_gelu_within_bound_of_exact():
     T, c = kernel_gelu_constants()
-    assert T == 4.0 and len(c) == 8
+    assert T == 4.0 and len(c) == 7
     x = np.linspace(-30.0, 30.0, 600001)
     exact = x * 0.5 * erfc(-x / np.sqrt(2.0))
-    assert np.abs(gelu_f32(x, T, c) - exact).max() <= 1.35e-4
+    assert np.abs(gelu_f32(x, T, c) - exact).max() <= 2.1e-4
 
 
 def test_kernel_gelu_special_values():
     T, c = kernel_gelu_constants()
     g = gelu_f32(np.array([0.0, 1e-3, -1e-3, 1.0, -1.0, 1e4, -1e4]), T, c)
     assert abs(g[0]) <= 1e-6                          # GELU(0) = 0
-    assert abs(g[3] - 0.8413447460685429) <= 1.35e-4   # Phi(1)
-    assert abs(g[4] + 0.15865525393145707) <= 1.35e-4  # -Phi(-1)
-    assert abs(g[5] - 1e4) <= 1e-3 and abs(g[6]) <= 1.35e-4
+    assert abs(g[3] - 0.8413447460685429) <= 2.1e-4   # Phi(1)
+    assert abs(g[4] + 0.15865525393145707) <= 2.1e-4  # -Phi(-1)
+    assert abs(g[5] - 1e4) <= 1e-3 and abs(g[6]) <= 2.1e-4
