@@ -16,18 +16,16 @@ from . import fca, synth
 
 def train(M: int = 4, F: int = 513, steps: int = 400, batch: int = 8192, lr: float = 1e-3,
           weight_decay: float = 1e-4, seed: int = 0, chunk_steps: int = 50, log=None, hidden: int = 256):
-    """Train a network of hidden width `hidden` for M microphones; returns
+    """Train a network of hidden width `hidden` for M microphones on
+    independent bins drawn on the device (synth.array_bins_device); returns
     (Mlp, list of batch losses)."""
     net = fca.Mlp(M, seed=seed, max_batch=batch, hidden=hidden)
-    rng = np.random.default_rng(10_000 + seed)
+    g = torch.Generator(device=net.device).manual_seed(10_000 + seed)
     losses = []
     step = 0
     while step < steps:
         k = min(chunk_steps, steps - step)
-        y, fpos, r = synth.array_bins(k * batch, M, F, rng)
-        yt = torch.from_numpy(y).cuda()
-        ft = torch.from_numpy(fpos).cuda()
-        rt = torch.from_numpy(r).cuda()
+        yt, ft, rt = synth.array_bins_device(k * batch, M, F, g, device=net.device)
         for i in range(k):
             sl = slice(i * batch, (i + 1) * batch)
             loss, _ = fca.fca_mlp_backward(net, yt[sl], ft[sl], rt[sl])

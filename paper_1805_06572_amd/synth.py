@@ -183,6 +183,47 @@ def array_bins(n: int, M: int, F: int, rng: np.random.Generator):
     return y.astype(np.complex64), fpos, r
 
 
+def array_bins_device(n: int, M: int, F: int, g, device="cuda:0"):
+    """``array_bins`` drawn with torch on a device (the training batches of
+    the learned start): the same model, drawn as x_j = sqrt(v_j) (a_j w_j +
+    sqrt(0.1) Gamma(f)^(1/2) z_j) with w_j ~ CN(0, 1), z_j ~ CN(0, I), whose
+    covariance is v_j (a_j a_j^H + 0.1 Gamma(f)) (Gamma's square root per
+    frequency from its eigendecomposition, negative rounding clipped), and
+    torch's generator g, so the draws differ from the numpy version.
+    Returns device tensors y [n, M] complex64, fpos [n], r [n] float32."""
+    import torch
+
+    f32 = dict(device=device, dtype=torch.float32)
+    fr = bin_frequencies_hz(F)
+    mm = np.arange(M)
+    dist = np.abs(mm[:, None] - mm[None, :]) * MIC_SPACING_M
+    Gam = np.sinc(2.0 * fr[:, None, None] * dist[None] / SOUND_SPEED_MPS)     # [F, M, M] real
+    w, U = np.linalg.eigh(Gam)
+    BG = torch.from_numpy(U * np.sqrt(np.clip(w, 0.0, None))[:, None, :]).to(**f32)
+    u = torch.rand((n, 2), generator=g, **f32) * float(np.pi)
+    theta = torch.sort(u, dim=1).values                       # source 1: the smaller angle
+    k = torch.randint(0, F, (n,), generator=g, device=device)
+    fhz = torch.from_numpy(fr).to(**f32)[k]
+    mu, var = -1.9635100260214235, np.pi ** 2 / 2.0
+    v = torch.exp(mu + float(np.sqrt(var)) * torch.randn((n, 2), generator=g, **f32))
+    m = torch.arange(M, **f32)
+    y = torch.zeros((n, M), dtype=torch.complex64, device=device)
+
+    def cn(shape):
+        return torch.complex(torch.randn(shape, generator=g, **f32), torch.randn(shape, generator=g, **f32)) / float(
+            np.sqrt(2.0))
+    for j in range(2):
+        ph = -2.0 * np.pi * fhz[:, None] * m[None, :] * MIC_SPACING_M * torch.cos(theta[:, j:j + 1]) / SOUND_SPEED_MPS
+        a = torch.polar(torch.ones_like(ph), ph)                                 # [n, M]
+        z = cn((n, M))
+        diffuse = torch.complex(torch.matmul(BG[k], z.real[:, :, None])[:, :, 0],
+                                torch.matmul(BG[k], z.imag[:, :, None])[:, :, 0])
+        y = y + torch.sqrt(v[:, j])[:, None] * (a * cn((n, 1)) + float(np.sqrt(0.1)) * diffuse)
+    fpos = k.to(torch.float32) / max(F - 1, 1)
+    r = v[:, 0] / (v[:, 0] + v[:, 1])
+    return y, fpos, r
+
+
 def condition_numbers(R: np.ndarray) -> np.ndarray:
     """[F] max_j cond_2(R_j(f)) of the true covariances (a data property used
     to decide which bins a finite-precision comparison is meaningful on)."""

@@ -187,6 +187,16 @@ def test_batched_inference_equals_single_mixture_calls(fca, H):
         np.testing.assert_array_equal(g.cpu().numpy(), fca.fca_mlp_init_powers(net, y).cpu().numpy())
     with pytest.raises(ValueError):
         fca.fca_mlp_init_powers_batch(net, [ys[0], ys[0][:5]])
+    # the C entry point itself refuses empty or incomplete job lists
+    import ctypes
+    L = fca.lib()
+    assert L.fca_mlp_init_powers_batch(net.handle, 0, None, 17, None, None) == fca.FCA_E_ARG
+    k = 2
+    yp = (ctypes.c_void_p * k)(ys[0].data_ptr(), None)
+    vp = (ctypes.c_void_p * k)(got[0].data_ptr(), got[1].data_ptr())
+    nn = (ctypes.c_int32 * k)(130, 1)
+    assert L.fca_mlp_init_powers_batch(net.handle, k, yp, 17, nn, vp) == fca.FCA_E_ARG
+    assert "null buffer" in L.fca_mlp_last_error(net.handle).decode()
 
 
 def test_learned_starts_from_the_context_equal_set_start(fca):
