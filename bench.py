@@ -288,12 +288,12 @@ def run_large(args):
         # EM rates it above the plain start at iteration 0
         from paper_1805_06572_amd import learned_init
         t0 = time.perf_counter()
-        net, _ = learned_init.train(M=M, F=F, steps=args.train_steps // 2, batch=8192, seed=0, hidden=64)
+        net, _ = learned_init.train(M=M, F=F, steps=args.train_steps, batch=8192, seed=0, hidden=64)
         train_s = time.perf_counter() - t0
         chosen, ll_p, ll_l, _ = learned_init.choose_starts(net, run.ctx, ys)
         v0_mix0 = fca.fca_mlp_init_powers(net, ys[0]) if chosen[0] else None
         net.close()
-        learned = {"hidden": 64, "train_steps": args.train_steps // 2, "train_s": train_s,
+        learned = {"hidden": 64, "train_steps": args.train_steps, "train_s": train_s,
                    "learned_start_chosen": int(chosen.sum()),
                    "ll0_gain_where_chosen": float((ll_l - ll_p)[chosen].sum())}
     ms_step, em_ms = run.timed(args.steps, args.warmup)
@@ -425,7 +425,8 @@ def run_time_to_target(args):
     learned = {}
     for H in widths:
         t0 = time.perf_counter()
-        net, _ = learned_init.train(M=M, F=F, steps=args.train_steps, batch=8192, seed=0, hidden=H)
+        net, _ = learned_init.train(M=M, F=F, steps=args.train_steps, batch=8192, seed=0, hidden=H,
+                                    cosine=args.cosine)
         train_s = time.perf_counter() - t0
         bce, bce_const = learned_init.evaluate(net, n=65536, M=M, F=F)
         bl_ms, bl_init_ms, bl_iters, bl_hist, chosen, adv = batched(net)
@@ -479,7 +480,10 @@ def main():
     ap.add_argument("--F", type=int, default=513)
     ap.add_argument("--N", type=int, default=1000)
     ap.add_argument("--mixtures", type=int, default=256, help="time-to-target: held-out mixtures")
-    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--train-steps", type=int, default=None,
+                    help="training steps of 8192 bins for the learned start (default: 20000 for "
+                         "time-to-target, 2000 for the large workload)")
+    ap.add_argument("--cosine", action="store_true", help="time-to-target: cosine-decayed training rate")
     ap.add_argument("--plain-large", dest="learned_large", action="store_false",
                     help="large workload: plain start only (no learned start)")
     ap.add_argument("--hidden", default="64,256",
@@ -500,6 +504,8 @@ def main():
         sys.exit(2)
     if args.iters is None:
         args.iters = 100 if args.workload == "large" else 50
+    if args.train_steps is None:
+        args.train_steps = 2000 if args.workload == "large" else 20000
     import torch
     torch.cuda.set_device(0)
     runner = {"array": run_array, "batched": run_batched, "large": run_large,

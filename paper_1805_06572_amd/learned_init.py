@@ -15,10 +15,12 @@ from . import fca, synth
 
 
 def train(M: int = 4, F: int = 513, steps: int = 400, batch: int = 8192, lr: float = 1e-3,
-          weight_decay: float = 1e-4, seed: int = 0, chunk_steps: int = 50, log=None, hidden: int = 256):
+          weight_decay: float = 1e-4, seed: int = 0, chunk_steps: int = 50, log=None, hidden: int = 256,
+          cosine: bool = False):
     """Train a network of hidden width `hidden` for M microphones on
-    independent bins drawn on the device (synth.array_bins_device); returns
-    (Mlp, list of batch losses)."""
+    independent bins drawn on the device (synth.array_bins_device), AdamW at
+    rate lr (cosine: decayed to 0 over the steps); returns (Mlp, list of
+    batch losses)."""
     net = fca.Mlp(M, seed=seed, max_batch=batch, hidden=hidden)
     g = torch.Generator(device=net.device).manual_seed(10_000 + seed)
     losses = []
@@ -29,7 +31,9 @@ def train(M: int = 4, F: int = 513, steps: int = 400, batch: int = 8192, lr: flo
         for i in range(k):
             sl = slice(i * batch, (i + 1) * batch)
             loss, _ = fca.fca_mlp_backward(net, yt[sl], ft[sl], rt[sl])
-            fca.fca_mlp_adamw(net, lr=lr, weight_decay=weight_decay)
+            t = step + i
+            lr_t = lr * 0.5 * (1.0 + np.cos(np.pi * t / steps)) if cosine else lr
+            fca.fca_mlp_adamw(net, lr=lr_t, weight_decay=weight_decay)
             losses.append(loss)
         step += k
         if log:
