@@ -295,7 +295,7 @@ def run_large(args):
         net.close()
         learned = {"hidden": 64, "train_steps": args.train_steps, "train_s": train_s,
                    "learned_start_chosen": int(chosen.sum()),
-                   "ll0_gain_where_chosen": float((ll_l - ll_p)[chosen].sum())}
+                   "ll_gain_after_1_iteration_where_chosen": float((ll_l - ll_p)[chosen].sum())}
     ms_step, em_ms = run.timed(args.steps, args.warmup)
     flags = fca.fca_status_per_freq(run.ctx)
     run_R, run_v = run.R, run.v
