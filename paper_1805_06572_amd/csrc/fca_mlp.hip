@@ -536,6 +536,11 @@ void mlp_free(fca_mlp* m) {
 int layer_in(const fca_mlp* m, int l) { return l == 0 ? kKP : m->hidden; }
 
 hipError_t refresh_weights(fca_mlp* m) {
+    // an inference on another stream may still read the BF16 weights
+    if (m->jobs_done_ev) {
+        hipError_t e = hipStreamWaitEvent(m->stream, m->jobs_done_ev, 0);
+        if (e != hipSuccess) return e;
+    }
     for (int l = 0; l < kLayers; ++l) {
         const int64_t cnt = (int64_t)m->hidden * layer_in(m, l);
         mlp_weight_copy_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, m->stream>>>(
@@ -681,6 +686,9 @@ fca_status fca_mlp_create(int32_t M, int32_t hidden, uint64_t seed, int32_t max_
 void fca_mlp_destroy(fca_mlp* m) {
     if (!m) return;
     (void)hipStreamSynchronize(m->stream);
+    // an inference enqueued on another stream (fca_set_learned_starts) may
+    // still read the weights and the job table
+    if (m->jobs_done_ev) (void)hipEventSynchronize(m->jobs_done_ev);
     mlp_free(m);
     delete m;
 }

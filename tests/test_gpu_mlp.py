@@ -248,6 +248,33 @@ def test_learned_starts_from_the_context_equal_set_start(fca):
         fca.fca_destroy(c8)
 
 
+def test_learned_starts_on_another_stream_and_early_teardown(fca):
+    """A context on a side stream takes its learned starts from a network
+    created on the default stream; the network may be destroyed right after
+    the call (the teardown waits for the inference). Same run as on one
+    stream."""
+    ys = [torch.from_numpy(synth.array_mixture(4, 9, n, seed=900 + n, complex64=True).y).cuda() for n in (80, 33)]
+    net = fca.Mlp(4, seed=11, max_batch=256, hidden=64)
+    ref = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+    try:
+        fca.fca_set_learned_starts(ref, net)
+        want, _, _ = fca.fca_em_step(ref, 3, want_R=False, want_v=False, allow_flags=True)
+        want = want.cpu().numpy()
+    finally:
+        fca.fca_destroy(ref)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+        try:
+            fca.fca_set_learned_starts(ctx, net)
+            net.close()
+            got, _, _ = fca.fca_em_step(ctx, 3, want_R=False, want_v=False, allow_flags=True)
+            got = got.cpu().numpy()
+        finally:
+            fca.fca_destroy(ctx)
+    np.testing.assert_array_equal(got, want)
+
+
 def test_run_batch_chunk_schedule(fca):
     """A chunk sequence gives the same histories as single steps; the stop
     decision is taken at chunk boundaries only."""
