@@ -35,6 +35,7 @@ namespace {
 constexpr int kMaxHidden = 256;
 constexpr int kKP = 32;        // padded input width
 constexpr int kLayers = 3;     // hidden layers
+constexpr int kGradSplits = 16;  // K splits of the weight-gradient GEMMs (K = batch)
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -134,6 +135,8 @@ struct GemmArgs {
     bf16* out_bf;       // bf16 [rows][cols]: GELU(pre) (fwd) or dpre (bwd)
     bf16* out_bfT;      // bf16 [cols][ldt]: the same, transposed
     int ldt;
+    int kchunk;         // K per split (blockIdx.z; 0 = all of K); kEpiStore writes split z at
+                        // out_f32 + z rows cols
 };
 
 template <int EPI>
@@ -148,7 +151,10 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero8 = (bf16x8){(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
-    for (int k0 = 0; k0 < g.K; k0 += 32) {
+    const int kb = g.kchunk > 0 ? blockIdx.z * g.kchunk : 0;
+    const int ke = g.kchunk > 0 ? min(g.K, kb + g.kchunk) : g.K;
+    if (EPI == kEpiStore && g.kchunk > 0) g.out_f32 += (int64_t)blockIdx.z * g.rows * g.cols;
+    for (int k0 = kb; k0 < ke; k0 += 32) {
         bf16x8 av[2], bv[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
@@ -491,6 +497,7 @@ struct fca_mlp {
     bf16 *D = nullptr, *DT = nullptr, *D2 = nullptr, *D2T = nullptr;
     float *dz = nullptr, *r = nullptr;
     float* ogpart = nullptr;  // [max_batch / 64 + 1][H + 1] partial sums of the output-layer gradient
+    float* gpart = nullptr;   // [kGradSplits][H][H] split-K partial weight gradients
     double* loss_terms = nullptr;
     // fused-inference job tables (grown on demand): pinned staging, device copy
     InferJob* jobs_host = nullptr;
@@ -518,7 +525,7 @@ bool mlp_alloc(P** p, size_t bytes) {
 
 void mlp_free(fca_mlp* m) {
     void* ptrs[] = {m->p, m->g, m->m1, m->m2, m->X, m->XT, m->D, m->DT, m->D2, m->D2T, m->dz, m->r, m->ogpart,
-                    m->loss_terms, m->jobs_dev};
+                    m->loss_terms, m->jobs_dev, m->gpart};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (m->jobs_host) (void)hipHostFree(m->jobs_host);
@@ -551,9 +558,20 @@ hipError_t refresh_weights(fca_mlp* m) {
 
 template <int EPI>
 hipError_t gemm(hipStream_t s, const GemmArgs& a) {
-    const dim3 grid((a.cols + 63) / 64, (a.rows + 63) / 64);
+    const int splits = a.kchunk > 0 ? (a.K + a.kchunk - 1) / a.kchunk : 1;
+    const dim3 grid((a.cols + 63) / 64, (a.rows + 63) / 64, splits);
     mlp_gemm_kernel<EPI><<<grid, 256, 0, s>>>(a);
     return hipGetLastError();
+}
+
+// out[i] = sum over the splits z of part[z][i], in split order
+__global__ void mlp_split_sum_kernel(const float* __restrict__ part, int splits, int64_t count,
+                                     float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += part[z * count + i];
+    out[i] = s;
 }
 
 // forward of n <= max_batch bins (features, three hidden layers)
@@ -649,6 +667,7 @@ fca_status fca_mlp_create(int32_t M, int32_t hidden, uint64_t seed, int32_t max_
          mlp_alloc(&m->D2, (size_t)max_batch * hidden * 2) && mlp_alloc(&m->D2T, (size_t)max_batch * hidden * 2) &&
          mlp_alloc(&m->dz, (size_t)max_batch * 4) && mlp_alloc(&m->r, (size_t)max_batch * 4) &&
          mlp_alloc(&m->ogpart, (size_t)(max_batch / kOgRows + 1) * (hidden + 1) * 4) &&
+         mlp_alloc(&m->gpart, (size_t)kGradSplits * hidden * std::max(hidden, kKP) * 4) &&
          mlp_alloc(&m->loss_terms, (size_t)max_batch * 8);
     if (!ok) {
         mlp_free(m);
@@ -755,8 +774,18 @@ fca_status fca_mlp_backward(fca_mlp* m, const float* y, const float* fpos, const
         gw.K = n;
         gw.lda = m->ldt;
         gw.ldb = m->ldt;
-        gw.out_f32 = m->g + m->off_W[l];
+        // K = n is long and the output small: the K range is split over
+        // kGradSplits workgroup layers, summed afterwards in split order
+        gw.kchunk = ((n / kGradSplits + 31) / 32) * 32;
+        gw.out_f32 = m->gpart;
         MLP_HIP(m, gemm<kEpiStore>(s, gw));
+        {
+            const int splits = (n + gw.kchunk - 1) / gw.kchunk;
+            const int64_t cnt = (int64_t)gw.rows * gw.cols;
+            mlp_split_sum_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(m->gpart, splits, cnt,
+                                                                               m->g + m->off_W[l]);
+            MLP_HIP(m, hipGetLastError());
+        }
         mlp_bias_grad_kernel<<<hid, 256, 0, s>>>(dcurT, n, m->ldt, m->g + m->off_b[l]);
         MLP_HIP(m, hipGetLastError());
         if (l > 0) {

@@ -216,8 +216,8 @@ def array_bins_device(n: int, M: int, F: int, g, device="cuda:0"):
         ph = -2.0 * np.pi * fhz[:, None] * m[None, :] * MIC_SPACING_M * torch.cos(theta[:, j:j + 1]) / SOUND_SPEED_MPS
         a = torch.polar(torch.ones_like(ph), ph)                                 # [n, M]
         z = cn((n, M))
-        diffuse = torch.complex(torch.matmul(BG[k], z.real[:, :, None])[:, :, 0],
-                                torch.matmul(BG[k], z.imag[:, :, None])[:, :, 0])
+        Bk = BG[k]                                                              # [n, M, M] real
+        diffuse = torch.complex((Bk * z.real[:, None, :]).sum(-1), (Bk * z.imag[:, None, :]).sum(-1))
         y = y + torch.sqrt(v[:, j])[:, None] * (a * cn((n, 1)) + float(np.sqrt(0.1)) * diffuse)
     fpos = k.to(torch.float32) / max(F - 1, 1)
     r = v[:, 0] / (v[:, 0] + v[:, 1])
