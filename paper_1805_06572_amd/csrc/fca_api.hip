@@ -69,6 +69,11 @@ struct fca_ctx {
     double2* R_init = nullptr;
     double2* P = nullptr;
     double2* Pinv = nullptr;  // P^-1 per problem (for the separation)
+    // the stored start's basis (P, Lambda, log|det P|^2 of theta^(0)); with
+    // v_init it makes a reset a handful of whole-buffer copies
+    double2* P0 = nullptr;
+    double* lam0 = nullptr;
+    double* logdet0 = nullptr;
     double* lam = nullptr;
     double* logdet = nullptr;
     int* flags = nullptr;
@@ -165,7 +170,8 @@ fca_status dev_alloc(fca_ctx* c, P** p, size_t bytes) {
 
 void free_ctx_memory(fca_ctx* c) {
     void* dev[] = {c->y, c->v, c->v_init, c->R_init, c->P, c->Pinv, c->lam, c->logdet, c->flags, c->ll,
-                   c->ll_tot, c->fsum, c->R_stage, c->probs, c->x_off, c->probs_act, c->flag_sum};
+                   c->ll_tot, c->fsum, c->R_stage, c->probs, c->x_off, c->probs_act, c->flag_sum,
+                   c->P0, c->lam0, c->logdet0};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->ll_host) (void)hipHostFree(c->ll_host);
@@ -216,35 +222,64 @@ fca_status validate(const fca_problem* p, int b, const fca_problem* p0) {
     return FCA_OK;
 }
 
-// The basis of the initial values of mixture b: the FP64 GEVD of
-// (R1^(0), R2^(0)) read from R (R_init of the mixture unless a staged copy
-// is given). Enqueued only.
-fca_status reset_basis(fca_ctx* c, int b, const double2* R, hipStream_t s) {
+// The stored basis of mixture b: the FP64 GEVD of (R1^(0), R2^(0)) read from
+// R (R_init of the mixture unless a staged copy is given) into P0, lam0,
+// logdet0; status bits into flags. Enqueued only.
+fca_status compute_basis(fca_ctx* c, int b, const double2* R, hipStream_t s) {
     const MixInfo& mi = c->mix[b];
     const int64_t mm = (int64_t)mi.M * mi.M;
     const double2* R1 = R ? R : c->R_init + mi.R_base;
     const double2* R2 = R1 + (int64_t)c->F * mm;
-    FCA_HIP(c, launch_gevd(mi.M, c->F, R1, R2, mm, mm, c->P + (int64_t)mi.pid0 * kMaxM * kMaxM,
-                           kMaxM * kMaxM, c->lam + (int64_t)mi.pid0 * kMaxM, kMaxM,
-                           c->logdet + mi.pid0, c->flags + mi.pid0, s));
+    FCA_HIP(c, launch_gevd(mi.M, c->F, R1, R2, mm, mm, c->P0 + (int64_t)mi.pid0 * kMaxM * kMaxM,
+                           kMaxM * kMaxM, c->lam0 + (int64_t)mi.pid0 * kMaxM, kMaxM,
+                           c->logdet0 + mi.pid0, c->flags + mi.pid0, s));
     return FCA_OK;
 }
 
-// Initial values (Algorithm 1, step 1) of mixture b: v^(0) from v_init or the
-// plain start, then the basis (reset_basis). Enqueued only.
-fca_status reset_mixture(fca_ctx* c, int b, const double2* R, hipStream_t s) {
+// The stored start (Algorithm 1, step 1) of mixture b: v^(0) in v_init (the
+// plain start computed from y, unless a caller's v0 is stored there) and the
+// basis (compute_basis). Enqueued only.
+fca_status compute_start(fca_ctx* c, int b, const double2* R, hipStream_t s) {
     const MixInfo& mi = c->mix[b];
-    char* v = static_cast<char*>(c->v) + mi.v_base * c->rsz;
-    if (mi.has_v0) {
-        FCA_HIP(c, hipMemcpyAsync(v, static_cast<char*>(c->v_init) + mi.v_base * c->rsz,
-                                  2ull * c->F * mi.npad * c->rsz, hipMemcpyDeviceToDevice, s));
-    } else {
+    if (!mi.has_v0) {
         const void* yb = static_cast<char*>(c->y) + mi.y_base * c->esz;
         double* fs = c->fsum + (int64_t)b * (c->F + 1);
         FCA_HIP(c, launch_power_sums(c->fp64, yb, mi.M, c->F, mi.N, mi.npad, fs, s));
-        FCA_HIP(c, launch_default_v(c->fp64, yb, fs, mi.M, c->F, mi.N, mi.npad, v, s));
+        FCA_HIP(c, launch_default_v(c->fp64, yb, fs, mi.M, c->F, mi.N, mi.npad,
+                                    static_cast<char*>(c->v_init) + mi.v_base * c->rsz, s));
     }
-    return reset_basis(c, b, R, s);
+    return compute_basis(c, b, R, s);
+}
+
+// The working state of mixture b (v, P, Lambda, log|det P|^2, flags) back to
+// its stored start. Enqueued only.
+fca_status restore_start(fca_ctx* c, int b, hipStream_t s) {
+    const MixInfo& mi = c->mix[b];
+    const int64_t p0 = mi.pid0, F = c->F;
+    FCA_HIP(c, hipMemcpyAsync(static_cast<char*>(c->v) + mi.v_base * c->rsz,
+                              static_cast<char*>(c->v_init) + mi.v_base * c->rsz, 2ull * F * mi.npad * c->rsz,
+                              hipMemcpyDeviceToDevice, s));
+    FCA_HIP(c, hipMemcpyAsync(c->P + p0 * kMaxM * kMaxM, c->P0 + p0 * kMaxM * kMaxM,
+                              (size_t)F * kMaxM * kMaxM * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    FCA_HIP(c, hipMemcpyAsync(c->lam + p0 * kMaxM, c->lam0 + p0 * kMaxM, (size_t)F * kMaxM * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    FCA_HIP(c, hipMemcpyAsync(c->logdet + p0, c->logdet0 + p0, (size_t)F * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    FCA_HIP(c, launch_fill_u32(c->flags + p0, 0u, F, s));
+    return FCA_OK;
+}
+
+// The working state of every mixture back to its stored start: whole-buffer
+// copies and one fill (no memset, so it may be captured in a graph).
+// Enqueued only.
+fca_status restore_all(fca_ctx* c, hipStream_t s) {
+    const size_t np = (size_t)c->nprob;
+    FCA_HIP(c, hipMemcpyAsync(c->v, c->v_init, (size_t)c->v_tot * c->rsz, hipMemcpyDeviceToDevice, s));
+    FCA_HIP(c, hipMemcpyAsync(c->P, c->P0, np * kMaxM * kMaxM * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    FCA_HIP(c, hipMemcpyAsync(c->lam, c->lam0, np * kMaxM * sizeof(double), hipMemcpyDeviceToDevice, s));
+    FCA_HIP(c, hipMemcpyAsync(c->logdet, c->logdet0, np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    FCA_HIP(c, launch_fill_u32(c->flags, 0u, c->nprob, s));
+    return FCA_OK;
 }
 
 // The stored initial powers, allocated on first use. In FP32 contexts the
@@ -280,17 +315,17 @@ fca_status check_initial_flags(fca_ctx* c, int b0, int b1) {
     return FCA_OK;
 }
 
-// Initial values (Algorithm 1, step 1) for every mixture; all mixtures active.
+// Every mixture back to its stored start (Algorithm 1, step 1), all active;
+// waits for the stream.
 fca_status do_reset(fca_ctx* c) {
-    for (int b = 0; b < c->B; ++b) {
-        fca_status st = reset_mixture(c, b, nullptr, c->stream);
-        if (st != FCA_OK) return st;
-    }
+    fca_status st = restore_all(c, c->stream);
+    if (st != FCA_OK) return st;
     if (!c->all_active || c->act_dirty) c->shape_version += 1;
     std::fill(c->active.begin(), c->active.end(), 1);
     c->all_active = true;
     c->act_dirty = false;
-    return check_initial_flags(c, 0, c->B);
+    FCA_HIP(c, hipStreamSynchronize(c->stream));
+    return FCA_OK;
 }
 
 // Launch tables of the active mixtures (the full tables filtered, group
@@ -414,10 +449,14 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     c->v_tot = v_tot;
     c->active.assign(B, 1);
     FCA_TRY(dev_alloc(c, &c->v, 2 * v_tot * c->rsz));
-    if (any_v0) FCA_TRY(ensure_v_init(c));
+    (void)any_v0;
+    FCA_TRY(ensure_v_init(c));  // holds every mixture's stored start
     FCA_TRY(dev_alloc(c, &c->R_init, R_tot * sizeof(double2)));
     FCA_TRY(dev_alloc(c, &c->P, (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2)));
     FCA_TRY(dev_alloc(c, &c->Pinv, (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2)));
+    FCA_TRY(dev_alloc(c, &c->P0, (size_t)c->nprob * kMaxM * kMaxM * sizeof(double2)));
+    FCA_TRY(dev_alloc(c, &c->lam0, (size_t)c->nprob * kMaxM * sizeof(double)));
+    FCA_TRY(dev_alloc(c, &c->logdet0, (size_t)c->nprob * sizeof(double)));
     FCA_TRY(dev_alloc(c, &c->lam, (size_t)c->nprob * kMaxM * sizeof(double)));
     FCA_TRY(dev_alloc(c, &c->logdet, (size_t)c->nprob * sizeof(double)));
     FCA_TRY(dev_alloc(c, &c->flags, (size_t)c->nprob * sizeof(int)));
@@ -562,9 +601,11 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     }
     FCA_TRY(hipcall(hipStreamSynchronize(s), "hipStreamSynchronize"));
 
-    st = do_reset(c);
+    for (int b = 0; b < B; ++b) FCA_TRY(compute_start(c, b, nullptr, s));
+    st = check_initial_flags(c, 0, B);
     if (st == FCA_E_NOT_PD) st = FCA_E_ARG;
     FCA_TRY(st);
+    FCA_TRY(do_reset(c));
 #undef FCA_TRY
     *out = c;
     return FCA_OK;
@@ -606,11 +647,11 @@ fca_status fca_set_start(fca_ctx* c, int32_t b, const double* R0, const void* v0
     if (R0) {
         // stage, decompose and check before the mixture's stored start changes
         FCA_HIP(c, hipMemcpyAsync(c->R_stage, R0, rbytes, hipMemcpyDefault, s));
-        fca_status st = reset_mixture(c, b, c->R_stage, s);
+        fca_status st = compute_basis(c, b, c->R_stage, s);
         if (st != FCA_OK) return st;
         st = check_initial_flags(c, b, b + 1);
         if (st == FCA_E_NOT_PD) {
-            st = reset_mixture(c, b, nullptr, s);
+            st = compute_basis(c, b, nullptr, s);  // the stored basis of the old R0 again
             if (st == FCA_OK) st = check_initial_flags(c, b, b + 1);
             if (st == FCA_OK) {
                 set_err(c, "fca_set_start: R0 of mixture %d is not positive definite", b);
@@ -650,10 +691,10 @@ fca_status fca_set_start(fca_ctx* c, int32_t b, const double* R0, const void* v0
         FCA_HIP(c, e);
     }
     mi.has_v0 = v0 != nullptr;
-    c->shape_version += 1;  // a captured reset would copy or compute the old kind of start
-    fca_status st = reset_mixture(c, b, nullptr, s);
+    c->shape_version += 1;  // the start changed since any capture
+    fca_status st = compute_start(c, b, nullptr, s);
+    if (st == FCA_OK) st = restore_start(c, b, s);
     if (st != FCA_OK) return st;
-    FCA_HIP(c, launch_fill_u32(c->flags + mi.pid0, 0u, c->F, s));
     if (!c->active[b]) {
         c->active[b] = 1;
         c->act_dirty = true;
@@ -706,22 +747,32 @@ fca_status fca_set_learned_starts(fca_ctx* c, fca_mlp* m, int32_t count, const i
         return e == hipErrorOutOfMemory ? FCA_E_NOMEM : FCA_E_ARG;
     }
     FCA_HIP(c, e);
+    // the rest of theta^(0): the basis of the plain R (stored already unless
+    // a caller's R0 was in place), copied into the working state
     for (int b : list) {
         MixInfo& mi = c->mix[b];
         if (!mi.R_default) {
             FCA_HIP(c, launch_default_R(mi.M, c->F, c->R_init + mi.R_base, s));
             mi.R_default = true;
+            fca_status st = compute_basis(c, b, nullptr, s);
+            if (st != FCA_OK) return st;
         }
         mi.has_v0 = true;
-        fca_status st = reset_basis(c, b, nullptr, s);
-        if (st != FCA_OK) return st;
-        FCA_HIP(c, launch_fill_u32(c->flags + mi.pid0, 0u, c->F, s));
         if (!c->active[b]) {
             c->active[b] = 1;
             c->act_dirty = true;
         }
     }
-    c->shape_version += 1;  // a captured reset would compute the old kind of start
+    if (!mixtures && count == c->B) {
+        fca_status st = restore_all(c, s);
+        if (st != FCA_OK) return st;
+    } else {
+        for (int b : list) {
+            fca_status st = restore_start(c, b, s);
+            if (st != FCA_OK) return st;
+        }
+    }
+    c->shape_version += 1;  // the starts changed since any capture
     return FCA_OK;
 }
 
@@ -1205,11 +1256,8 @@ fca_status fca_graph_capture(fca_ctx* c, int32_t iters, int32_t with_reset, doub
     FCA_HIP(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     auto body = [&]() -> fca_status {
         if (with_reset) {
-            for (int b = 0; b < c->B; ++b) {
-                fca_status r = reset_mixture(c, b, nullptr, s);
-                if (r != FCA_OK) return r;
-            }
-            FCA_HIP(c, launch_fill_u32(c->flags, 0u, c->nprob, s));
+            fca_status r = restore_all(c, s);
+            if (r != FCA_OK) return r;
         }
         int done = 0;
         do {
