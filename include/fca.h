@@ -105,7 +105,9 @@ fca_status fca_init_batch(const fca_problem *p, int32_t B, fca_ctx **out);
 
 /* Set the initial values again from the R0 and v0 given at init (or the
  * plain start), clearing all per-frequency flags (Algorithm 1, step 1), and
- * make every mixture active again (fca_set_active). Allocates nothing. */
+ * make every mixture active again (fca_set_active). The starts are kept
+ * materialised (powers and the basis of their GEVD), so this is a few
+ * whole-buffer device copies; waits for the stream. Allocates nothing. */
 fca_status fca_reset(fca_ctx *c);
 
 /* Replace the initial values of mixture b and reset that mixture to them
@@ -116,10 +118,9 @@ fca_status fca_reset(fca_ctx *c);
  *       host or device, copied; must be positive.
  * The new start is what later fca_reset calls return to, and the mixture is
  * made active. A non-positive-definite R0 gives FCA_E_ARG and leaves mixture
- * b reset to its previous start. The first call with v0 != NULL on a context
- * created without any v0 allocates the context's start-power buffer. Runs
- * asynchronously on the context's stream unless R0 or v0 is a host pointer
- * or R0 is given (its definiteness is checked before returning). */
+ * b's stored start and current state as they were. Runs asynchronously on
+ * the context's stream unless v0 is a host pointer or R0 is given (its
+ * definiteness is checked before returning). */
 fca_status fca_set_start(fca_ctx *c, int32_t b, const double *R0, const void *v0);
 
 /* Take mixture b out of (active = 0) or back into (active != 0) later
