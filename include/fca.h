@@ -118,7 +118,8 @@ fca_status fca_reset(fca_ctx *c);
  *       host or device, copied; must be positive.
  * The new start is what later fca_reset calls return to, and the mixture is
  * made active. A non-positive-definite R0 gives FCA_E_ARG and leaves mixture
- * b's stored start and current state as they were. Runs asynchronously on
+ * b's stored start and its parameters as they were (its per-frequency flags
+ * are cleared). Runs asynchronously on
  * the context's stream unless v0 is a host pointer or R0 is given (its
  * definiteness is checked before returning). */
 fca_status fca_set_start(fca_ctx *c, int32_t b, const double *R0, const void *v0);
