@@ -251,35 +251,43 @@ fca_status compute_start(fca_ctx* c, int b, const double2* R, hipStream_t s) {
     return compute_basis(c, b, R, s);
 }
 
+// Copies of the stored start into the working state for problems
+// [p0, p0 + np) whose powers lie at [v0, v0 + nv) reals, and zero flags:
+// one launch (no memset or copy nodes when captured). Enqueued only.
+fca_status restore_range(fca_ctx* c, int64_t p0, int64_t np, int64_t v0, int64_t nv, hipStream_t s) {
+    auto w = [](const void* p) { return static_cast<const uint32_t*>(p); };
+    auto wd = [](void* p) { return static_cast<uint32_t*>(p); };
+    const int64_t vw = (int64_t)c->rsz / 4;  // words per real
+    WordSegs g{};
+    g.src[0] = w(static_cast<const char*>(c->v_init) + v0 * c->rsz);
+    g.dst[0] = wd(static_cast<char*>(c->v) + v0 * c->rsz);
+    g.end[0] = nv * vw;
+    g.src[1] = w(c->P0 + p0 * kMaxM * kMaxM);
+    g.dst[1] = wd(c->P + p0 * kMaxM * kMaxM);
+    g.end[1] = g.end[0] + np * kMaxM * kMaxM * 4;
+    g.src[2] = w(c->lam0 + p0 * kMaxM);
+    g.dst[2] = wd(c->lam + p0 * kMaxM);
+    g.end[2] = g.end[1] + np * kMaxM * 2;
+    g.src[3] = w(c->logdet0 + p0);
+    g.dst[3] = wd(c->logdet + p0);
+    g.end[3] = g.end[2] + np * 2;
+    g.src[4] = nullptr;
+    g.dst[4] = wd(c->flags + p0);
+    g.end[4] = g.end[3] + np;
+    FCA_HIP(c, launch_multi_copy(g, s));
+    return FCA_OK;
+}
+
 // The working state of mixture b (v, P, Lambda, log|det P|^2, flags) back to
 // its stored start. Enqueued only.
 fca_status restore_start(fca_ctx* c, int b, hipStream_t s) {
     const MixInfo& mi = c->mix[b];
-    const int64_t p0 = mi.pid0, F = c->F;
-    FCA_HIP(c, hipMemcpyAsync(static_cast<char*>(c->v) + mi.v_base * c->rsz,
-                              static_cast<char*>(c->v_init) + mi.v_base * c->rsz, 2ull * F * mi.npad * c->rsz,
-                              hipMemcpyDeviceToDevice, s));
-    FCA_HIP(c, hipMemcpyAsync(c->P + p0 * kMaxM * kMaxM, c->P0 + p0 * kMaxM * kMaxM,
-                              (size_t)F * kMaxM * kMaxM * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    FCA_HIP(c, hipMemcpyAsync(c->lam + p0 * kMaxM, c->lam0 + p0 * kMaxM, (size_t)F * kMaxM * sizeof(double),
-                              hipMemcpyDeviceToDevice, s));
-    FCA_HIP(c, hipMemcpyAsync(c->logdet + p0, c->logdet0 + p0, (size_t)F * sizeof(double),
-                              hipMemcpyDeviceToDevice, s));
-    FCA_HIP(c, launch_fill_u32(c->flags + p0, 0u, F, s));
-    return FCA_OK;
+    return restore_range(c, mi.pid0, c->F, mi.v_base, 2ll * c->F * mi.npad, s);
 }
 
-// The working state of every mixture back to its stored start: whole-buffer
-// copies and one fill (no memset, so it may be captured in a graph).
-// Enqueued only.
+// The working state of every mixture back to its stored start. Enqueued only.
 fca_status restore_all(fca_ctx* c, hipStream_t s) {
-    const size_t np = (size_t)c->nprob;
-    FCA_HIP(c, hipMemcpyAsync(c->v, c->v_init, (size_t)c->v_tot * c->rsz, hipMemcpyDeviceToDevice, s));
-    FCA_HIP(c, hipMemcpyAsync(c->P, c->P0, np * kMaxM * kMaxM * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    FCA_HIP(c, hipMemcpyAsync(c->lam, c->lam0, np * kMaxM * sizeof(double), hipMemcpyDeviceToDevice, s));
-    FCA_HIP(c, hipMemcpyAsync(c->logdet, c->logdet0, np * sizeof(double), hipMemcpyDeviceToDevice, s));
-    FCA_HIP(c, launch_fill_u32(c->flags, 0u, c->nprob, s));
-    return FCA_OK;
+    return restore_range(c, 0, c->nprob, 0, c->v_tot, s);
 }
 
 // The stored initial powers, allocated on first use. In FP32 contexts the

@@ -76,6 +76,22 @@ hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int
 // p[i] = val for count 32-bit words (a kernel, not a memset: graph-capturable).
 hipError_t launch_fill_u32(void* p, uint32_t val, int64_t count, hipStream_t s);
 
+// Segments of 32-bit words for launch_multi_copy: segment k copies
+// end[k] - end[k-1] words from src[k] to dst[k] (src null: writes zeros);
+// unused trailing segments repeat the last end.
+struct WordSegs {
+    static constexpr int kMax = 5;
+    const uint32_t* src[kMax];
+    uint32_t* dst[kMax];
+    int64_t end[kMax];
+};
+// launch_multi_copy's split of the segments into 16-byte or 4-byte units
+struct WordSegUnits {
+    int64_t end[WordSegs::kMax];
+    int vec[WordSegs::kMax];
+};
+hipError_t launch_multi_copy(const WordSegs& segs, hipStream_t s);
+
 // One mixture of a fused learned-start inference (fca_mlp.hip): y element
 // (f, n, microphone m) at y[f y_sf + n y_sn + m y_sm] (complex64); v_j(n,f)
 // written to out[j o_sj + f o_sf + n] and, if out2 is not null, to out2 at

@@ -56,6 +56,51 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t val, int64_t 
         p[i] = val;
 }
 
+// Up to WordSegs::kMax copies of 32-bit words (src null: fill with zero) in
+// one launch. Each segment is cut into units of 4 words (16-byte accesses)
+// when both its addresses are 16-byte aligned, else of 1 word; the units of
+// all segments form one index space.
+__global__ void multi_copy_kernel(WordSegs segs, WordSegUnits u) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < u.end[WordSegs::kMax - 1]; i += stride) {
+        int k = 0;
+        while (i >= u.end[k]) ++k;
+        const int64_t j = i - (k ? u.end[k - 1] : 0);
+        const uint32_t* src = segs.src[k];
+        uint32_t* dst = segs.dst[k];
+        const int64_t n = segs.end[k] - (k ? segs.end[k - 1] : 0);
+        if (u.vec[k]) {
+            const int64_t w = 4 * j;
+            if (w + 4 <= n) {
+                const uint4 val = src ? *reinterpret_cast<const uint4*>(src + w) : make_uint4(0u, 0u, 0u, 0u);
+                *reinterpret_cast<uint4*>(dst + w) = val;
+            } else {
+                for (int64_t q = w; q < n; ++q) dst[q] = src ? src[q] : 0u;
+            }
+        } else {
+            dst[j] = src ? src[j] : 0u;
+        }
+    }
+}
+
+hipError_t launch_multi_copy(const WordSegs& segs, hipStream_t s) {
+    WordSegUnits u{};
+    int64_t acc = 0, prev = 0;
+    for (int k = 0; k < WordSegs::kMax; ++k) {
+        const int64_t n = segs.end[k] - prev;
+        prev = segs.end[k];
+        const bool al = (reinterpret_cast<uintptr_t>(segs.dst[k]) % 16 == 0) &&
+                        (!segs.src[k] || reinterpret_cast<uintptr_t>(segs.src[k]) % 16 == 0);
+        u.vec[k] = al ? 1 : 0;
+        acc += al ? (n + 3) / 4 : n;
+        u.end[k] = acc;
+    }
+    if (acc <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>((acc + 255) / 256, 8192);
+    multi_copy_kernel<<<(unsigned)g, 256, 0, s>>>(segs, u);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(void* p, uint32_t val, int64_t count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     const int64_t g = std::min<int64_t>((count + 255) / 256, 4096);
