@@ -462,19 +462,21 @@ __global__ __launch_bounds__(256) void separate_kernel(const EmProblem* __restri
                                                        const int64_t* __restrict__ x_off) {
     using T2 = typename Vec2<T>::type;
     using MT = Math<T>;
-    __shared__ double2 sP[M * M];
-    __shared__ double2 sQ[M * M];  // P^-H
-    __shared__ double sLam[M];
+    __shared__ T2 sP[M * M];  // P and P^-H in the bulk precision
+    __shared__ T2 sQ[M * M];
+    __shared__ T sLam[M];
     const EmProblem pr = probs[blockIdx.y];
     if ((int)blockIdx.x * 256 >= pr.n) return;
     const int tid = threadIdx.x;
     const int64_t pbase = (int64_t)pr.pid * kMaxM * kMaxM;
     if (tid < M * M) {
-        sP[tid] = Pg[pbase + tid];
+        const double2 p = Pg[pbase + tid];
         const int a = tid / M, b = tid % M;
-        sQ[tid] = cconj(Pinv[pbase + b * M + a]);
+        const double2 q = cconj(Pinv[pbase + b * M + a]);
+        sP[tid] = make_vec2<T>((T)p.x, (T)p.y);
+        sQ[tid] = make_vec2<T>((T)q.x, (T)q.y);
     }
-    if (tid < M) sLam[tid] = lamg[(int64_t)pr.pid * kMaxM + tid];
+    if (tid < M) sLam[tid] = (T)lamg[(int64_t)pr.pid * kMaxM + tid];
     __syncthreads();
     const int n = blockIdx.x * 256 + tid;
     if (n >= pr.n) return;
@@ -492,11 +494,11 @@ __global__ __launch_bounds__(256) void separate_kernel(const EmProblem* __restri
         T sr = T(0), si = T(0);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const double2 p = sP[m * M + i];
-            sr = fma((T)p.x, yr[m], fma((T)p.y, yi[m], sr));
-            si = fma((T)p.x, yi[m], fma(-(T)p.y, yr[m], si));
+            const T2 p = sP[m * M + i];
+            sr = fma(p.x, yr[m], fma(p.y, yi[m], sr));
+            si = fma(p.x, yi[m], fma(-p.y, yr[m], si));
         }
-        const T g = a1 * (T)sLam[i] * MT::rcp(fma(a1, (T)sLam[i], a2));
+        const T g = a1 * sLam[i] * MT::rcp(fma(a1, sLam[i], a2));
         mr[i] = g * sr;
         mi[i] = g * si;
     }
@@ -507,9 +509,9 @@ __global__ __launch_bounds__(256) void separate_kernel(const EmProblem* __restri
         T sr = T(0), si = T(0);
 #pragma unroll
         for (int b = 0; b < M; ++b) {
-            const double2 q = sQ[a * M + b];
-            sr = fma((T)q.x, mr[b], fma(-(T)q.y, mi[b], sr));
-            si = fma((T)q.x, mi[b], fma((T)q.y, mr[b], si));
+            const T2 q = sQ[a * M + b];
+            sr = fma(q.x, mr[b], fma(-q.y, mi[b], sr));
+            si = fma(q.x, mi[b], fma(q.y, mr[b], si));
         }
         T2 o1, o2;
         o1.x = sr; o1.y = si;
