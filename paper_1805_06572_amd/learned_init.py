@@ -57,34 +57,34 @@ def evaluate(net, n: int = 65536, M: int = 4, F: int = 513, seed: int = 99):
     return bce, bce_const
 
 
-def choose_starts(net, ctx, ys, judge_iter: int = 1):
+def choose_starts(net, ctx, ys, choice_iter: int = 1):
     """Per mixture of a batched FP32 context, keep whichever of the plain and
-    the learned start has the higher log-likelihood after `judge_iter` EM
-    iterations, LL(theta^judge_iter) (both evaluated by the EM itself, all
-    mixtures in one batch per start). judge_iter = 0 compares the starts
+    the learned start has the higher log-likelihood after `choice_iter` EM
+    iterations, LL(theta^choice_iter) (both evaluated by the EM itself, all
+    mixtures in one batch per start). choice_iter = 0 compares the starts
     themselves; that favours the plain start, whose equal powers fit the
     mixture's total power well but leave the sources undistinguished, while
     one iteration is enough to show the learned start ahead.
 
     Expects ctx fresh, at its plain starts. The learned run is not thrown
     away: a mixture that keeps its learned start stays at
-    theta^(judge_iter + 1) of it; a mixture that falls back is reset to its
+    theta^(choice_iter + 1) of it; a mixture that falls back is reset to its
     plain theta^0. Returns (chosen [B] bool: learned start kept, ll_plain [B],
     ll_learned [B], advanced [B]: EM iterations already run from the chosen
     start)."""
     # the plain run is thrown away: j iterations, then an evaluation-only pass
     # for LL(theta^j)
-    if judge_iter > 0:
-        fca.fca_em_step(ctx, judge_iter, want_loglik=False, want_R=False, want_v=False, allow_flags=True)
+    if choice_iter > 0:
+        fca.fca_em_step(ctx, choice_iter, want_loglik=False, want_R=False, want_v=False, allow_flags=True)
     ll, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False, allow_flags=True)
     ll_plain = ll[:, 0].cpu().numpy()
     fca.fca_set_learned_starts(ctx, net)
-    ll, _, _ = fca.fca_em_step(ctx, judge_iter + 1, want_R=False, want_v=False, allow_flags=True)
-    ll_learned = ll[:, judge_iter].cpu().numpy()
+    ll, _, _ = fca.fca_em_step(ctx, choice_iter + 1, want_R=False, want_v=False, allow_flags=True)
+    ll_learned = ll[:, choice_iter].cpu().numpy()
     chosen = ll_learned > ll_plain
     for b in np.nonzero(~chosen)[0]:
         fca.fca_set_start(ctx, int(b))
-    advanced = np.where(chosen, judge_iter + 1, 0)
+    advanced = np.where(chosen, choice_iter + 1, 0)
     return chosen, ll_plain, ll_learned, advanced
 
 
