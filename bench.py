@@ -412,7 +412,7 @@ def run_time_to_target(args):
             if net is not None:
                 chosen, _, _, adv = learned_init.choose_starts(net, ctx, ys)
             t2 = time.perf_counter()
-            iters, hist = schedule.run_batch(ctx, 2 * L, (16, 8, 8, 4), stop)
+            iters, hist = schedule.run_batch(ctx, 2 * L, (16, 8, 4), stop)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
             fca.fca_destroy(ctx)
@@ -464,7 +464,7 @@ def run_time_to_target(args):
         "start_choice": "per mixture, the start with the higher LL after 1 EM iteration (plain start as "
                         "fallback); a kept learned start continues from its 2nd iterate",
         "stop_rule": "reached target, or LL rise below 1e-6 of the total (converged elsewhere), checked after "
-                     "16, 24, 32 and then every 4 iterations (each call reloads the frames: ~1 ms at 256 "
+                     "16, 24 and then every 4 iterations (each call reloads the frames: ~1 ms at 256 "
                      "mixtures)"}
     return rec
 
@@ -486,7 +486,7 @@ def main():
     ap.add_argument("--cosine", action="store_true", help="time-to-target: cosine-decayed training rate")
     ap.add_argument("--plain-large", dest="learned_large", action="store_false",
                     help="large workload: plain start only (no learned start)")
-    ap.add_argument("--hidden", default="64,256",
+    ap.add_argument("--hidden", default="32,64,256",
                     help="time-to-target: hidden widths of the learned-start networks (the first one is the "
                          "headline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

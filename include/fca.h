@@ -245,7 +245,7 @@ fca_status fca_graph_launch(fca_ctx *c, int32_t count);
  * A per-bin MLP predicts r = v1 / (v1 + v2) from features of y(n,f):
  * log(|y_m|^2 + 1e-20) for each microphone, cos and sin of the phase of y_m
  * relative to microphone 1 (m = 2..M), and f / (F - 1) (IN = 3M - 1 values,
- * zero-padded to 32). Three hidden layers of width H (64, 128 or 256) with
+ * zero-padded to 32). Three hidden layers of width H (32, 64, 128 or 256) with
  * GELU, one sigmoid output; BF16 weights and activations into MFMA, FP32
  * accumulation, FP32 master weights, AdamW; loss = mean binary cross-
  * entropy against soft targets. The learned start is
@@ -266,7 +266,7 @@ fca_status fca_graph_launch(fca_ctx *c, int32_t count);
 typedef struct fca_mlp fca_mlp;
 
 /* max_batch: largest n of one forward/backward call, a multiple of 64.
- * 2 <= M <= 8; hidden (H) is 64, 128 or 256, else FCA_E_ARG. Weights are
+ * 2 <= M <= 8; hidden (H) is 32, 64, 128 or 256, else FCA_E_ARG. Weights are
  * initialised from seed. All work runs on `stream`. */
 fca_status fca_mlp_create(int32_t M, int32_t hidden, uint64_t seed, int32_t max_batch, void *stream, fca_mlp **out);
 void fca_mlp_destroy(fca_mlp *m);

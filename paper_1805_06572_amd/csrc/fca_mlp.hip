@@ -6,7 +6,7 @@
 // through the v0 argument of fca_init.
 //
 // Network: x (IN = 3M - 1 features, zero-padded to KP = 32) -> 3 hidden
-// layers of width H (64, 128 or 256, chosen at creation) with GELU -> 1
+// layers of width H (32, 64, 128 or 256, chosen at creation) with GELU -> 1
 // logit -> sigmoid.
 // Features: log(|y_m|^2 + 1e-20) for each microphone, cos and sin of the
 // phase of y_m relative to microphone 1 (m = 2..M), and f / (F - 1).
@@ -310,37 +310,47 @@ __global__ void mlp_weight_copy_kernel(const float* __restrict__ W, int rows, in
 // One workgroup (4 waves) per tile of kTile bins of y[F][N][M] in the order
 // f N + n: features -> three hidden layers (BF16 MFMA 16x16x32, FP32
 // accumulation) -> output layer -> sigmoid -> v0[j][f][n]. The activations of
-// the tile stay in LDS; the weights are read from L2. Wave w owns the output
-// columns 16 CT w .. 16 CT (w + 1) - 1 of every layer (H = 64 CT) for all
-// rows of the tile (CT x kRT MFMA tiles). Same arithmetic as the training
+// the tile stay in LDS; the weights are read from L2. The waves split the
+// layer outputs into NCG column groups of 16 CT columns and 4 / NCG row
+// groups of 16 RT rows (InferShape): for H >= 64 each wave owns 16 CT =
+// H / 4 columns of all kTile rows, for H = 32 a pair of waves shares the 32
+// columns and each owns half the rows. Same arithmetic as the training
 // forward (features, bias, GELU, BF16 rounding of the hidden activations,
 // FP32 output layer) up to the order of the output-layer sum.
-constexpr int kRT = 8;            // row tiles of 16 per wave
+constexpr int kRT = 8;            // row tiles of 16 per tile
 constexpr int kTile = 16 * kRT;   // bins per workgroup
 constexpr int kXP = kKP + 8;      // LDS row pitch of the features (bf16)
+
+template <int H>
+struct InferShape {
+    static constexpr int NCG = H >= 64 ? 4 : H / 16;  // column groups (waves side by side)
+    static constexpr int CT = H / (16 * NCG);         // column tiles of 16 per wave
+    static constexpr int RT = kRT * NCG / 4;          // row tiles of 16 per wave
+    static_assert(H >= 32 && H % (16 * NCG) == 0 && NCG * (kRT / RT) == 4, "four waves per tile");
+};
 
 template <int H>
 struct InferShared {
     static constexpr int kHP = H + 8;  // LDS row pitch of the hidden activations (bf16)
     bf16 X[kTile * kXP];
     bf16 Hs[kTile * kHP];
-    float zp[4][kTile];
+    float zp[InferShape<H>::NCG][kTile];
     float sv[kTile];
 };
 
-// out^T = W A^T for this wave's 16 CT output columns and the tile's kTile
-// rows: acc[ct][rt] is the 16 x 16 block (columns c0 + 16 ct.., rows
-// 16 rt..), lane l holding columns c0 + 16 ct + 4 (l / 16) + q, q = 0..3, of
-// row 16 rt + l % 16 (the MFMA A operand is W, the B operand the
-// activations, both K-contiguous).
-template <int K, int LDA, int CT>
+// out^T = W A^T for this wave's 16 CT output columns and RT x 16 rows (A
+// points at the first of them): acc[ct][rt] is the 16 x 16 block (columns
+// c0 + 16 ct.., rows 16 rt..), lane l holding columns c0 + 16 ct + 4 (l / 16)
+// + q, q = 0..3, of row 16 rt + l % 16 (the MFMA A operand is W, the B
+// operand the activations, both K-contiguous).
+template <int K, int LDA, int CT, int RT>
 __device__ __forceinline__ void infer_layer(const bf16* __restrict__ A, const bf16* __restrict__ W, int c0, int lane,
-                                            f32x4 (&acc)[CT][kRT]) {
+                                            f32x4 (&acc)[CT][RT]) {
     const int li = lane & 15, lk = (lane >> 4) * 8;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-        for (int rt = 0; rt < kRT; ++rt) acc[ct][rt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int rt = 0; rt < RT; ++rt) acc[ct][rt] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int k0 = 0; k0 < K; k0 += 32) {
         bf16x8 wv[CT];
@@ -348,7 +358,7 @@ __device__ __forceinline__ void infer_layer(const bf16* __restrict__ A, const bf
         for (int ct = 0; ct < CT; ++ct)
             wv[ct] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(c0 + ct * 16 + li) * K + k0 + lk);
 #pragma unroll
-        for (int rt = 0; rt < kRT; ++rt) {
+        for (int rt = 0; rt < RT; ++rt) {
             const bf16x8 hv = *reinterpret_cast<const bf16x8*>(A + (rt * 16 + li) * LDA + k0 + lk);
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
@@ -357,10 +367,11 @@ __device__ __forceinline__ void infer_layer(const bf16* __restrict__ A, const bf
     }
 }
 
-// H = bf16(GELU(acc + bias)) for this wave's columns: four consecutive
-// columns of one row per lane and block (one 8-byte LDS write)
-template <int CT, int LDH>
-__device__ __forceinline__ void infer_store_hidden(const f32x4 (&acc)[CT][kRT], const float* __restrict__ bias,
+// H = bf16(GELU(acc + bias)) for this wave's columns and rows (Hs points at
+// the first row): four consecutive columns of one row per lane and block
+// (one 8-byte LDS write)
+template <int CT, int RT, int LDH>
+__device__ __forceinline__ void infer_store_hidden(const f32x4 (&acc)[CT][RT], const float* __restrict__ bias,
                                                    bf16* Hs, int c0, int lane) {
     const int li = lane & 15, cq = (lane >> 4) * 4;
 #pragma unroll
@@ -368,7 +379,7 @@ __device__ __forceinline__ void infer_store_hidden(const f32x4 (&acc)[CT][kRT], 
         const int col = c0 + ct * 16 + cq;
         const float4 b = *reinterpret_cast<const float4*>(bias + col);
 #pragma unroll
-        for (int rt = 0; rt < kRT; ++rt) {
+        for (int rt = 0; rt < RT; ++rt) {
             typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
             const f32x4 v = acc[ct][rt];
             const bf16x4 h = (bf16x4){(bf16)gelu(v[0] + b.x), (bf16)gelu(v[1] + b.y), (bf16)gelu(v[2] + b.z),
@@ -385,7 +396,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
     const InferJob* __restrict__ jobs, int njobs, int M, const bf16* __restrict__ W0, const bf16* __restrict__ W1,
     const bf16* __restrict__ W2, const float* __restrict__ bias0, const float* __restrict__ bias1,
     const float* __restrict__ bias2, const float* __restrict__ w4, const float* __restrict__ b4) {
-    constexpr int CT = H / 64;
+    using Shape = InferShape<H>;
+    constexpr int CT = Shape::CT, RT = Shape::RT, NCG = Shape::NCG;
     using Sh = InferShared<H>;
     extern __shared__ __align__(16) unsigned char smem[];
     Sh& sh = *reinterpret_cast<Sh*>(smem);
@@ -421,28 +433,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
         sh.sv[tid] = s;
     }
     __syncthreads();
-    const int c0 = w * 16 * CT;
-    f32x4 acc[CT][kRT];
-    infer_layer<kKP, kXP, CT>(sh.X, W0, c0, lane, acc);
-    infer_store_hidden<CT, Sh::kHP>(acc, bias0, sh.Hs, c0, lane);
+    const int cg = w % NCG, row0 = (w / NCG) * 16 * RT;  // this wave's column group and first row
+    const int c0 = cg * 16 * CT;
+    bf16* const hs = sh.Hs + row0 * Sh::kHP;
+    f32x4 acc[CT][RT];
+    infer_layer<kKP, kXP, CT, RT>(sh.X + row0 * kXP, W0, c0, lane, acc);
+    infer_store_hidden<CT, RT, Sh::kHP>(acc, bias0, hs, c0, lane);
     __syncthreads();
-    infer_layer<H, Sh::kHP, CT>(sh.Hs, W1, c0, lane, acc);
+    infer_layer<H, Sh::kHP, CT, RT>(hs, W1, c0, lane, acc);
     __syncthreads();  // every wave has read Hs before it is overwritten
-    infer_store_hidden<CT, Sh::kHP>(acc, bias1, sh.Hs, c0, lane);
+    infer_store_hidden<CT, RT, Sh::kHP>(acc, bias1, hs, c0, lane);
     __syncthreads();
-    infer_layer<H, Sh::kHP, CT>(sh.Hs, W2, c0, lane, acc);
+    infer_layer<H, Sh::kHP, CT, RT>(hs, W2, c0, lane, acc);
     // output layer: z = sum_c GELU(pre3_c) w4_c, this wave's columns per row
     const int li = lane & 15, cq = (lane >> 4) * 4;
-    float part[kRT];
+    float part[RT];
 #pragma unroll
-    for (int rt = 0; rt < kRT; ++rt) part[rt] = 0.0f;
+    for (int rt = 0; rt < RT; ++rt) part[rt] = 0.0f;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int col = c0 + ct * 16 + cq;
         const float4 b = *reinterpret_cast<const float4*>(bias2 + col);
         const float4 wc = *reinterpret_cast<const float4*>(w4 + col);
 #pragma unroll
-        for (int rt = 0; rt < kRT; ++rt) {
+        for (int rt = 0; rt < RT; ++rt) {
             const f32x4 v = acc[ct][rt];
             float x = part[rt];
             x = fmaf(gelu(v[0] + b.x), wc.x, x);
@@ -453,17 +467,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
         }
     }
 #pragma unroll
-    for (int rt = 0; rt < kRT; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
         float x = part[rt];
         x += __shfl_xor(x, 16, 64);
         x += __shfl_xor(x, 32, 64);
-        if (lane < 16) sh.zp[w][rt * 16 + li] = x;
+        if (lane < 16) sh.zp[cg][row0 + rt * 16 + li] = x;
     }
     __syncthreads();
     if (tid < kTile) {
         const int64_t bin = r0 + tid;
         if (bin < FN) {
-            const float z = ((sh.zp[0][tid] + sh.zp[1][tid]) + (sh.zp[2][tid] + sh.zp[3][tid])) + b4[0];
+            const float zs = NCG == 4 ? (sh.zp[0][tid] + sh.zp[1][tid]) + (sh.zp[2 % NCG][tid] + sh.zp[3 % NCG][tid])
+                                      : sh.zp[0][tid] + sh.zp[1 % NCG][tid];
+            const float z = zs + b4[0];
             const float r = 1.0f / (1.0f + expf(-z));
             const float ri = fminf(fmaxf(r, 1e-6f), 1.0f - 1e-6f);
             const float s = sh.sv[tid];
@@ -631,8 +647,8 @@ fca_status fca_mlp_create(int32_t M, int32_t hidden, uint64_t seed, int32_t max_
         g_mlp_error = "fca_mlp_create: need 2 <= M <= 8 and max_batch a positive multiple of 64";
         return FCA_E_ARG;
     }
-    if (hidden != 64 && hidden != 128 && hidden != kMaxHidden) {
-        g_mlp_error = "fca_mlp_create: hidden width must be 64, 128 or 256";
+    if (hidden != 32 && hidden != 64 && hidden != 128 && hidden != kMaxHidden) {
+        g_mlp_error = "fca_mlp_create: hidden width must be 32, 64, 128 or 256";
         return FCA_E_ARG;
     }
     fca_mlp* m = new (std::nothrow) fca_mlp();
@@ -920,6 +936,7 @@ hipError_t mlp_infer_jobs(fca_mlp* m, MlpInferJob* jobs, int count, hipStream_t 
         return e;
     if ((e = hipEventRecord(m->jobs_ev, s)) != hipSuccess) return e;
     switch (m->hidden) {
+        case 32: e = launch_infer<32>(m, m->jobs_dev, count, tiles, s); break;
         case 64: e = launch_infer<64>(m, m->jobs_dev, count, tiles, s); break;
         case 128: e = launch_infer<128>(m, m->jobs_dev, count, tiles, s); break;
         default: e = launch_infer<kMaxHidden>(m, m->jobs_dev, count, tiles, s); break;

@@ -16,7 +16,7 @@ def run_batch(ctx, max_iters: int, chunk, stop):
     """Run until every mixture is stopped or has had max_iters iterations.
 
     chunk: iterations per fca_em_step call, an int or a sequence of ints whose
-    last entry repeats (e.g. (16, 8, 8, 4): few calls while no mixture can be
+    last entry repeats (e.g. (16, 8, 4): few calls while no mixture can be
     done yet, fine steps later). stop(b, ll) -> bool is asked after every
     chunk with the log-likelihood
     history ll = [LL(theta^(0)), ..., LL(theta^(l-1))] of each still-active

@@ -39,7 +39,7 @@ def blocks(p, H):
     return out
 
 
-@pytest.mark.parametrize("M,H", [(2, 256), (4, 256), (8, 256), (4, 64), (8, 128)])
+@pytest.mark.parametrize("M,H", [(2, 256), (4, 256), (8, 256), (4, 64), (8, 128), (4, 32), (8, 32)])
 def test_forward_matches_reference(fca, M, H):
     net = fca.Mlp(M, seed=3, max_batch=1024, hidden=H)
     assert net.num_params == ref.num_params(H)
@@ -52,7 +52,7 @@ def test_forward_matches_reference(fca, M, H):
     assert np.corrcoef(got, want)[0, 1] > 0.99
 
 
-@pytest.mark.parametrize("H", [256, 64])
+@pytest.mark.parametrize("H", [256, 64, 32])
 def test_backward_matches_reference(fca, H):
     M = 4
     net = fca.Mlp(M, seed=5, max_batch=2048, hidden=H)
@@ -151,6 +151,7 @@ def test_batched_start_choice_and_per_mixture_stop(fca, choice_iter):
 
 
 @pytest.mark.parametrize("M,F,N,H", [(4, 33, 300, 256), (2, 5, 61, 256), (8, 17, 130, 256), (4, 33, 300, 64),
+                                     (4, 33, 300, 32), (2, 5, 61, 32), (8, 17, 130, 32),
                                      (8, 17, 130, 64), (3, 9, 77, 128)])
 def test_fused_learned_start_matches_forward_and_reference(fca, M, F, N, H):
     """fca_mlp_init_powers (one fused kernel per mixture, tiles of 128 bins
@@ -174,7 +175,7 @@ def test_fused_learned_start_matches_forward_and_reference(fca, M, F, N, H):
     np.testing.assert_allclose(r_gpu, want, atol=2e-2)
 
 
-@pytest.mark.parametrize("H", [64, 256])
+@pytest.mark.parametrize("H", [32, 64, 256])
 def test_batched_inference_equals_single_mixture_calls(fca, H):
     """fca_mlp_init_powers_batch (one launch over mixtures of uneven N,
     including ragged tiles and a one-frame mixture) gives bitwise the

@@ -18,7 +18,7 @@ def small_params(rng, H=256):
     return p
 
 
-@pytest.mark.parametrize("H", [256, 64])
+@pytest.mark.parametrize("H", [256, 64, 32])
 def test_gradient_matches_finite_differences(H):
     rng = np.random.default_rng(0)
     p = small_params(rng, H)
@@ -60,7 +60,7 @@ def test_bf16_rounding_is_nearest_even():
 
 
 def test_parameter_count_names_one_width():
-    for H in (64, 128, 256):
+    for H in (32, 64, 128, 256):
         assert mlp.hidden_width(mlp.num_params(H)) == H
     with pytest.raises(ValueError):
         mlp.hidden_width(mlp.num_params(64) + 1)
