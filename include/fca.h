@@ -255,8 +255,8 @@ fca_status fca_graph_launch(fca_ctx *c, int32_t count);
  * (|error| <= 2.1e-4 against x Phi(x)); the backward uses the exact GELU's
  * derivative. The network costs about 2 (32 H + 2 H^2 + H) flop and 3 H
  * GELUs per bin: at M = 4 the EM spends about 500 flop per bin and
- * iteration, so H = 256 costs as much as tens of EM iterations and H = 64
- * about ten times less.
+ * iteration, so H = 256 costs as much as tens of EM iterations, H = 64
+ * about ten times less and H = 32 about half of H = 64.
  * Parameter vector (fp32, flat): for each hidden layer l = 1..3 its weight
  * [H][in_l] (in_1 = 32, the padded input; in_2 = in_3 = H) then its bias
  * [H]; then the output weight [H] and bias [1].
