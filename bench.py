@@ -399,10 +399,13 @@ def run_time_to_target(args):
     def stop(b, ll):
         return hit_rule(b, ll) or conv_rule(b, ll)
 
-    def batched(net):
+    mask = args.mask_sharpen if args.mask_sharpen > 0 else None
+
+    def batched(net, mask=None):
         """Wall time of one batched FP32 run from context-ready to every
         mixture stopped, with the learned start of `net` (or the plain start
-        if None); warm: the same run once before, untimed."""
+        if None; with `mask`, the learned start's R from its masks sharpened
+        by that exponent); warm: the same run once before, untimed."""
         res = None
         for rep in range(2):
             ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
@@ -410,7 +413,7 @@ def run_time_to_target(args):
             t1 = time.perf_counter()
             chosen, adv = None, np.zeros(len(ys), dtype=int)
             if net is not None:
-                chosen, _, _, adv = learned_init.choose_starts(net, ctx, ys)
+                chosen, _, _, adv = learned_init.choose_starts(net, ctx, ys, mask_sharpen=mask)
             t2 = time.perf_counter()
             iters, hist = schedule.run_batch(ctx, 2 * L, (16, 8, 4), stop)
             torch.cuda.synchronize()
@@ -429,9 +432,20 @@ def run_time_to_target(args):
                                     cosine=args.cosine)
         train_s = time.perf_counter() - t0
         bce, bce_const = learned_init.evaluate(net, n=65536, M=M, F=F)
-        bl_ms, bl_init_ms, bl_iters, bl_hist, chosen, adv = batched(net)
+        bl_ms, bl_init_ms, bl_iters, bl_hist, chosen, adv = batched(net, mask)
         bl_hits = [first_hit(h, thr[k]) for k, h in enumerate(bl_hist)]
         bl_hits = [None if h is None else int(h + a) for h, a in zip(bl_hits, adv)]
+        extra = {}
+        if mask is not None and H == widths[0]:
+            # the same network without the mask-based R, for comparison
+            nm_ms, nm_init_ms, nm_iters, nm_hist, nm_chosen, nm_adv = batched(net, None)
+            nm_hits = [first_hit(h, thr[k]) for k, h in enumerate(nm_hist)]
+            nm_hits = [None if h is None else int(h + a) for h, a in zip(nm_hits, nm_adv)]
+            extra["without_mask_R"] = {
+                "batched_learned_start_fp32_ms": nm_ms, "start_choice_ms": nm_init_ms,
+                "speedup_vs_plain_fp64": plain64_ms / nm_ms, "mean_iterations_run": float(np.mean(nm_iters)),
+                "mean_iterations_to_target": float(np.mean([h for h in nm_hits if h is not None])),
+                "reached": sum(i is not None for i in nm_hits), "learned_start_chosen": int(np.sum(nm_chosen))}
         learned[H] = {
             "hidden": H, "batched_learned_start_fp32_ms": bl_ms, "start_choice_ms": bl_init_ms,
             "speedup_vs_plain_fp64": plain64_ms / bl_ms, "speedup_vs_plain_fp32": plain32_ms / bl_ms,
@@ -440,7 +454,8 @@ def run_time_to_target(args):
             "iterations_to_target": bl_hits, "reached": sum(i is not None for i in bl_hits),
             "learned_start_chosen": int(np.sum(chosen)),
             "mlp_train_s": train_s, "mlp_train_steps": args.train_steps,
-            "mlp_heldout_bce": bce, "constant_predictor_bce": bce_const}
+            "mlp_heldout_bce": bce, "constant_predictor_bce": bce_const,
+            "mask_R": None if mask is None else {"sharpen": mask, "load": 1e-3}, **extra}
         net.close()
     head = learned[widths[0]]
     bl_ms = head["batched_learned_start_fp32_ms"]
@@ -448,7 +463,8 @@ def run_time_to_target(args):
                       {"workload": f"time to target: {K} held-out array mixtures (AR(1) log-powers), M={M}, "
                                    f"F={F}, N={N}; target = LL of plain FastFCA (FP64, plain start) after "
                                    f"{L} iterations, reached at 99.9 % of its rise; learned start of hidden "
-                                   f"width {widths[0]}",
+                                   f"width {widths[0]}" + ("" if mask is None else
+                                                          f", R from its masks (sharpen {mask})"),
                        "mixtures": K, "M": M, "F": F, "N": N, "iterations": L, "hidden": widths[0]})
     rec["steps"], rec["warmup"] = 1, 1
     rec["time_to_target"] = {
@@ -462,7 +478,8 @@ def run_time_to_target(args):
                     "batched_plain": sum(i is not None for i in bp_hits)},
         "learned": [learned[H] for H in widths],
         "start_choice": "per mixture, the start with the higher LL after 1 EM iteration (plain start as "
-                        "fallback); a kept learned start continues from its 2nd iterate",
+                        "fallback); a kept learned start continues from its 2nd iterate; the learned start "
+                        "takes R from its masks (fca_set_mask_covariances) unless --mask-sharpen 0",
         "stop_rule": "reached target, or LL rise below 1e-6 of the total (converged elsewhere), checked after "
                      "16, 24 and then every 4 iterations (each call reloads the frames: ~1 ms at 256 "
                      "mixtures)"}
@@ -489,6 +506,9 @@ def main():
     ap.add_argument("--hidden", default="32,64,256",
                     help="time-to-target: hidden widths of the learned-start networks (the first one is the "
                          "headline)")
+    ap.add_argument("--mask-sharpen", type=float, default=3.0,
+                    help="time-to-target: sharpening exponent of the masks that give the learned start its R "
+                         "(0: plain R)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="time the eager calls instead of the captured step")

@@ -293,6 +293,21 @@ fca_status fca_mlp_adamw(fca_mlp *m, float lr, float beta1, float beta2, float e
  * network's stream). FCA_E_ARG for an FP64 context, a mixture index out of
  * range or a mixture whose M differs from the network's. */
 fca_status fca_set_learned_starts(fca_ctx *c, fca_mlp *m, int32_t count, const int32_t *mixtures);
+/* Initial spatial covariances from time-frequency masks (the experiments of
+ * Section 4 start from covariances estimated with masks; the paper gives no
+ * formula, this is the plain mask-weighted estimate). For each listed
+ * mixture (mixtures = NULL: mixtures 0..count-1) the masks come from its
+ * stored powers v_j^(0) (e.g. a learned start): r = v1 / (v1 + v2) (1/2
+ * where both are 0), sharpened to r^p / (r^p + (1 - r)^p) with p = sharpen,
+ * w_1 = r, w_2 = 1 - r. Then A_j(f) = sum_n w_j y y^H (FP64 sums) and
+ * R_j^(0)(f) = M A_j / tr(A_j) + load I ((1 + load) I where tr(A_j) = 0).
+ * These become the stored R start (the powers stay), the initial
+ * decomposition is recomputed, and the mixture is reset and made active.
+ * 1 <= sharpen <= 64, 0 < load <= 1e6, else FCA_E_ARG. If a decomposition
+ * fails (FCA_E_NOT_PD) every listed mixture gets the default R back and is
+ * still reset. Waits for the context's stream. A later fca_set_start without
+ * R0, or fca_set_learned_starts, puts the default R back. */
+fca_status fca_set_mask_covariances(fca_ctx *c, int32_t count, const int32_t *mixtures, double sharpen, double load);
 /* learned start for a mixture y [F][N][M] complex64 (contiguous, device):
  * v0_out [2][F][N] float (device), usable as fca_problem.v0. One fused
  * kernel, enqueued on the network's stream without waiting: v0_out is

@@ -93,6 +93,8 @@ struct fca_ctx {
     // the problems of active mixtures only (probs_act, groups_act; used by the
     // EM calls while some mixture is inactive), rebuilt lazily.
     std::vector<EmProblem> table;
+    MaskCovMix* mask_mix = nullptr;       // device table of fca_set_mask_covariances (B entries)
+    MaskCovMix* mask_mix_host = nullptr;  // pinned staging of it
     EmProblem* table_act = nullptr;  // pinned host staging of probs_act (nprob entries)
     hipEvent_t table_ev = nullptr;   // the last upload from table_act
     EmProblem* probs_act = nullptr;
@@ -171,12 +173,13 @@ fca_status dev_alloc(fca_ctx* c, P** p, size_t bytes) {
 void free_ctx_memory(fca_ctx* c) {
     void* dev[] = {c->y, c->v, c->v_init, c->R_init, c->P, c->Pinv, c->lam, c->logdet, c->flags, c->ll,
                    c->ll_tot, c->fsum, c->R_stage, c->probs, c->x_off, c->probs_act, c->flag_sum,
-                   c->P0, c->lam0, c->logdet0};
+                   c->P0, c->lam0, c->logdet0, c->mask_mix};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->ll_host) (void)hipHostFree(c->ll_host);
     if (c->flag_sum_host) (void)hipHostFree(c->flag_sum_host);
     if (c->table_act) (void)hipHostFree(c->table_act);
+    if (c->mask_mix_host) (void)hipHostFree(c->mask_mix_host);
     if (c->table_ev) (void)hipEventDestroy(c->table_ev);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -782,6 +785,121 @@ fca_status fca_set_learned_starts(fca_ctx* c, fca_mlp* m, int32_t count, const i
     }
     c->shape_version += 1;  // the starts changed since any capture
     return FCA_OK;
+}
+
+fca_status fca_set_mask_covariances(fca_ctx* c, int32_t count, const int32_t* mixtures, double sharpen, double load) {
+    if (!c) return FCA_E_ARG;
+    if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
+    if (count < 1 || count > c->B) {
+        set_err(c, "fca_set_mask_covariances: count %d outside 1..%d", count, c->B);
+        return FCA_E_ARG;
+    }
+    if (!(sharpen >= 1.0 && sharpen <= 64.0)) {
+        set_err(c, "fca_set_mask_covariances: sharpen %g outside [1, 64]", sharpen);
+        return FCA_E_ARG;
+    }
+    if (!(load > 0.0 && load <= 1e6)) {
+        set_err(c, "fca_set_mask_covariances: load %g outside (0, 1e6]", load);
+        return FCA_E_ARG;
+    }
+    std::vector<int> list(count);
+    for (int i = 0; i < count; ++i) {
+        const int b = mixtures ? mixtures[i] : i;
+        if (b < 0 || b >= c->B) {
+            set_err(c, "fca_set_mask_covariances: mixture %d outside 0..%d", b, c->B - 1);
+            return FCA_E_ARG;
+        }
+        list[i] = b;
+    }
+    const hipStream_t s = c->stream;
+    {
+        fca_status st = ensure_v_init(c);
+        if (st != FCA_OK) return st;
+    }
+    if (!c->mask_mix) {
+        fca_status st = dev_alloc(c, &c->mask_mix, sizeof(MaskCovMix) * c->B);
+        if (st != FCA_OK) return st;
+        if (hipHostMalloc(reinterpret_cast<void**>(&c->mask_mix_host), sizeof(MaskCovMix) * c->B) != hipSuccess) {
+            (void)hipGetLastError();
+            c->mask_mix_host = nullptr;
+            (void)hipFree(c->mask_mix);
+            c->mask_mix = nullptr;
+            set_err(c, "fca_set_mask_covariances: pinned allocation failed");
+            return FCA_E_NOMEM;
+        }
+    }
+    // one launch per microphone count; the staging is free again when this
+    // call returns (it ends with the stream synchronised)
+    int k = 0;
+    for (int M = 2; M <= kMaxM; ++M) {
+        const int k0 = k;
+        for (int b : list) {
+            const MixInfo& mi = c->mix[b];
+            if (mi.M == M) c->mask_mix_host[k++] = MaskCovMix{mi.y_base, mi.v_base, mi.R_base, mi.N, mi.npad};
+        }
+        if (k == k0) continue;
+        FCA_HIP(c, hipMemcpyAsync(c->mask_mix + k0, c->mask_mix_host + k0, sizeof(MaskCovMix) * (k - k0),
+                                  hipMemcpyHostToDevice, s));
+        FCA_HIP(c, launch_mask_cov(c->fp64, M, c->mask_mix + k0, k - k0, c->F, c->y, c->v_init, c->R_init, sharpen,
+                                   load, s));
+    }
+    // the bases: one decomposition launch per run of consecutive listed
+    // mixtures of equal M (their R blocks lie 2 F M^2 apart, their problems
+    // consecutive)
+    for (size_t i = 0; i < list.size();) {
+        const int b0 = list[i];
+        const MixInfo& m0 = c->mix[b0];
+        size_t e = i + 1;
+        while (e < list.size() && list[e] == list[e - 1] + 1 && c->mix[list[e]].M == m0.M) ++e;
+        const int nb = (int)(e - i);
+        const int64_t mm = (int64_t)m0.M * m0.M;
+        const double2* R1 = c->R_init + m0.R_base;
+        FCA_HIP(c, launch_gevd_runs(m0.M, nb * c->F, c->F, 2LL * c->F * mm, R1, R1 + (int64_t)c->F * mm, mm, mm,
+                                    c->P0 + (int64_t)m0.pid0 * kMaxM * kMaxM, kMaxM * kMaxM,
+                                    c->lam0 + (int64_t)m0.pid0 * kMaxM, kMaxM, c->logdet0 + m0.pid0,
+                                    c->flags + m0.pid0, s));
+        for (size_t k = i; k < e; ++k) c->mix[list[k]].R_default = false;
+        i = e;
+    }
+    const bool all = !mixtures && count == c->B;
+    fca_status st = FCA_OK;
+    if (all) {
+        st = check_initial_flags(c, 0, c->B);
+    } else {
+        for (int b : list)
+            if ((st = check_initial_flags(c, b, b + 1)) != FCA_OK) break;
+    }
+    if (st == FCA_E_NOT_PD) {
+        // back to the default R for every listed mixture
+        const std::string why = c->err;
+        for (int b : list) {
+            MixInfo& mi = c->mix[b];
+            FCA_HIP(c, launch_default_R(mi.M, c->F, c->R_init + mi.R_base, s));
+            mi.R_default = true;
+            fca_status st2 = compute_basis(c, b, nullptr, s);
+            if (st2 == FCA_OK) st2 = check_initial_flags(c, b, b + 1);
+            if (st2 != FCA_OK) return st2;
+        }
+        set_err(c, "fca_set_mask_covariances: %s; the listed mixtures keep the default R", why.c_str());
+    } else if (st != FCA_OK) {
+        return st;
+    }
+    for (int b : list) {
+        if (!c->active[b]) {
+            c->active[b] = 1;
+            c->act_dirty = true;
+        }
+    }
+    fca_status st3 = FCA_OK;
+    if (all) {
+        st3 = restore_all(c, s);
+    } else {
+        for (int b : list)
+            if ((st3 = restore_start(c, b, s)) != FCA_OK) break;
+    }
+    if (st3 != FCA_OK) return st3;
+    c->shape_version += 1;  // the starts changed since any capture
+    return st == FCA_E_NOT_PD ? FCA_E_NOT_PD : FCA_OK;
 }
 
 fca_status fca_set_active(fca_ctx* c, int32_t b, int32_t active) {

@@ -130,7 +130,25 @@ hipError_t launch_gevd(int M, int count, const double2* A, const double2* B, int
                        int64_t stride_b, double2* P, int64_t stride_p, double* lam, int64_t stride_l,
                        double* logdet, int* flags, hipStream_t s);
 
+// As launch_gevd for runs of `per` pencils: pencil i reads its inputs at
+// (i / per) outer + (i % per) stride_a (stride_b) and writes P, lam, logdet,
+// flags at index i.
+hipError_t launch_gevd_runs(int M, int count, int per, int64_t outer, const double2* A, const double2* B,
+                            int64_t stride_a, int64_t stride_b, double2* P, int64_t stride_p, double* lam,
+                            int64_t stride_l, double* logdet, int* flags, hipStream_t s);
+
 hipError_t launch_default_R(int M, int F, double2* R, hipStream_t s);
+
+// Mask-weighted initial covariances (mask_cov_kernel) of `count` mixtures of
+// M microphones (device table `mix`): y_int of a mixture at y_base (complex
+// elements, [f][m][npad]), its stored powers at v_base (reals, [j][f][npad]),
+// R_1 at R_base and R_2 at R_base + F M M (complex128, [f][M][M]).
+struct MaskCovMix {
+    int64_t y_base, v_base, R_base;
+    int32_t N, npad;
+};
+hipError_t launch_mask_cov(bool fp64, int M, const MaskCovMix* mix, int count, int F, const void* y, const void* v,
+                           double2* R, double p, double load, hipStream_t s);
 
 hipError_t launch_ll_reduce(const double* ll, int64_t ll_stride, int iters, int B, int F,
                             double* out, hipStream_t s);

@@ -260,8 +260,9 @@ hipError_t launch_copy_v_in(bool fp64, const void* v0, int F, int N, int npad, v
 // lam = 1.
 template <int M>
 __global__ __launch_bounds__(64) void gevd_kernel(const double2* __restrict__ A, const double2* __restrict__ B,
-                                                  int64_t stride_a, int64_t stride_b, double2* __restrict__ P,
-                                                  int64_t stride_p, double* __restrict__ lam, int64_t stride_l,
+                                                  int64_t stride_a, int64_t stride_b, int per, int64_t outer,
+                                                  double2* __restrict__ P, int64_t stride_p,
+                                                  double* __restrict__ lam, int64_t stride_l,
                                                   double* __restrict__ logdet, int* __restrict__ flags) {
     constexpr int MM = M * M;
     __shared__ double2 sA[MM], sB[MM], sId[MM], sPn[MM];
@@ -269,11 +270,13 @@ __global__ __launch_bounds__(64) void gevd_kernel(const double2* __restrict__ A,
     __shared__ GevdScratch sWs;
     const int64_t i = blockIdx.x;
     const int tid = threadIdx.x;
+    // pencil i of run i / per: its inputs at (i / per) outer + (i % per) stride
+    const int64_t ia = (i / per) * outer + (i % per) * stride_a, ib = (i / per) * outer + (i % per) * stride_b;
     if (tid < MM) {
         const int r = tid / M, c = tid % M;
         // Hermitian inputs: build the full matrices from the upper triangles
-        const double2 a = (r <= c) ? A[i * stride_a + r * M + c] : cconj(A[i * stride_a + c * M + r]);
-        const double2 b = (r <= c) ? B[i * stride_b + r * M + c] : cconj(B[i * stride_b + c * M + r]);
+        const double2 a = (r <= c) ? A[ia + r * M + c] : cconj(A[ia + c * M + r]);
+        const double2 b = (r <= c) ? B[ib + r * M + c] : cconj(B[ib + c * M + r]);
         sA[tid] = (r == c) ? make_double2(a.x, 0.0) : a;
         sB[tid] = (r == c) ? make_double2(b.x, 0.0) : b;
         sId[tid] = make_double2(r == c ? 1.0 : 0.0, 0.0);
@@ -291,15 +294,16 @@ __global__ __launch_bounds__(64) void gevd_kernel(const double2* __restrict__ A,
     }
 }
 
-hipError_t launch_gevd(int M, int count, const double2* A, const double2* B, int64_t stride_a,
-                       int64_t stride_b, double2* P, int64_t stride_p, double* lam, int64_t stride_l,
-                       double* logdet, int* flags, hipStream_t s) {
+hipError_t launch_gevd_runs(int M, int count, int per, int64_t outer, const double2* A, const double2* B,
+                            int64_t stride_a, int64_t stride_b, double2* P, int64_t stride_p, double* lam,
+                            int64_t stride_l, double* logdet, int* flags, hipStream_t s) {
     if (count <= 0) return hipSuccess;
+    if (per < 1) return hipErrorInvalidValue;
     switch (M) {
-#define FCA_GEVD_CASE(MM_)                                                                                  \
-    case MM_:                                                                                               \
-        gevd_kernel<MM_><<<count, 64, 0, s>>>(A, B, stride_a, stride_b, P, stride_p, lam, stride_l, logdet, \
-                                              flags);                                                       \
+#define FCA_GEVD_CASE(MM_)                                                                                 \
+    case MM_:                                                                                              \
+        gevd_kernel<MM_><<<count, 64, 0, s>>>(A, B, stride_a, stride_b, per, outer, P, stride_p, lam,     \
+                                              stride_l, logdet, flags);                                    \
         break;
         FCA_GEVD_CASE(1) FCA_GEVD_CASE(2) FCA_GEVD_CASE(3) FCA_GEVD_CASE(4)
         FCA_GEVD_CASE(5) FCA_GEVD_CASE(6) FCA_GEVD_CASE(7) FCA_GEVD_CASE(8)
@@ -307,6 +311,13 @@ hipError_t launch_gevd(int M, int count, const double2* A, const double2* B, int
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_gevd(int M, int count, const double2* A, const double2* B, int64_t stride_a,
+                       int64_t stride_b, double2* P, int64_t stride_p, double* lam, int64_t stride_l,
+                       double* logdet, int* flags, hipStream_t s) {
+    return launch_gevd_runs(M, count, count > 0 ? count : 1, 0, A, B, stride_a, stride_b, P, stride_p, lam,
+                            stride_l, logdet, flags, s);
 }
 
 // R1 = I, R2 = I + 0.5 e1 e1^H at every frequency: R[2][F][M][M].
@@ -326,6 +337,149 @@ __global__ void default_R_kernel(int M, int F, double2* __restrict__ R) {
 hipError_t launch_default_R(int M, int F, double2* R, hipStream_t s) {
     default_R_kernel<<<grid_for(2LL * F * M * M, 256), 256, 0, s>>>(M, F, R);
     return hipGetLastError();
+}
+
+// ============================================================== mask-weighted covariances
+// Initial spatial covariances from time-frequency masks (the kind of start the
+// experiments of Section 4 use): with r = v1 / (v1 + v2) of the stored
+// powers (1/2 where both vanish), sharpened to r^p / (r^p + (1 - r)^p), the
+// masks are w_1 = r and w_2 = 1 - r, A_j = sum_n w_j y y^H, and
+// R_j = M A_j / tr(A_j) + load I (trace M before the loading; (1 + load) I
+// where tr(A_j) = 0). One workgroup per (mixture, frequency): blockIdx.x = f,
+// blockIdx.y = entry of `mix`. The upper triangles of A_j are FP64 register
+// sums (both sources in one pass over the frames for M <= 4, one source per
+// pass above), reduced in a fixed order (wave butterflies, then the four
+// waves in order). An integer p is applied by repeated multiplication.
+__device__ __forceinline__ double mask_power(double r, double p, int ip) {
+    if (ip > 0) {
+        double x = r;
+        for (int k = 1; k < ip; ++k) x *= r;
+        return x;
+    }
+    return pow(r, p);
+}
+
+template <int M, typename T>
+__global__ __launch_bounds__(256) void mask_cov_kernel(const MaskCovMix* __restrict__ mix, int F,
+                                                       const typename Vec2<T>::type* __restrict__ y,
+                                                       const T* __restrict__ v, double2* __restrict__ R, double p,
+                                                       double load) {
+    constexpr int NU = M * (M + 1) / 2;  // upper-triangle entries
+    constexpr int NS = M <= 4 ? 2 : 1;   // sources per pass
+    __shared__ double red[4][NS][2 * NU];
+    const MaskCovMix mx = mix[blockIdx.y];
+    const int f = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int ip = (p == floor(p) && p <= 64.0) ? (int)p : 0;  // integer exponent, or 0
+    const auto* yf = y + mx.y_base + (int64_t)f * M * mx.npad;
+    const T* v1 = v + mx.v_base + (int64_t)f * mx.npad;
+    const T* v2 = v1 + (int64_t)F * mx.npad;
+    for (int j0 = 0; j0 < 2; j0 += NS) {
+        double are[NS][NU], aim[NS][NU];
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+#pragma unroll
+            for (int u = 0; u < NU; ++u) are[q][u] = aim[q][u] = 0.0;
+        for (int n = tid; n < mx.N; n += 256) {
+            const double a = (double)v1[n], b = (double)v2[n];
+            double r = (a + b > 0.0) ? a / (a + b) : 0.5;
+            if (p != 1.0) {
+                const double rp = mask_power(r, p, ip), sp = mask_power(1.0 - r, p, ip);
+                r = rp / (rp + sp);
+            }
+            double yr[M], yi[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const auto ym = yf[(int64_t)m * mx.npad + n];
+                yr[m] = (double)ym.x;
+                yi[m] = (double)ym.y;
+            }
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const double wt = (j0 + q) == 0 ? r : 1.0 - r;
+                int u = 0;
+#pragma unroll
+                for (int i = 0; i < M; ++i) {
+                    const double wr = wt * yr[i], wi = wt * yi[i];
+#pragma unroll
+                    for (int k = i; k < M; ++k, ++u) {  // w y_i conj(y_k)
+                        are[q][u] = fma(wr, yr[k], fma(wi, yi[k], are[q][u]));
+                        aim[q][u] = fma(wi, yr[k], fma(-wr, yi[k], aim[q][u]));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                double x = are[q][u], z = aim[q][u];
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    x += __shfl_xor(x, off, 64);
+                    z += __shfl_xor(z, off, 64);
+                }
+                if (lane == 0) {
+                    red[w][q][u] = x;
+                    red[w][q][NU + u] = z;
+                }
+            }
+        __syncthreads();
+        if (tid < NS * M * M) {
+            const int q = tid / (M * M), e = tid % (M * M);
+            const int i = e / M, k = e % M;
+            const int a = i < k ? i : k, c = i < k ? k : i;  // upper entry (a, c)
+            const int u = a * M - a * (a - 1) / 2 + (c - a);
+            double tr = 0.0;
+            for (int d = 0; d < M; ++d) {
+                const int ud = d * M - d * (d - 1) / 2;
+                tr += ((red[0][q][ud] + red[1][q][ud]) + (red[2][q][ud] + red[3][q][ud]));
+            }
+            const double xr = (red[0][q][u] + red[1][q][u]) + (red[2][q][u] + red[3][q][u]);
+            double xi = (red[0][q][NU + u] + red[1][q][NU + u]) + (red[2][q][NU + u] + red[3][q][NU + u]);
+            if (i > k) xi = -xi;  // lower entry: conjugate
+            double2 out;
+            if (tr > 0.0) {
+                out.x = (double)M * xr / tr;
+                out.y = (double)M * xi / tr;
+            } else {
+                out.x = i == k ? 1.0 : 0.0;
+                out.y = 0.0;
+            }
+            if (i == k) {
+                out.x += load;
+                out.y = 0.0;
+            }
+            R[mx.R_base + (int64_t)(j0 + q) * F * M * M + (int64_t)f * M * M + e] = out;
+        }
+        __syncthreads();  // red is reused by the next pass
+    }
+}
+
+template <typename T>
+static hipError_t launch_mask_cov_t(int M, const MaskCovMix* mix, int count, int F, const void* y, const void* v,
+                                    double2* R, double p, double load, hipStream_t s) {
+    const dim3 grid((unsigned)F, (unsigned)count);
+    using T2 = typename Vec2<T>::type;
+    const T2* yy = static_cast<const T2*>(y);
+    const T* vv = static_cast<const T*>(v);
+    switch (M) {
+        case 2: mask_cov_kernel<2, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 3: mask_cov_kernel<3, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 4: mask_cov_kernel<4, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 5: mask_cov_kernel<5, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 6: mask_cov_kernel<6, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 7: mask_cov_kernel<7, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 8: mask_cov_kernel<8, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_cov(bool fp64, int M, const MaskCovMix* mix, int count, int F, const void* y, const void* v,
+                           double2* R, double p, double load, hipStream_t s) {
+    if (count < 1 || count > 65535 || F < 1) return hipErrorInvalidValue;
+    return fp64 ? launch_mask_cov_t<double>(M, mix, count, F, y, v, R, p, load, s)
+                : launch_mask_cov_t<float>(M, mix, count, F, y, v, R, p, load, s);
 }
 
 // ============================================================== log-likelihood totals

@@ -326,7 +326,7 @@ struct InferShape {
     static constexpr int NCG = H >= 64 ? 4 : H / 16;  // column groups (waves side by side)
     static constexpr int CT = H / (16 * NCG);         // column tiles of 16 per wave
     static constexpr int RT = kRT * NCG / 4;          // row tiles of 16 per wave
-    static_assert(H >= 32 && H % (16 * NCG) == 0 && NCG * (kRT / RT) == 4, "four waves per tile");
+    static_assert((NCG == 2 || NCG == 4) && H % (16 * NCG) == 0 && NCG * (kRT / RT) == 4, "four waves per tile");
 };
 
 template <int H>
@@ -477,8 +477,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
     if (tid < kTile) {
         const int64_t bin = r0 + tid;
         if (bin < FN) {
-            const float zs = NCG == 4 ? (sh.zp[0][tid] + sh.zp[1][tid]) + (sh.zp[2 % NCG][tid] + sh.zp[3 % NCG][tid])
-                                      : sh.zp[0][tid] + sh.zp[1 % NCG][tid];
+            float zs;  // the column groups' partial sums, in a fixed order
+            if constexpr (NCG == 4) zs = (sh.zp[0][tid] + sh.zp[1][tid]) + (sh.zp[2][tid] + sh.zp[3][tid]);
+            else zs = sh.zp[0][tid] + sh.zp[1][tid];
             const float z = zs + b4[0];
             const float r = 1.0f / (1.0f + expf(-z));
             const float ri = fminf(fmaxf(r, 1e-6f), 1.0f - 1e-6f);

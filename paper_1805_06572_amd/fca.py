@@ -37,7 +37,8 @@ EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set
             "fca_launch_groups", "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch",
             "fca_mlp_create", "fca_mlp_destroy", "fca_mlp_num_params", "fca_mlp_last_error",
             "fca_mlp_get_params", "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward",
-            "fca_mlp_adamw", "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts"]
+            "fca_mlp_adamw", "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
+            "fca_set_mask_covariances"]
 
 
 class fca_problem(ctypes.Structure):
@@ -102,6 +103,7 @@ def lib() -> ctypes.CDLL:
         L.fca_mlp_init_powers_batch.argtypes = [vp, i32, ctypes.POINTER(vp), i32, ctypes.POINTER(i32),
                                                 ctypes.POINTER(vp)]
         L.fca_set_learned_starts.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
+        L.fca_set_mask_covariances.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.c_double, ctypes.c_double]
         for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set_active", "fca_em_step", "fca_conv_em_step", "fca_separate",
                      "fca_status_per_freq", "fca_gevd", "fca_timing", "fca_launch_groups",
                      "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch", "fca_mlp_create", "fca_mlp_get_params",
@@ -512,3 +514,17 @@ def fca_set_learned_starts(ctx: Ctx, m: Mlp, mixtures=None):
         mixtures = [int(b) for b in mixtures]
         n, arr = len(mixtures), (ctypes.c_int32 * len(mixtures))(*mixtures)
     _check(lib().fca_set_learned_starts(ctx.handle, m.handle, n, arr), ctx)
+
+
+def fca_set_mask_covariances(ctx: Ctx, mixtures=None, sharpen: float = 3.0, load: float = 1e-3):
+    """Initial R_j from time-frequency masks made of the stored powers of the
+    listed mixtures (default: all): r = v1 / (v1 + v2) sharpened to
+    r^p / (r^p + (1 - r)^p), R_j = M A_j / tr A_j + load I with
+    A_j = sum_n w_j y y^H (w_1 = r, w_2 = 1 - r); each mixture is reset to its
+    new start and made active."""
+    if mixtures is None:
+        n, arr = ctx.B, None
+    else:
+        mixtures = [int(b) for b in mixtures]
+        n, arr = len(mixtures), (ctypes.c_int32 * len(mixtures))(*mixtures)
+    _check(lib().fca_set_mask_covariances(ctx.handle, n, arr, float(sharpen), float(load)), ctx)

@@ -4,7 +4,9 @@ Trains the library's per-bin network (fca_mlp_*, hand-written HIP kernels)
 on independent bins of the array workload, and produces the learned start
 v_j^(0) = (r, 1 - r) 2 ||y||^2 / M for a mixture. The plain start stays the
 fallback: `choose_starts` evaluates the log-likelihood of both starts with
-the EM itself (after one iteration by default) and keeps the better one.
+the EM itself (after one iteration by default) and keeps the better one. The
+learned powers can also serve as time-frequency masks for the initial
+spatial covariances (fca_set_mask_covariances).
 """
 from __future__ import annotations
 
@@ -57,7 +59,7 @@ def evaluate(net, n: int = 65536, M: int = 4, F: int = 513, seed: int = 99):
     return bce, bce_const
 
 
-def choose_starts(net, ctx, ys, choice_iter: int = 1):
+def choose_starts(net, ctx, ys, choice_iter: int = 1, mask_sharpen=None, mask_load: float = 1e-3):
     """Per mixture of a batched FP32 context, keep whichever of the plain and
     the learned start has the higher log-likelihood after `choice_iter` EM
     iterations, LL(theta^choice_iter) (both evaluated by the EM itself, all
@@ -65,6 +67,10 @@ def choose_starts(net, ctx, ys, choice_iter: int = 1):
     themselves; that favours the plain start, whose equal powers fit the
     mixture's total power well but leave the sources undistinguished, while
     one iteration is enough to show the learned start ahead.
+
+    With mask_sharpen set, the learned start also takes its spatial
+    covariances from the network's masks (fca_set_mask_covariances with
+    that sharpening and mask_load); the plain start keeps the default R.
 
     Expects ctx fresh, at its plain starts. The learned run is not thrown
     away: a mixture that keeps its learned start stays at
@@ -79,6 +85,8 @@ def choose_starts(net, ctx, ys, choice_iter: int = 1):
     ll, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False, allow_flags=True)
     ll_plain = ll[:, 0].cpu().numpy()
     fca.fca_set_learned_starts(ctx, net)
+    if mask_sharpen is not None:
+        fca.fca_set_mask_covariances(ctx, sharpen=mask_sharpen, load=mask_load)
     ll, _, _ = fca.fca_em_step(ctx, choice_iter + 1, want_R=False, want_v=False, allow_flags=True)
     ll_learned = ll[:, choice_iter].cpu().numpy()
     chosen = ll_learned > ll_plain
