@@ -345,11 +345,12 @@ hipError_t launch_default_R(int M, int F, double2* R, hipStream_t s) {
 // powers (1/2 where both vanish), sharpened to r^p / (r^p + (1 - r)^p), the
 // masks are w_1 = r and w_2 = 1 - r, A_j = sum_n w_j y y^H, and
 // R_j = M A_j / tr(A_j) + load I (trace M before the loading; (1 + load) I
-// where tr(A_j) = 0). One workgroup per (mixture, frequency): blockIdx.x = f,
-// blockIdx.y = entry of `mix`. The upper triangles of A_j are FP64 register
-// sums (both sources in one pass over the frames for M <= 4, one source per
-// pass above), reduced in a fixed order (wave butterflies, then the four
-// waves in order). An integer p is applied by repeated multiplication.
+// where tr(A_j) = 0). One wave per (mixture, frequency): blockIdx.x = f,
+// blockIdx.y = entry of `mix` (a wave-sized workgroup keeps the fixed cost
+// of the reduction to one wave per problem). The upper triangles of A_j are
+// FP64 register sums (both sources in one pass over the frames for M <= 4,
+// one source per pass above), reduced by a butterfly in a fixed order. An
+// integer p is applied by repeated multiplication.
 __device__ __forceinline__ double mask_power(double r, double p, int ip) {
     if (ip > 0) {
         double x = r;
@@ -359,16 +360,18 @@ __device__ __forceinline__ double mask_power(double r, double p, int ip) {
     return pow(r, p);
 }
 
+constexpr int kMaskThreads = 64;
+
 template <int M, typename T>
-__global__ __launch_bounds__(256) void mask_cov_kernel(const MaskCovMix* __restrict__ mix, int F,
+__global__ __launch_bounds__(kMaskThreads) void mask_cov_kernel(const MaskCovMix* __restrict__ mix, int F,
                                                        const typename Vec2<T>::type* __restrict__ y,
                                                        const T* __restrict__ v, double2* __restrict__ R, double p,
                                                        double load) {
     constexpr int NU = M * (M + 1) / 2;  // upper-triangle entries
     constexpr int NS = M <= 4 ? 2 : 1;   // sources per pass
-    __shared__ double red[4][NS][2 * NU];
+    __shared__ double red[NS][2 * NU];
     const MaskCovMix mx = mix[blockIdx.y];
-    const int f = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int f = blockIdx.x, tid = threadIdx.x;
     const int ip = (p == floor(p) && p <= 64.0) ? (int)p : 0;  // integer exponent, or 0
     const auto* yf = y + mx.y_base + (int64_t)f * M * mx.npad;
     const T* v1 = v + mx.v_base + (int64_t)f * mx.npad;
@@ -379,7 +382,7 @@ __global__ __launch_bounds__(256) void mask_cov_kernel(const MaskCovMix* __restr
         for (int q = 0; q < NS; ++q)
 #pragma unroll
             for (int u = 0; u < NU; ++u) are[q][u] = aim[q][u] = 0.0;
-        for (int n = tid; n < mx.N; n += 256) {
+        for (int n = tid; n < mx.N; n += kMaskThreads) {
             const double a = (double)v1[n], b = (double)v2[n];
             double r = (a + b > 0.0) ? a / (a + b) : 0.5;
             if (p != 1.0) {
@@ -418,9 +421,9 @@ __global__ __launch_bounds__(256) void mask_cov_kernel(const MaskCovMix* __restr
                     x += __shfl_xor(x, off, 64);
                     z += __shfl_xor(z, off, 64);
                 }
-                if (lane == 0) {
-                    red[w][q][u] = x;
-                    red[w][q][NU + u] = z;
+                if (tid == 0) {
+                    red[q][u] = x;
+                    red[q][NU + u] = z;
                 }
             }
         __syncthreads();
@@ -430,12 +433,9 @@ __global__ __launch_bounds__(256) void mask_cov_kernel(const MaskCovMix* __restr
             const int a = i < k ? i : k, c = i < k ? k : i;  // upper entry (a, c)
             const int u = a * M - a * (a - 1) / 2 + (c - a);
             double tr = 0.0;
-            for (int d = 0; d < M; ++d) {
-                const int ud = d * M - d * (d - 1) / 2;
-                tr += ((red[0][q][ud] + red[1][q][ud]) + (red[2][q][ud] + red[3][q][ud]));
-            }
-            const double xr = (red[0][q][u] + red[1][q][u]) + (red[2][q][u] + red[3][q][u]);
-            double xi = (red[0][q][NU + u] + red[1][q][NU + u]) + (red[2][q][NU + u] + red[3][q][NU + u]);
+            for (int d = 0; d < M; ++d) tr += red[q][d * M - d * (d - 1) / 2];
+            const double xr = red[q][u];
+            double xi = red[q][NU + u];
             if (i > k) xi = -xi;  // lower entry: conjugate
             double2 out;
             if (tr > 0.0) {
@@ -463,13 +463,13 @@ static hipError_t launch_mask_cov_t(int M, const MaskCovMix* mix, int count, int
     const T2* yy = static_cast<const T2*>(y);
     const T* vv = static_cast<const T*>(v);
     switch (M) {
-        case 2: mask_cov_kernel<2, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
-        case 3: mask_cov_kernel<3, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
-        case 4: mask_cov_kernel<4, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
-        case 5: mask_cov_kernel<5, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
-        case 6: mask_cov_kernel<6, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
-        case 7: mask_cov_kernel<7, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
-        case 8: mask_cov_kernel<8, T><<<grid, 256, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 2: mask_cov_kernel<2, T><<<grid, kMaskThreads, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 3: mask_cov_kernel<3, T><<<grid, kMaskThreads, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 4: mask_cov_kernel<4, T><<<grid, kMaskThreads, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 5: mask_cov_kernel<5, T><<<grid, kMaskThreads, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 6: mask_cov_kernel<6, T><<<grid, kMaskThreads, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 7: mask_cov_kernel<7, T><<<grid, kMaskThreads, 0, s>>>(mix, F, yy, vv, R, p, load); break;
+        case 8: mask_cov_kernel<8, T><<<grid, kMaskThreads, 0, s>>>(mix, F, yy, vv, R, p, load); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

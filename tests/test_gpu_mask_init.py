@@ -1,5 +1,5 @@
 """GPU parity of fca_set_mask_covariances (mask-weighted initial covariances, one
-workgroup per mixture and frequency) against the oracle's plain definition
+wave per mixture and frequency) against the oracle's plain definition
 (oracle/mask_init.py), through the C ABI. The start is read back as the R of
 theta^(0) recovered from its generalized eigendecomposition, so the
 tolerance (relative 1e-9) covers that round trip in FP64."""
@@ -55,7 +55,7 @@ def _default_R(M, F):
     ("fp32", [(4, 300), (4, 77), (4, 1), (2, 40), (2, 513), (8, 90)], 2.5),
     ("fp64", [(3, 64), (3, 65), (5, 200), (6, 31), (7, 10)], 1.0)])
 def test_mask_start_matches_oracle(fca, prec, shapes, p):
-    """Mixtures of M = 2..8 with uneven N (ragged against the 256-thread
+    """Mixtures of M = 2..8 with uneven N (ragged against the 64-frame
     workgroup, single-frame mixtures), runs of equal M (one decomposition
     launch each) and a silent frequency; integer, fractional and no
     sharpening; the masks come from seeded powers given as v0."""
