@@ -296,7 +296,8 @@ fca_status fca_set_learned_starts(fca_ctx *c, fca_mlp *m, int32_t count, const i
 /* Initial spatial covariances from time-frequency masks (the experiments of
  * Section 4 start from covariances estimated with masks; the paper gives no
  * formula, this is the plain mask-weighted estimate). For each listed
- * mixture (mixtures = NULL: mixtures 0..count-1) the masks come from its
+ * mixture (mixtures: host array of count indices, or NULL for mixtures
+ * 0..count-1) the masks come from its
  * stored powers v_j^(0) (e.g. a learned start): r = v1 / (v1 + v2) (1/2
  * where both are 0), sharpened to r^p / (r^p + (1 - r)^p) with p = sharpen,
  * w_1 = r, w_2 = 1 - r. Then A_j(f) = sum_n w_j y y^H (FP64 sums) and
