@@ -110,10 +110,11 @@ def test_learned_start_feeds_the_em_with_fallback(fca):
     assert (chosen is None) == (ll_learned <= ll_plain)
 
 
-@pytest.mark.parametrize("choice_iter", [0, 1])
-def test_batched_start_choice_and_per_mixture_stop(fca, choice_iter):
+@pytest.mark.parametrize("choice_iter,mask", [(0, None), (1, None), (1, 3.0)])
+def test_batched_start_choice_and_per_mixture_stop(fca, choice_iter, mask):
     """choose_starts keeps the better start per mixture in one batch, compared
-    by LL(theta^choice_iter) of each start (checked against lone runs), and
+    by LL(theta^choice_iter) of each start (checked against lone runs; with
+    `mask`, the learned start also takes the mask-based R), and
     leaves a kept learned start choice_iter + 1 iterations in; run_batch
     stops each mixture on its own rule, and each history continues a lone
     run of that mixture from the chosen start."""
@@ -126,23 +127,30 @@ def test_batched_start_choice_and_per_mixture_stop(fca, choice_iter):
         ys.append(torch.from_numpy(synth.array_mixture(4, 33, n, seed=200 + k, v=v).y).cuda())
     ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
     try:
-        chosen, llp, lll, adv = learned_init.choose_starts(net, ctx, ys, choice_iter=choice_iter)
+        chosen, llp, lll, adv = learned_init.choose_starts(net, ctx, ys, choice_iter=choice_iter,
+                                                           mask_sharpen=mask)
         np.testing.assert_array_equal(chosen, lll > llp)
         np.testing.assert_array_equal(adv, np.where(chosen, choice_iter + 1, 0))
         iters, hist = schedule.run_batch(ctx, 20, 2, lambda b, ll: len(ll) >= 2 * (b + 1))
         assert list(iters) == [2, 4, 6]
     finally:
         fca.fca_destroy(ctx)
+    def lone_ctx(y, v0):
+        c = fca.fca_init(y, v0=v0, prec=fca.FCA_FP32_BULK)
+        if v0 is not None and mask is not None:
+            fca.fca_set_mask_covariances(c, sharpen=mask)
+        return c
+
     for k, y in enumerate(ys):
         v0l = fca.fca_mlp_init_powers(net, y)
         for want, v0 in ((llp[k], None), (lll[k], v0l)):
-            lone = fca.fca_init(y, v0=v0, prec=fca.FCA_FP32_BULK)
+            lone = lone_ctx(y, v0)
             try:
                 ll, _, _ = fca.fca_em_step(lone, choice_iter + 1, want_R=False, want_v=False, allow_flags=True)
             finally:
                 fca.fca_destroy(lone)
             np.testing.assert_allclose(want, ll.cpu().numpy()[0, choice_iter], rtol=1e-12)
-        lone = fca.fca_init(y, v0=v0l if chosen[k] else None, prec=fca.FCA_FP32_BULK)
+        lone = lone_ctx(y, v0l if chosen[k] else None)
         try:
             ll, _, _ = fca.fca_em_step(lone, int(adv[k] + iters[k]), want_R=False, want_v=False, allow_flags=True)
         finally:
