@@ -401,6 +401,14 @@ def run_time_to_target(args):
 
     mask = args.mask_sharpen if args.mask_sharpen > 0 else None
 
+    def choice_iter(m):
+        """Iterations before the starts are compared: 0 with the mask-based R
+        (its LL(theta^0) already ranks the starts), 1 without (at theta^0 the
+        plain start's equal powers look better than they are)."""
+        if args.choice_iter >= 0:
+            return args.choice_iter
+        return 0 if m is not None else 1
+
     def batched(net, mask=None):
         """Wall time of one batched FP32 run from context-ready to every
         mixture stopped, with the learned start of `net` (or the plain start
@@ -413,7 +421,8 @@ def run_time_to_target(args):
             t1 = time.perf_counter()
             chosen, adv = None, np.zeros(len(ys), dtype=int)
             if net is not None:
-                chosen, _, _, adv = learned_init.choose_starts(net, ctx, ys, mask_sharpen=mask)
+                chosen, _, _, adv = learned_init.choose_starts(net, ctx, ys, choice_iter=choice_iter(mask),
+                                                               mask_sharpen=mask)
             t2 = time.perf_counter()
             iters, hist = schedule.run_batch(ctx, 2 * L, (16, 8, 4), stop)
             torch.cuda.synchronize()
@@ -477,9 +486,10 @@ def run_time_to_target(args):
         "reached": {"plain_fp32": sum(i is not None for i in plain32_its),
                     "batched_plain": sum(i is not None for i in bp_hits)},
         "learned": [learned[H] for H in widths],
-        "start_choice": "per mixture, the start with the higher LL after 1 EM iteration (plain start as "
-                        "fallback); a kept learned start continues from its 2nd iterate; the learned start "
-                        "takes R from its masks (fca_set_mask_covariances) unless --mask-sharpen 0",
+        "start_choice": f"per mixture, the start with the higher LL after {choice_iter(mask)} EM iteration(s) "
+                        f"({choice_iter(None)} without the mask-based R; plain start as fallback); a kept "
+                        "learned start continues from the iterate after the comparison; the learned start takes "
+                        "R from its masks (fca_set_mask_covariances) unless --mask-sharpen 0",
         "stop_rule": "reached target, or LL rise below 1e-6 of the total (converged elsewhere), checked after "
                      "16, 24 and then every 4 iterations (each call reloads the frames: ~1 ms at 256 "
                      "mixtures)"}
@@ -506,6 +516,9 @@ def main():
     ap.add_argument("--hidden", default="32,64,256",
                     help="time-to-target: hidden widths of the learned-start networks (the first one is the "
                          "headline)")
+    ap.add_argument("--choice-iter", type=int, default=-1,
+                    help="time-to-target: EM iterations after which the plain and learned starts are compared "
+                         "(-1: 0 with the mask-based R, 1 without)")
     ap.add_argument("--mask-sharpen", type=float, default=3.0,
                     help="time-to-target: sharpening exponent of the masks that give the learned start its R "
                          "(0: plain R)")

@@ -71,6 +71,8 @@ def choose_starts(net, ctx, ys, choice_iter: int = 1, mask_sharpen=None, mask_lo
     With mask_sharpen set, the learned start also takes its spatial
     covariances from the network's masks (fca_set_mask_covariances with
     that sharpening and mask_load); the plain start keeps the default R.
+    That start is far ahead already at theta^0, so choice_iter = 0 suffices
+    for it.
 
     Expects ctx fresh, at its plain starts. The learned run is not thrown
     away: a mixture that keeps its learned start stays at
