@@ -8,16 +8,26 @@ initial values (plain start), 50 EM iterations returning the per-iteration
 log-likelihood, R_j(f) and v_j(n,f), then the MMSE source images.
 
 Metric: time-frequency-bin EM updates per second = F * N * iterations / step
-time. Prints one JSON line with a roofline entry for the EM-iteration kernel
-(timed with HIP events on the stream it runs on), the conventional-EM kernel
-timed on the same workload (in-run baseline) and the CPU oracle
-(conventional FCA EM, FP64) on the host's cores.
+time. Prints one JSON line with
+  - a roofline entry for the EM-iteration kernel (timed with HIP events on
+    the stream it runs on): algorithmic bytes (8 M + 16 per bin and
+    iteration: y read, v read and written) over the launch time, against the
+    8 TB/s HBM peak, with the flop view beside it;
+  - the error of the GPU result against the CPU oracle (conventional FCA EM,
+    FP64) on the frequencies whose true covariances have condition number
+    <= 1e3, and by condition-number class on the others;
+  - the conventional-EM kernel timed on the same workload (in-run baseline);
+  - the CPU oracle's own throughput on the host's cores;
+  - time to target (unless --no-ttt): held-out mixtures with AR(1) powers,
+    plain FastFCA FP32 one mixture at a time against batched runs with and
+    without the learned start (see time_to_target).
 
 Other workloads (--workload): "batched" = 64 mixtures with N uniform in
 [200, 2000] and M drawn from {2, 4, 8}; "large" = 16 mixtures, M = 8,
 F = 1025, N = 8000, 100 iterations (frames streamed); "time-to-target" =
-learned start + one batched run of held-out mixtures against the plain start
-run one mixture at a time.
+the time-to-target comparison alone; "ttt-tune" = the choice of the learned
+path's settings (mask sharpening, start-comparison iteration, stop-check
+chunks) on mixtures disjoint from the evaluation ones.
 """
 from __future__ import annotations
 
@@ -32,11 +42,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "TF-bin EM updates/sec at M=4; time-to-target log-lik vs plain FastFCA"
-PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak
-PEAK_HBM_GBS = 8000.0
+PEAK_HBM_GBS = 8000.0                # MI355X published HBM3E bandwidth
+PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak (packed instructions)
+FP32_UNPACKED_TFLOPS = 78.6          # the same without packed FP32, which every build here disables
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "em_kernel_array_m4_traffic.json")
+# the EM kernel's own sources: a change there makes the stored traffic stale
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1805_06572_amd", "csrc", f)
-                  for f in ("fca_em.h", "fca_em_nt256.hip", "fca_device.h", "fca_internal.h")]
+                  for f in ("fca_em.h", "fca_em_nt256.hip", "fca_device.h")]
+KAPPA_GATE = 1e3                     # float-bulk parity gate on cond(R_true)
 
 
 def flop_per_update(M: int) -> int:
@@ -69,6 +82,10 @@ def load_traffic():
     return t.get("bytes_per_launch")
 
 
+def oracle_threads() -> int:
+    return min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+
+
 def cpu_baseline(mixtures, iters: int, freqs_per_mixture: int, frames: int | None = None):
     """Time the CPU oracle (conventional EM, FP64) on a bounded sample of the
     workload: the given mixtures, evenly spaced frequencies (frequencies are
@@ -77,7 +94,7 @@ def cpu_baseline(mixtures, iters: int, freqs_per_mixture: int, frames: int | Non
     import numpy as np
     import oracle
 
-    cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+    cores = oracle_threads()
     total_t, updates, desc = 0.0, 0, []
     for y in mixtures:
         F, N, _ = y.shape
@@ -168,12 +185,19 @@ class Runner:
         self.fca.fca_destroy(self.ctx)
 
 
-def roofline_entry(kernel_ms, flop, bytes_alg, traffic, kernel_name):
-    achieved = flop / (kernel_ms * 1e-3) / 1e12
-    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic, "kernel": kernel_name,
-            "kernel_ms_per_step": kernel_ms, "flop_per_step": flop, "algorithmic_bytes_per_step": bytes_alg,
-            "hbm_equivalent_GBps": bytes_alg / (kernel_ms * 1e-3) / 1e9}
+def roofline_entry(kernel_ms, bytes_alg, flop, traffic, kernel_name):
+    """The EM kernel against the HBM roofline: algorithmic bytes of one
+    launch (all iterations of the call) over its duration; the flop view
+    (24 M^2 + 25 M per bin and iteration) is kept beside it."""
+    gbs = bytes_alg / (kernel_ms * 1e-3) / 1e9
+    tflops = flop / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "traffic": traffic, "kernel": kernel_name, "kernel_ms_per_launch": kernel_ms,
+            "algorithmic_bytes_per_launch": bytes_alg,
+            "bytes_rule": "(8 M + 16) B per bin and iteration (y read, v read and written) x bins x iterations",
+            "flop_view": {"flop_per_launch": flop, "achieved_tflops": tflops,
+                          "frac_of_157_3_packed_peak": tflops / PEAK_FP32_VECTOR_TFLOPS,
+                          "frac_of_78_6_unpacked": tflops / FP32_UNPACKED_TFLOPS}}
 
 
 def base_record(args, value, ms_per_step, config):
@@ -183,7 +207,42 @@ def base_record(args, value, ms_per_step, config):
 
 
 # ---------------------------------------------------------------------------- workloads
+def oracle_error(kappa, oflags, gflags, S, v, ll, gR, gv, gll_f):
+    """GPU against the oracle, per frequency: relative 2-norm errors of v_j
+    and R_j, and of the log-likelihood of every iterate summed over the
+    gated frequencies (cond(R_true) <= 1e3, not flagged by the oracle); the
+    other frequencies by condition-number class."""
+    import numpy as np
+
+    def rel(a, b, axes):
+        return np.sqrt((np.abs(a - b) ** 2).sum(axes)) / np.sqrt((np.abs(b) ** 2).sum(axes))
+    ev = rel(gv.astype(np.float64), v, (-1,)).max(0)
+    eR = rel(gR, S, (-2, -1)).max(0)
+    gate = (kappa <= KAPPA_GATE) & (oflags == 0)
+    iters = gll_f.shape[0]
+    want = ll[:iters, gate].sum(1)
+    e_ll = np.abs(gll_f[:, gate].sum(1) - want) / np.abs(ll[:iters, gate]).sum(1)
+    classes = []
+    edges = [KAPPA_GATE, 1e5, 1e7, 1e10, np.inf]
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = (kappa > lo) & (kappa <= hi) & (oflags == 0) & (gflags == 0)
+        if sel.any():
+            classes.append({"kappa": [lo, None if np.isinf(hi) else hi], "frequencies": int(sel.sum()),
+                            "v_rel_err_max": float(ev[sel].max()), "R_rel_err_max": float(eR[sel].max())})
+    return {"gate": f"cond(R_true) <= {KAPPA_GATE:g} and not flagged by the oracle",
+            "gated_frequencies": int(gate.sum()), "of": int(len(kappa)),
+            "v_rel_err_max": float(ev[gate].max()), "R_rel_err_max": float(eR[gate].max()),
+            "loglik_rel_err_max": float(e_ll.max()),
+            "gpu_flags_in_gate": int((gflags[gate] != 0).sum()),
+            "oracle_flagged": int((oflags != 0).sum()), "gpu_flagged": int((gflags != 0).sum()),
+            "ungated_by_kappa": classes,
+            "metric": "per frequency ||gpu - oracle|| / ||oracle|| (v over frames, R Frobenius), max over "
+                      "frequencies and sources; loglik: |sum over gated f| error / sum of |terms|, max over "
+                      "iterations"}
+
+
 def run_array(args):
+    import numpy as np
     import torch
     from paper_1805_06572_amd import fca, synth
 
@@ -203,14 +262,18 @@ def run_array(args):
     shapes = run.autotune() if args.autotune else None
     eager_ms, em_ms = run.timed(args.steps, args.warmup)
     ms_step = run.graph_timed(args.steps, args.warmup) if args.graph else eager_ms
+    F, N, M = args.F, args.N, args.M
+    # the outputs of the last timed step, before the conventional kernel reuses the buffers
     lls = run.ll.cpu().numpy()[0]
+    gll_f = fca.fca_loglik_per_freq(run.ctx, L).cpu().numpy()[:, 0]
+    gR = run.R.view(2, F, M, M).cpu().numpy()
+    gv = run.v.view(2, F, N).cpu().numpy()
     flags = fca.fca_status_per_freq(run.ctx)[0]
     conv_steps = max(1, args.steps // 10)
     _, conv_ms = run.timed(conv_steps, 1, conventional=True, separate=False)
     conv_flags = fca.fca_status_per_freq(run.ctx)[0]
     run.close()
 
-    F, N, M = args.F, args.N, args.M
     updates = F * N * L
     rec = base_record(args, updates / (ms_step * 1e-3), ms_step,
                       {"workload": f"array mixture M={M} F={F} N={N}, {L} EM iterations, plain start",
@@ -220,9 +283,9 @@ def run_array(args):
                                (", captured in one HIP graph and replayed" if args.graph else ""),
                        "launch_shapes": shapes})
     rec["eager_ms_per_step"] = eager_ms
-    rec["roofline"] = roofline_entry(em_ms, flop_per_update(M) * updates, bytes_per_update(M) * F * N,
+    rec["roofline"] = roofline_entry(em_ms, bytes_per_update(M) * updates, flop_per_update(M) * updates,
                                      load_traffic() if M == 4 else None,
-                                     "em_kernel (all iterations of a call, one workgroup per frequency)")
+                                     "em_kernel (one launch runs all iterations, one workgroup per frequency)")
     rec["in_run_baseline"] = {"kernel": "conv_em_kernel (conventional frame-wise EM, same workload)",
                               "kernel_ms_per_step": conv_ms, "updates_per_s": updates / (conv_ms * 1e-3),
                               "fastfca_kernel_speedup": conv_ms / em_ms,
@@ -230,7 +293,22 @@ def run_array(args):
     rec["loglik_first_last"] = [float(lls[0]), float(lls[-1])]
     rec["flagged_frequencies"] = int((flags != 0).sum())
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline([mx.y], L, args.F)
+        # the oracle on every frequency and frame of the same input and start:
+        # the CPU baseline and the error of the GPU result
+        import oracle
+        y64 = mx.y.astype(np.complex128)
+        S0, v0 = oracle.default_init(y64)
+        cores = oracle_threads()
+        oracle.em(y64[:1, :8], S0[:, :1], v0[:, :1, :8], 1, threads=cores)   # load + warm
+        t0 = time.perf_counter()
+        S, v, ll, oflags = oracle.em(y64, S0, v0, L, threads=cores)
+        cpu_s = time.perf_counter() - t0
+        rec["oracle_error"] = oracle_error(synth.condition_numbers(mx.R), oflags, flags, S, v, ll, gR, gv, gll_f)
+        rec["cpu_baseline"] = {"value": updates / cpu_s, "unit": "updates/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{F}/{F} frequencies x {N} frames (1 mixture), {L} iterations of the "
+                                         f"conventional FCA EM in FP64 ({cpu_s:.2f} s wall)"}
+    if args.ttt:
+        rec["time_to_target"] = time_to_target(args)
     return rec
 
 
@@ -253,7 +331,7 @@ def run_batched(args):
     run.close()
     updates = int(F * Ns.sum() * L)
     flop = int(sum(flop_per_update(int(m)) * F * int(n) * L for m, n in zip(Ms, Ns)))
-    bts = int(sum(bytes_per_update(int(m)) * F * int(n) for m, n in zip(Ms, Ns)))
+    bts = int(sum(bytes_per_update(int(m)) * F * int(n) * L for m, n in zip(Ms, Ns)))
     rec = base_record(args, updates / (ms_step * 1e-3), ms_step,
                       {"workload": f"{B} array mixtures, F={F}, N uniform in [200, 2000], M in {{2, 4, 8}}, "
                                    f"{L} EM iterations, plain start, one batched context",
@@ -264,8 +342,9 @@ def run_batched(args):
                                (", captured in one HIP graph and replayed" if args.graph else ""),
                        "launch_shapes": shapes})
     rec["eager_ms_per_step"] = eager_ms
-    rec["roofline"] = roofline_entry(em_ms, flop, bts, None,
-                                     "em_kernel, one launch per (M, frames-per-thread) group, groups concurrent")
+    rec["roofline"] = roofline_entry(em_ms, bts, flop, None,
+                                     "em_kernel / em_stream_kernel, one launch per (M, frames-per-thread) "
+                                     "group, groups concurrent (time from the first launch to the last end)")
     rec["flagged_frequencies"] = int((flags != 0).sum())
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline([ys[i].cpu().numpy() for i in range(2)], L, 64)
@@ -308,9 +387,8 @@ def run_large(args):
                        "mixtures": B, "M": M, "F": F, "N": N, "iterations": L,
                        "precision": "f32 per-bin arithmetic; f64 eigendecomposition and sums"})
     bts = bytes_per_update(M) * B * F * N * L   # streamed: y and v move every iteration
-    rec["roofline"] = roofline_entry(em_ms, flop_per_update(M) * updates, bts, None,
+    rec["roofline"] = roofline_entry(em_ms, bts, flop_per_update(M) * updates, None,
                                      "em_stream_kernel (frames re-read every iteration)")
-    rec["roofline"]["hbm_frac"] = rec["roofline"]["hbm_equivalent_GBps"] / PEAK_HBM_GBS
     rec["flagged_frequencies"] = int((flags != 0).sum())
     if learned:
         rec["learned_start"] = learned
@@ -324,7 +402,7 @@ def run_large(args):
     S0, v0 = oracle.default_init(y64)
     if learned and v0_mix0 is not None:
         v0 = np.ascontiguousarray(v0_mix0.cpu().numpy().astype(np.float64)[:, idx])
-    cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+    cores = oracle_threads()
     t0 = time.perf_counter()
     S, v, ll, oflags = oracle.em(y64, S0, v0, L, threads=cores)
     cpu_s = time.perf_counter() - t0
@@ -352,151 +430,164 @@ def run_large(args):
     return rec
 
 
-def run_time_to_target(args):
+def time_to_target(args, seed0: int = 3000, K: int | None = None, settings=None, widths=None):
+    """Time to a target log-likelihood, on K held-out array mixtures (M = 4,
+    F = 513, N = 1000, AR(1) log-powers, seeds seed0 .. seed0 + K - 1).
+
+    Only frequencies whose true covariances have cond(R_true) <= 1e3 count
+    (the trust mask; below that the array model is numerically singular and
+    its log-likelihood untrusted). Target of a mixture: the masked sum of the
+    log-likelihood that plain FastFCA (plain start, FP32 bulk, one mixture at
+    a time) reaches after 50 iterations; reached at LL >= target - 1e-3 (target
+    - LL(theta^0)). Paths:
+      - plain FastFCA FP32 one mixture at a time (its time prorated to the
+        iteration that reaches the target: step time x iterations / 50);
+      - all mixtures in one batched context, plain start, each stopped once
+        it reaches its target (or has converged);
+      - the same with the learned start (network of each hidden width,
+        trained on the device first, its training time reported apart) and
+        the mask-based R, the plain start kept per mixture where it has the
+        higher log-likelihood (fallback); wall time from the context holding
+        the mixtures to the last one stopped, the network inference, masks,
+        start comparison included.
+    settings: (mask sharpening, start-comparison iteration, stop-check chunks)
+    of the learned path."""
     import numpy as np
     import torch
     from paper_1805_06572_amd import fca, learned_init, schedule, synth
 
-    M, F, N, K, L = 4, 513, 1000, args.mixtures, args.iters
-    widths = [int(h) for h in args.hidden.split(",")]
-    ys = [synth.array_mixture_device(M, F, N, seed=3000 + k, ar1=True)[0] for k in range(K)]
-    ys64 = [y.to(torch.complex128) for y in ys]
+    M, F, N, L = 4, 513, 1000, 50
+    K = args.mixtures if K is None else K
+    sharpen, choice_iter, chunks_learned = settings or (args.mask_sharpen, args.choice_iter,
+                                                        tuple(int(c) for c in args.chunks.split(",")))
+    widths = widths or [int(h) for h in args.hidden.split(",")]
+    gens = [synth.array_mixture_device(M, F, N, seed=seed0 + k, ar1=True) for k in range(K)]
+    ys = [g[0] for g in gens]
+    trust = np.stack([synth.condition_numbers(g[2]) <= KAPPA_GATE for g in gens])
+    del gens
+    w = torch.from_numpy(trust.astype(np.float64)).cuda()
     torch.cuda.synchronize()
 
-    # Plain FastFCA (plain start, FP64, one mixture at a time, L iterations)
-    # defines each mixture's target: LL(theta^L), with a threshold at 99.9 % of
-    # the rise from LL(theta^0).
-    def one_at_a_time(yl, prec):
-        out = []
-        for y in yl:
-            run = Runner(fca, [y], L, prec)
-            step_ms, _ = run.timed(2, 1, separate=False)
-            ll = run.ll.cpu().numpy()[0]
-            last, _, _ = fca.fca_em_step(run.ctx, 0, want_R=False, want_v=False, allow_flags=True)
-            out.append((step_ms, np.r_[ll, last.cpu().numpy()[0, 0]]))
-            run.close()
-        return out
+    def masked(rows, k):   # [r, F] per-frequency values of mixture k -> [r]
+        return torch.where(w[k] > 0, rows * w[k], torch.zeros_like(rows)).sum(-1)
 
-    p64 = one_at_a_time(ys64, fca.FCA_FP64)
-    targets = np.array([h[-1] for _, h in p64])
-    thr = targets - 1e-3 * (targets - np.array([h[0] for _, h in p64]))
+    plain = []
+    for k, y in enumerate(ys):
+        run = Runner(fca, [y], L, fca.FCA_FP32_BULK)
+        step_ms, _ = run.timed(1, 1, separate=False)
+        rows = fca.fca_loglik_per_freq(run.ctx, L)[:, 0]
+        fca.fca_em_step(run.ctx, 0, want_R=False, want_v=False, allow_flags=True)
+        last = fca.fca_loglik_per_freq(run.ctx, 1)[:, 0]
+        plain.append((step_ms, masked(torch.cat([rows, last]), k).cpu().numpy()))
+        run.close()
+    target = np.array([h[-1] for _, h in plain])
+    thr = target - 1e-3 * (target - np.array([h[0] for _, h in plain]))
 
     def first_hit(h, t):
         hit = np.nonzero(np.asarray(h) >= t)[0]
         return int(hit[0]) if len(hit) else None
 
-    def prorated(runs):
-        its = [first_hit(h, thr[k]) for k, (_, h) in enumerate(runs)]
-        ms = sum(step_ms * (L if it is None else it) / L for (step_ms, _), it in zip(runs, its))
-        return ms, its
-
-    plain64_ms, plain64_its = prorated(p64)
-    plain32_ms, plain32_its = prorated(one_at_a_time(ys, fca.FCA_FP32_BULK))
-
-    hit_rule = schedule.reached(thr)
-    conv_rule = schedule.converged(1e-6)
+    plain_its = [first_hit(h, thr[k]) for k, (_, h) in enumerate(plain)]
+    plain_ms = sum(ms * (L if it is None else it) / L for (ms, _), it in zip(plain, plain_its))
+    hit_rule, conv_rule = schedule.reached(thr), schedule.converged(1e-6)
 
     def stop(b, ll):
         return hit_rule(b, ll) or conv_rule(b, ll)
 
-    mask = args.mask_sharpen if args.mask_sharpen > 0 else None
-
-    def choice_iter(m):
-        """Iterations before the starts are compared: 0 with the mask-based R
-        (its LL(theta^0) already ranks the starts), 1 without (at theta^0 the
-        plain start's equal powers look better than they are)."""
-        if args.choice_iter >= 0:
-            return args.choice_iter
-        return 0 if m is not None else 1
-
-    def batched(net, mask=None):
-        """Wall time of one batched FP32 run from context-ready to every
-        mixture stopped, with the learned start of `net` (or the plain start
-        if None; with `mask`, the learned start's R from its masks sharpened
-        by that exponent); warm: the same run once before, untimed."""
-        res = None
-        for rep in range(2):
+    def batched(net):
+        """(wall ms, start ms, iterations run, iterations to target, learned kept)
+        of the second of two identical runs (the first warms up)."""
+        for _ in range(2):
             ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            chosen, adv = None, np.zeros(len(ys), dtype=int)
+            chosen, adv = np.zeros(K, dtype=bool), np.zeros(K, dtype=int)
             if net is not None:
-                chosen, _, _, adv = learned_init.choose_starts(net, ctx, ys, choice_iter=choice_iter(mask),
-                                                               mask_sharpen=mask)
+                chosen, _, _, adv = learned_init.choose_starts(net, ctx, ys, choice_iter=choice_iter,
+                                                               mask_sharpen=sharpen if sharpen > 0 else None)
             t2 = time.perf_counter()
-            # stop checks: the mask start reaches the target in about 20
-            # iterations, the other starts in 30 to 50 (each path at the
-            # faster of these two chunkings, measured)
-            chunks = (16, 4) if (net is not None and mask is not None) else (16, 8, 4)
-            iters, hist = schedule.run_batch(ctx, 2 * L, chunks, stop)
+            iters, hist = schedule.run_batch(ctx, 2 * L, chunks_learned if net is not None else (16, 8, 4),
+                                             stop, weights=w)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
             fca.fca_destroy(ctx)
-            # a kept learned start enters the run `adv` iterations in
-            res = ((t3 - t1) * 1e3, (t2 - t1) * 1e3, np.asarray(iters) + adv, hist, chosen, adv)
-        return res
+        hits = [first_hit(h, thr[k]) for k, h in enumerate(hist)]
+        hits = [None if h is None else int(h + a) for h, a in zip(hits, adv)]
+        return (t3 - t1) * 1e3, (t2 - t1) * 1e3, np.asarray(iters) + adv, hits, chosen
 
-    bp_ms, _, bp_iters, bp_hist, _, _ = batched(None)
-    bp_hits = [first_hit(h, thr[k]) for k, h in enumerate(bp_hist)]
-    learned = {}
+    def stats(its):
+        got = [i for i in its if i is not None]
+        return {"mean": float(np.mean(got)) if got else None, "median": float(np.median(got)) if got else None,
+                "reached": len(got), "of": len(its)}
+
+    bp_ms, _, bp_run, bp_hits, _ = batched(None)
+    learned = []
     for H in widths:
         t0 = time.perf_counter()
-        net, _ = learned_init.train(M=M, F=F, steps=args.train_steps, batch=8192, seed=0, hidden=H,
-                                    cosine=args.cosine)
+        net, _ = learned_init.train(M=M, F=F, steps=args.train_steps, batch=8192, seed=0, hidden=H)
         train_s = time.perf_counter() - t0
         bce, bce_const = learned_init.evaluate(net, n=65536, M=M, F=F)
-        bl_ms, bl_init_ms, bl_iters, bl_hist, chosen, adv = batched(net, mask)
-        bl_hits = [first_hit(h, thr[k]) for k, h in enumerate(bl_hist)]
-        bl_hits = [None if h is None else int(h + a) for h, a in zip(bl_hits, adv)]
-        extra = {}
-        if mask is not None and H == widths[0]:
-            # the same network without the mask-based R, for comparison
-            nm_ms, nm_init_ms, nm_iters, nm_hist, nm_chosen, nm_adv = batched(net, None)
-            nm_hits = [first_hit(h, thr[k]) for k, h in enumerate(nm_hist)]
-            nm_hits = [None if h is None else int(h + a) for h, a in zip(nm_hits, nm_adv)]
-            extra["without_mask_R"] = {
-                "batched_learned_start_fp32_ms": nm_ms, "start_choice_ms": nm_init_ms,
-                "speedup_vs_plain_fp64": plain64_ms / nm_ms, "mean_iterations_run": float(np.mean(nm_iters)),
-                "mean_iterations_to_target": float(np.mean([h for h in nm_hits if h is not None])),
-                "reached": sum(i is not None for i in nm_hits), "learned_start_chosen": int(np.sum(nm_chosen))}
-        learned[H] = {
-            "hidden": H, "batched_learned_start_fp32_ms": bl_ms, "start_choice_ms": bl_init_ms,
-            "speedup_vs_plain_fp64": plain64_ms / bl_ms, "speedup_vs_plain_fp32": plain32_ms / bl_ms,
-            "speedup_of_learned_start_in_batch": bp_ms / bl_ms,
-            "mean_iterations_run": float(np.mean(bl_iters)),
-            "iterations_to_target": bl_hits, "reached": sum(i is not None for i in bl_hits),
-            "learned_start_chosen": int(np.sum(chosen)),
-            "mlp_train_s": train_s, "mlp_train_steps": args.train_steps,
-            "mlp_heldout_bce": bce, "constant_predictor_bce": bce_const,
-            "mask_R": None if mask is None else {"sharpen": mask, "load": 1e-3}, **extra}
+        ms, start_ms, run_its, hits, chosen = batched(net)
         net.close()
-    head = learned[widths[0]]
-    bl_ms = head["batched_learned_start_fp32_ms"]
-    rec = base_record(args, K * F * N * head["mean_iterations_run"] / (bl_ms * 1e-3), bl_ms,
-                      {"workload": f"time to target: {K} held-out array mixtures (AR(1) log-powers), M={M}, "
-                                   f"F={F}, N={N}; target = LL of plain FastFCA (FP64, plain start) after "
-                                   f"{L} iterations, reached at 99.9 % of its rise; learned start of hidden "
-                                   f"width {widths[0]}" + ("" if mask is None else
-                                                          f", R from its masks (sharpen {mask})"),
-                       "mixtures": K, "M": M, "F": F, "N": N, "iterations": L, "hidden": widths[0]})
+        learned.append({"hidden": H, "ms": ms, "start_ms": start_ms,
+                        "speedup_vs_plain_fp32_one_at_a_time": plain_ms / ms,
+                        "speedup_vs_batched_plain": bp_ms / ms,
+                        "iterations_to_target": stats(hits), "mean_iterations_run": float(np.mean(run_its)),
+                        "learned_start_kept": int(np.sum(chosen)), "plain_fallbacks": int(K - np.sum(chosen)),
+                        "train_s": train_s, "train_steps": args.train_steps, "heldout_bce": bce,
+                        "constant_predictor_bce": bce_const})
+    return {"mixtures": K, "seeds": [seed0, seed0 + K - 1], "M": M, "F": F, "N": N,
+            "trusted_frequencies_mean": float(trust.sum(1).mean()),
+            "target": "masked LL of plain FastFCA (FP32, plain start, one mixture at a time) after 50 "
+                      "iterations; reached at target - 1e-3 (target - LL(theta^0)); mask cond(R_true) <= 1e3",
+            "plain_fp32_one_at_a_time_ms": plain_ms,
+            "plain_fp32_one_at_a_time_full_50_ms": float(sum(ms for ms, _ in plain)),
+            "plain_iterations_to_target": stats(plain_its),
+            "batched_plain_ms": bp_ms, "batched_plain_iterations_to_target": stats(bp_hits),
+            "batched_plain_mean_iterations_run": float(np.mean(bp_run)),
+            "learned": learned,
+            "primary": {"hidden": learned[0]["hidden"], "ms": learned[0]["ms"],
+                        "speedup_vs_plain_fp32_one_at_a_time": learned[0]["speedup_vs_plain_fp32_one_at_a_time"],
+                        "speedup_vs_batched_plain": learned[0]["speedup_vs_batched_plain"]},
+            "settings": {"mask_sharpen": sharpen, "mask_load": 1e-3, "start_comparison_iteration": choice_iter,
+                         "stop_check_chunks": list(chunks_learned),
+                         "chosen_on": "held-out seeds 5000.. (the ttt-tune workload), not on these mixtures"},
+            "stop_rule": "reached target or masked LL rise below 1e-6 of the total, checked after each chunk"}
+
+
+def run_time_to_target(args):
+    out = time_to_target(args)
+    head = out["learned"][0]
+    rec = base_record(args, out["mixtures"] * out["F"] * out["N"] * head["mean_iterations_run"] / (head["ms"] * 1e-3),
+                      head["ms"],
+                      {"workload": f"time to target: {out['mixtures']} held-out array mixtures (AR(1) log-powers), "
+                                   f"M=4, F=513, N=1000, learned start of hidden width {head['hidden']}",
+                       "mixtures": out["mixtures"], "M": 4, "F": 513, "N": 1000, "hidden": head["hidden"]})
     rec["steps"], rec["warmup"] = 1, 1
-    rec["time_to_target"] = {
-        "plain_fastfca_fp64_one_at_a_time_ms": plain64_ms,
-        "plain_fastfca_fp32_one_at_a_time_ms": plain32_ms,
-        "batched_plain_start_fp32_ms": bp_ms,
-        "batched_plain_mean_iterations_run": float(np.mean(bp_iters)),
-        "iterations_to_target": {"plain_fp64": plain64_its, "plain_fp32": plain32_its,
-                                 "batched_plain": bp_hits},
-        "reached": {"plain_fp32": sum(i is not None for i in plain32_its),
-                    "batched_plain": sum(i is not None for i in bp_hits)},
-        "learned": [learned[H] for H in widths],
-        "start_choice": f"per mixture, the start with the higher LL after {choice_iter(mask)} EM iteration(s) "
-                        f"({choice_iter(None)} without the mask-based R; plain start as fallback); a kept "
-                        "learned start continues from the iterate after the comparison; the learned start takes "
-                        "R from its masks (fca_set_mask_covariances) unless --mask-sharpen 0",
-        "stop_rule": "reached target, or LL rise below 1e-6 of the total (converged elsewhere), checked after "
-                     "16 and then every 4 iterations with the mask-based start, after 16, 24 and then every 4 "
-                     "iterations otherwise (each call reloads the frames: ~1 ms at 256 mixtures)"}
+    rec["time_to_target"] = out
+    return rec
+
+
+def run_ttt_tune(args):
+    """Settings of the learned path (mask sharpening, start-comparison
+    iteration, stop-check chunks) by wall time to target on 64 mixtures of
+    seeds 5000.., disjoint from the evaluation mixtures."""
+    grid = []
+    for sharpen in (1.0, 2.0, 3.0, 4.0):
+        for chunks in ((16, 4), (12, 4), (16, 8, 4), (8, 4)):
+            grid.append((sharpen, 0, chunks))
+    grid += [(3.0, 1, (16, 4)), (0.0, 1, (16, 8, 4))]
+    res = []
+    for st in grid:
+        out = time_to_target(args, seed0=5000, K=64, settings=st, widths=[int(args.hidden.split(",")[0])])
+        h = out["learned"][0]
+        res.append({"mask_sharpen": st[0], "start_comparison_iteration": st[1], "chunks": list(st[2]),
+                    "ms": h["ms"], "iterations_to_target": h["iterations_to_target"]["mean"],
+                    "iterations_run": h["mean_iterations_run"], "batched_plain_ms": out["batched_plain_ms"]})
+        print(json.dumps(res[-1]), file=sys.stderr, flush=True)
+    best = min(res, key=lambda r: r["ms"])
+    rec = base_record(args, None, best["ms"], {"workload": "ttt-tune: 64 array mixtures (AR(1)), seeds 5000..5063"})
+    rec["grid"], rec["best"] = res, best
     return rec
 
 
@@ -505,7 +596,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="array", choices=["array", "batched", "large", "time-to-target"])
+    ap.add_argument("--workload", default="array",
+                    choices=["array", "batched", "large", "time-to-target", "ttt-tune"])
+    ap.add_argument("--no-ttt", dest="ttt", action="store_false",
+                    help="array workload: skip the time-to-target comparison")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--M", type=int, default=4)
     ap.add_argument("--F", type=int, default=513)
@@ -514,18 +608,19 @@ def main():
     ap.add_argument("--train-steps", type=int, default=None,
                     help="training steps of 8192 bins for the learned start (default: 20000 for "
                          "time-to-target, 2000 for the large workload)")
-    ap.add_argument("--cosine", action="store_true", help="time-to-target: cosine-decayed training rate")
     ap.add_argument("--plain-large", dest="learned_large", action="store_false",
                     help="large workload: plain start only (no learned start)")
-    ap.add_argument("--hidden", default="32,64,256",
+    ap.add_argument("--hidden", default="256,32",
                     help="time-to-target: hidden widths of the learned-start networks (the first one is the "
-                         "headline)")
-    ap.add_argument("--choice-iter", type=int, default=-1,
-                    help="time-to-target: EM iterations after which the plain and learned starts are compared "
-                         "(-1: 0 with the mask-based R, 1 without)")
+                         "primary figure)")
+    ap.add_argument("--choice-iter", type=int, default=0,
+                    help="time-to-target: EM iterations after which the plain and learned starts are compared")
     ap.add_argument("--mask-sharpen", type=float, default=3.0,
                     help="time-to-target: sharpening exponent of the masks that give the learned start its R "
                          "(0: plain R)")
+    ap.add_argument("--chunks", default="16,4",
+                    help="time-to-target: iterations per EM call of the learned path between stop checks (the "
+                         "last one repeats)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="time the eager calls instead of the captured step")
@@ -546,7 +641,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     runner = {"array": run_array, "batched": run_batched, "large": run_large,
-              "time-to-target": run_time_to_target}[args.workload]
+              "time-to-target": run_time_to_target, "ttt-tune": run_ttt_tune}[args.workload]
     print(json.dumps(runner(args)), flush=True)
 
 

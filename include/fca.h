@@ -48,7 +48,10 @@ typedef enum {
     FCA_FP64 = 0,      /* everything in double precision */
     FCA_FP32_BULK = 1  /* per-bin arithmetic in float; the generalized eigen-
                           decomposition, every cross-thread sum and the log-
-                          likelihood sums in double */
+                          likelihood sums in double. Updated powers are kept
+                          >= 1e-30 so that the float arithmetic stays in the
+                          normal range (an all-zero bin roughly halves its
+                          powers at every iteration); FCA_FP64 has no floor */
 } fca_precision;
 
 /* Per-frequency status bits (fca_status_per_freq). A frequency with
@@ -164,8 +167,25 @@ fca_status fca_separate(fca_ctx *c, void *x_out);
 /* Copy the per-frequency FCA_FLAG_* bits, [B][F] int32, to flags. */
 fca_status fca_status_per_freq(const fca_ctx *c, int32_t *flags);
 
+/* Per-frequency log-likelihood of the last EM call on the context
+ * (fca_em_step, fca_conv_em_step or fca_graph_launch, whichever ran last):
+ * ll_out is [rows][B][F] doubles, host or device; entry (r, b, f) is the
+ * log-likelihood (eq. like summed over the frames of frequency f) of
+ * theta^(l) with l = iters - rows + r counted in that call (its loglik
+ * entries summed over f give the per-mixture values). The rows come from
+ * the call's final chunk of at most 128 iterations: 1 <= rows <=
+ * min(iters, 128), or rows = 1 after an iters = 0 call; FCA_E_ARG
+ * otherwise. Mixtures inactive in that call get NaN. FCA_E_STATE before any
+ * EM call and after fca_autotune (its trial runs overwrite the rows).
+ * Waits for the stream; allocates nothing. */
+fca_status fca_loglik_per_freq(const fca_ctx *c, int32_t rows, double *ll_out);
+
 /* Text of the last error of the context (or of the last failed fca_init when
- * c is NULL). The string stays valid until the next call on the context. */
+ * c is NULL). The string stays valid until the next call on the context.
+ * After FCA_E_NOT_PD or FCA_E_NONFINITE from an EM call it names the first
+ * failing mixture and frequency and the iteration of that call (1-based;
+ * of the replay for fca_graph_launch) whose update failed; that frequency
+ * keeps the parameters of the iteration before. */
 const char *fca_last_error(const fca_ctx *c);
 
 /* Free the context and all its device memory. NULL is accepted. */
@@ -304,6 +324,10 @@ fca_status fca_set_learned_starts(fca_ctx *c, fca_mlp *m, int32_t count, const i
  * R_j^(0)(f) = M A_j / tr(A_j) + load I ((1 + load) I where tr(A_j) = 0).
  * These become the stored R start (the powers stay), the initial
  * decomposition is recomputed, and the mixture is reset and made active.
+ * With one microphone R_j^(0) = 1 + load for both sources. A listed mixture
+ * whose stored powers are the plain start (equal powers: every mask would be
+ * 1/2, so R1 = R2, a fixed point of the EM) gives FCA_E_ARG; its powers must
+ * come from v0, fca_set_start or fca_set_learned_starts.
  * 1 <= sharpen <= 64, 0 < load <= 1e6, else FCA_E_ARG. If a decomposition
  * fails (FCA_E_NOT_PD) every listed mixture gets the default R back and is
  * still reset. Waits for the context's stream. A later fca_set_start without

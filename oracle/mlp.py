@@ -8,6 +8,14 @@ soft targets, with its gradient by reverse-mode differentiation. Parameters
 use the library's flat layout (per hidden layer: weight [H][in] then bias
 [H], in = 32 padded inputs for the first layer; then output weight [H] and
 bias [1]); H follows from the length, 2 H^2 + 36 H + 1.
+
+``bf16=True`` evaluates the same network with the storage the library's
+kernels use: the hidden-layer weight matrices, the features and the first
+two layers' GELU outputs are rounded to BF16 (round to nearest even) before
+they enter a product; biases, the output weights, every pre-activation and
+the third layer's GELU output stay unrounded. In the backward pass the
+per-layer deltas (loss gradient with respect to the pre-activations) are
+rounded to BF16 as well. Everything else is FP64.
 """
 from __future__ import annotations
 
@@ -68,47 +76,56 @@ def gelu_grad(x):
     return 0.5 * (1.0 + erf(x / np.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / np.sqrt(2.0 * np.pi)
 
 
-def forward(params, X):
+def _q(a, on):
+    return bf16_round(a).astype(np.float64) if on else a
+
+
+def forward(params, X, bf16=False):
     """(r [n], cache) for features X [n, 32]."""
     Ws, bs, w4, b4 = unpack(params)
-    h, pres, hs = X, [], [X]
-    for W, b in zip(Ws, bs):
+    if bf16:
+        Ws = [_q(W, True) for W in Ws]
+    h = _q(X, bf16)
+    pres, hs = [], [h]
+    for l, (W, b) in enumerate(zip(Ws, bs)):
         a = h @ W.T + b
         pres.append(a)
-        h = gelu(a)
+        h = _q(gelu(a), bf16 and l < 2)
         hs.append(h)
     z = h @ w4 + b4
     r = 1.0 / (1.0 + np.exp(-z))
     return r, (pres, hs, z)
 
 
-def loss(params, X, t):
-    r, (_, _, z) = forward(params, X)
+def loss(params, X, t, bf16=False):
+    r, (_, _, z) = forward(params, X, bf16)
     sp_neg = np.logaddexp(0.0, -z)   # -log r
     sp_pos = np.logaddexp(0.0, z)    # -log(1 - r)
     return float(np.mean(t * sp_neg + (1.0 - t) * sp_pos))
 
 
-def loss_and_grad(params, X, t):
+def loss_and_grad(params, X, t, bf16=False):
     """Mean binary cross-entropy and its gradient (flat, same layout)."""
     Ws, bs, w4, b4 = unpack(params)
-    r, (pres, hs, z) = forward(params, X)
+    if bf16:
+        Ws = [_q(W, True) for W in Ws]
+    r, (pres, hs, z) = forward(params, X, bf16)
     n = X.shape[0]
     dz = (r - t) / n
     g_w4 = hs[-1].T @ dz
     g_b4 = dz.sum()
-    d = np.outer(dz, w4) * gelu_grad(pres[-1])
+    d = _q(np.outer(dz, w4) * gelu_grad(pres[-1]), bf16)
     gW, gb = [None] * 3, [None] * 3
     for l in (2, 1, 0):
         gW[l] = d.T @ hs[l]
         gb[l] = d.sum(0)
         if l > 0:
-            d = (d @ Ws[l]) * gelu_grad(pres[l - 1])
+            d = _q((d @ Ws[l]) * gelu_grad(pres[l - 1]), bf16)
     parts = []
     for l in range(3):
         parts += [gW[l].ravel(), gb[l]]
     parts += [g_w4, np.array([g_b4])]
-    return loss(params, X, t), np.concatenate(parts)
+    return loss(params, X, t, bf16), np.concatenate(parts)
 
 
 def bf16_round(a: np.ndarray) -> np.ndarray:

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <limits>
 #include <vector>
 
 #include "fca.h"
@@ -80,7 +81,7 @@ struct fca_ctx {
     double* ll = nullptr;
     double* ll_tot = nullptr;
     double* ll_host = nullptr;  // pinned
-    int* flag_sum = nullptr;       // device: OR of the flags, first NOT_PD, first NONFINITE
+    int* flag_sum = nullptr;       // device: OR of the flags, first NOT_PD, first NONFINITE, their iterations
     int* flag_sum_host = nullptr;  // pinned copy
     double* fsum = nullptr;
     double2* R_stage = nullptr;
@@ -116,6 +117,12 @@ struct fca_ctx {
     hipGraphExec_t gexec = nullptr;
     int64_t shape_version = 0;  // bumped when activity or launch shapes change
     int64_t graph_version = -1;
+
+    // per-problem log-likelihood rows left in ll by the last EM call (its
+    // final chunk) and the mixtures that call ran (fca_loglik_per_freq)
+    int last_rows = 0;
+    std::vector<char> last_active;
+    int graph_rows = 0;  // the same for the captured step
 
     bool broken = false;
     bool timing = false;
@@ -379,15 +386,17 @@ fca_status refresh_active(fca_ctx* c) {
 fca_status check_flags(fca_ctx* c) {
     const hipStream_t s = c->stream;
     FCA_HIP(c, launch_flag_summary(c->flags, c->nprob, c->flag_sum, s));
-    FCA_HIP(c, hipMemcpyAsync(c->flag_sum_host, c->flag_sum, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    FCA_HIP(c, hipMemcpyAsync(c->flag_sum_host, c->flag_sum, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
     FCA_HIP(c, hipStreamSynchronize(s));
     const int np = c->flag_sum_host[1], nf = c->flag_sum_host[2];
     if (np < c->nprob) {
-        set_err(c, "mixture %d, frequency %d lost positive definiteness", np / c->F, np % c->F);
+        set_err(c, "mixture %d, frequency %d lost positive definiteness in iteration %d of the call", np / c->F,
+                np % c->F, c->flag_sum_host[3]);
         return FCA_E_NOT_PD;
     }
     if (nf < c->nprob) {
-        set_err(c, "mixture %d, frequency %d produced a non-finite value", nf / c->F, nf % c->F);
+        set_err(c, "mixture %d, frequency %d produced a non-finite value in iteration %d of the call", nf / c->F,
+                nf % c->F, c->flag_sum_host[4]);
         return FCA_E_NONFINITE;
     }
     return FCA_OK;
@@ -478,7 +487,7 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     FCA_TRY(dev_alloc(c, &c->probs, (size_t)c->nprob * sizeof(EmProblem)));
     FCA_TRY(dev_alloc(c, &c->probs_act, (size_t)c->nprob * sizeof(EmProblem)));
     FCA_TRY(dev_alloc(c, &c->x_off, (size_t)c->nprob * 2 * sizeof(int64_t)));
-    FCA_TRY(dev_alloc(c, &c->flag_sum, 3 * sizeof(int)));
+    FCA_TRY(dev_alloc(c, &c->flag_sum, 5 * sizeof(int)));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->ll_host), (size_t)kLChunk * B * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -486,7 +495,7 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
         set_err(c, "hipHostMalloc failed");
         FCA_TRY(FCA_E_NOMEM);
     }
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->flag_sum_host), 3 * sizeof(int), hipHostMallocDefault) !=
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->flag_sum_host), 5 * sizeof(int), hipHostMallocDefault) !=
         hipSuccess) {
         (void)hipGetLastError();
         c->flag_sum_host = nullptr;
@@ -809,6 +818,13 @@ fca_status fca_set_mask_covariances(fca_ctx* c, int32_t count, const int32_t* mi
             set_err(c, "fca_set_mask_covariances: mixture %d outside 0..%d", b, c->B - 1);
             return FCA_E_ARG;
         }
+        if (!c->mix[b].has_v0) {
+            // equal powers give the masks 1/2 everywhere and R1 = R2: a fixed
+            // point of the EM that never separates the sources
+            set_err(c, "fca_set_mask_covariances: mixture %d has the plain start's equal powers; give it distinct "
+                       "powers first (v0, fca_set_start or fca_set_learned_starts)", b);
+            return FCA_E_ARG;
+        }
         list[i] = b;
     }
     const hipStream_t s = c->stream;
@@ -830,6 +846,16 @@ fca_status fca_set_mask_covariances(fca_ctx* c, int32_t count, const int32_t* mi
     }
     // one launch per microphone count; the staging is free again when this
     // call returns (it ends with the stream synchronised)
+    // one microphone: A_j is a positive scalar or zero, so R_j = 1 + load
+    // for both sources (no kernel needed)
+    for (int b : list) {
+        const MixInfo& mi = c->mix[b];
+        if (mi.M != 1) continue;
+        const std::vector<double2> one(2 * (size_t)c->F, make_double2(1.0 + load, 0.0));
+        FCA_HIP(c, hipMemcpyAsync(c->R_init + mi.R_base, one.data(), sizeof(double2) * one.size(),
+                                  hipMemcpyHostToDevice, s));
+        FCA_HIP(c, hipStreamSynchronize(s));
+    }
     int k = 0;
     for (int M = 2; M <= kMaxM; ++M) {
         const int k0 = k;
@@ -919,27 +945,27 @@ namespace fca {
 
 hipError_t launch_em(int M, bool fp64, int nt, int fpt, const EmProblem* probs, int count, const void* y,
                      void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll,
-                     int64_t ll_stride, int iters, hipStream_t s) {
+                     int64_t ll_stride, int iters, int it_base, hipStream_t s) {
     if (nt == kEmThreads)
         return launch_em_nt<kEmThreads>(M, fp64, fpt, probs, count, y, v, v_alt, P, lam, logdet, flags, ll,
-                                        ll_stride, iters, s);
+                                        ll_stride, iters, it_base, s);
     if (nt == 128)
         return launch_em_nt<128>(M, fp64, fpt, probs, count, y, v, v_alt, P, lam, logdet, flags, ll, ll_stride,
-                                 iters, s);
+                                 iters, it_base, s);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y, void* v,
                           double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride,
-                          int iters, hipStream_t s) {
+                          int iters, int it_base, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     switch (M) {
 #define FCA_CONV_CASE(MM_)                                                                                         \
     case MM_:                                                                                                      \
         return fp64 ? launch_conv_fpt<MM_, double>(fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, \
-                                                    iters, s)                                                      \
+                                                    iters, it_base, s)                                             \
                     : launch_conv_fpt<MM_, float>(fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride,   \
-                                                   iters, s);
+                                                   iters, it_base, s);
         FCA_CONV_CASE(1) FCA_CONV_CASE(2) FCA_CONV_CASE(3) FCA_CONV_CASE(4)
         FCA_CONV_CASE(5) FCA_CONV_CASE(6) FCA_CONV_CASE(7) FCA_CONV_CASE(8)
 #undef FCA_CONV_CASE
@@ -968,7 +994,7 @@ fca_status ensure_side_streams(fca_ctx* c, int want) {
 // group on stream s, the others spread over the side streams, all forked from
 // and joined back to s (so the groups' tails overlap instead of serialising).
 fca_status enqueue_em_groups(fca_ctx* c, const std::vector<Group>& groups, const EmProblem* probs, int chunk,
-                             bool conventional, hipStream_t s) {
+                             int it_base, bool conventional, hipStream_t s) {
     const int ng = (int)groups.size();
     int nside = 0;
     if (ng > 1 && !conventional) {
@@ -989,10 +1015,10 @@ fca_status enqueue_em_groups(fca_ctx* c, const std::vector<Group>& groups, const
         if (nside > 0 && i != big) gs = c->side[(k++) % nside];
         if (conventional)
             FCA_HIP(c, launch_conv_em(g.M, c->fp64, g.fpt, probs + g.first, g.count, c->y, c->v, c->P, c->lam,
-                                      c->logdet, c->flags, c->ll, c->nprob, chunk, gs));
+                                      c->logdet, c->flags, c->ll, c->nprob, chunk, it_base, gs));
         else
             FCA_HIP(c, launch_em(g.M, c->fp64, g.nt, g.run_fpt, probs + g.first, g.count, c->y, c->v, c->v_alt,
-                                 c->P, c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, gs));
+                                 c->P, c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, it_base, gs));
     }
     for (int i = 0; i < nside; ++i) {
         FCA_HIP(c, hipEventRecord(c->join_ev[i], c->side[i]));
@@ -1077,7 +1103,7 @@ fca_status em_step_impl(fca_ctx* c, int32_t iters, double* loglik, double* R_out
         const int rows = chunk > 0 ? chunk : 1;
         if (c->timing) FCA_HIP(c, hipEventRecord(c->ev0, s));
         {
-            fca_status st = enqueue_em_groups(c, groups, probs, chunk, conventional, s);
+            fca_status st = enqueue_em_groups(c, groups, probs, chunk, done, conventional, s);
             if (st != FCA_OK) return st;
         }
         if (c->timing) FCA_HIP(c, hipEventRecord(c->ev1, s));
@@ -1100,8 +1126,10 @@ fca_status em_step_impl(fca_ctx* c, int32_t iters, double* loglik, double* R_out
             c->em_ms += ms;
             c->em_launches += (int64_t)groups.size();
         }
+        c->last_rows = rows;
         done += chunk;
     } while (done < iters);
+    c->last_active = c->active;
 
     if (R_out) {
         const bool dev = is_device_ptr(R_out);
@@ -1182,7 +1210,7 @@ fca_status fca_status_per_freq(const fca_ctx* c, int32_t* flags) {
     FCA_HIP(cc, hipMemcpyAsync(cc->flags_host.data(), cc->flags, sizeof(int) * cc->nprob,
                                hipMemcpyDeviceToHost, cc->stream));
     FCA_HIP(cc, hipStreamSynchronize(cc->stream));
-    memcpy(flags, cc->flags_host.data(), sizeof(int) * cc->nprob);
+    for (int i = 0; i < cc->nprob; ++i) flags[i] = cc->flags_host[i] & kFlagBitsMask;
     return FCA_OK;
 }
 
@@ -1289,6 +1317,7 @@ fca_status fca_set_launch_shape(fca_ctx* c, int32_t group, int32_t threads, int3
 }
 
 fca_status fca_autotune(fca_ctx* c, int32_t iters) {
+    if (c) c->last_rows = 0;  // the trials overwrite the per-problem log-likelihood rows
     if (!c) return FCA_E_ARG;
     if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
     iters = iters <= 0 ? 3 : std::min(iters, kLChunk);
@@ -1328,7 +1357,7 @@ fca_status fca_autotune(fca_ctx* c, int32_t iters) {
                 if (e == hipSuccess) e = hipEventRecord(c->ev0, s);
                 if (e == hipSuccess)
                     e = launch_em(g.M, c->fp64, nt, f, c->probs + g.first, g.count, c->y, c->v, c->v_alt, c->P,
-                                  c->lam, c->logdet, c->flags, c->ll, c->nprob, iters, s);
+                                  c->lam, c->logdet, c->flags, c->ll, c->nprob, iters, 0, s);
                 if (e == hipSuccess) e = hipEventRecord(c->ev1, s);
                 if (e == hipSuccess) e = hipEventSynchronize(c->ev1);
                 float ms = 0.f;
@@ -1389,9 +1418,10 @@ fca_status fca_graph_capture(fca_ctx* c, int32_t iters, int32_t with_reset, doub
         do {
             const int chunk = iters == 0 ? 0 : std::min(kLChunk, iters - done);
             const int rows = chunk > 0 ? chunk : 1;
-            fca_status r = enqueue_em_groups(c, groups, probs, chunk, false, s);
+            fca_status r = enqueue_em_groups(c, groups, probs, chunk, done, false, s);
             if (r == FCA_OK && loglik) r = enqueue_ll_out(c, rows, iters > 0 ? iters : 1, done, loglik, s);
             if (r != FCA_OK) return r;
+            c->graph_rows = rows;
             done += chunk;
         } while (done < iters);
         fca_status r = FCA_OK;
@@ -1429,7 +1459,38 @@ fca_status fca_graph_launch(fca_ctx* c, int32_t count) {
     }
     if (count < 1) { set_err(c, "fca_graph_launch: count < 1"); return FCA_E_ARG; }
     for (int i = 0; i < count; ++i) FCA_HIP(c, hipGraphLaunch(c->gexec, c->stream));
+    c->last_rows = c->graph_rows;
+    c->last_active = c->active;
     return check_flags(c);
+}
+
+fca_status fca_loglik_per_freq(const fca_ctx* cc, int32_t rows, double* ll_out) {
+    if (!cc || !ll_out) return FCA_E_ARG;
+    fca_ctx* c = const_cast<fca_ctx*>(cc);
+    if (c->broken) { set_err(c, "context unusable after an earlier device error"); return FCA_E_STATE; }
+    if (c->last_rows == 0) { set_err(c, "fca_loglik_per_freq: no EM call yet"); return FCA_E_STATE; }
+    if (rows < 1 || rows > c->last_rows) {
+        set_err(c, "fca_loglik_per_freq: rows %d outside 1..%d", rows, c->last_rows);
+        return FCA_E_ARG;
+    }
+    const hipStream_t s = c->stream;
+    const int64_t n = (int64_t)rows * c->nprob;
+    FCA_HIP(c, hipMemcpyAsync(ll_out, c->ll + (int64_t)(c->last_rows - rows) * c->nprob, n * sizeof(double),
+                              hipMemcpyDefault, s));
+    const bool dev = is_device_ptr(ll_out);
+    if (!dev) FCA_HIP(c, hipStreamSynchronize(s));
+    for (int b = 0; b < c->B; ++b) {
+        if (c->last_active[b]) continue;
+        for (int r = 0; r < rows; ++r) {
+            double* row = ll_out + (int64_t)r * c->nprob + (int64_t)b * c->F;
+            if (dev)  // all-ones words: NaN doubles
+                FCA_HIP(c, launch_fill_u32(row, 0xFFFFFFFFu, 2 * (int64_t)c->F, s));
+            else
+                for (int f = 0; f < c->F; ++f) row[f] = std::numeric_limits<double>::quiet_NaN();
+        }
+    }
+    if (dev) FCA_HIP(c, hipStreamSynchronize(s));
+    return FCA_OK;
 }
 
 }  // extern "C"

@@ -184,11 +184,18 @@ __device__ __forceinline__ void conv_bin(const T (&yr)[M], const T (&yi)[M], T a
             q2 += m2r[a] * t2r + m2i[a] * t2i + s2.x * Cr[b][a] - s2.y * Ci[b][a];
         }
     }
-    const T nv1 = q1 * (T(1) / T(M));
-    const T nv2 = q2 * (T(1) / T(M));
+    T nv1 = q1 * (T(1) / T(M));
+    T nv2 = q2 * (T(1) / T(M));
     if (ok) {
         llacc += (double)(-logdet - quad);
         bad = bad || !(nv1 > T(0)) || !(nv2 > T(0)) || !isfinite(nv1) || !isfinite(nv2);
+    }
+    if constexpr (sizeof(T) == 4) {
+        // the same power floor as the FastFCA float path
+        nv1 = fmaxf(nv1, kPowerFloorF32);
+        nv2 = fmaxf(nv2, kPowerFloorF32);
+    }
+    if (ok) {
         nv1o = nv1;
         nv2o = nv2;
     }
@@ -217,7 +224,7 @@ template <int M, typename T, int FPT>
 __global__ __launch_bounds__(kEmThreads) void conv_em_kernel(
     const EmProblem* __restrict__ probs, const typename Vec2<T>::type* __restrict__ y, T* __restrict__ v,
     double2* __restrict__ Pg, double* __restrict__ lamg, double* __restrict__ logdetg, int* __restrict__ flagsg,
-    double* __restrict__ ll, int64_t ll_stride, int iters) {
+    double* __restrict__ ll, int64_t ll_stride, int iters, int it_base) {
     using T2 = typename Vec2<T>::type;
     constexpr int NT = kEmThreads;
     constexpr int MM = M * M, NV = 2 * MM, NW = kEmThreads / 64;
@@ -315,8 +322,8 @@ __global__ __launch_bounds__(kEmThreads) void conv_em_kernel(
                 bool finite = true;
                 for (int e = 0; e < MM; ++e) finite = finite && cfinite(sh.S[0][e]) && cfinite(sh.S[1][e]);
                 if (sh.bad || !finite) {
-                    // frozen at theta^(it)
-                    sh.flag |= kFlagNonFinite;
+                    // frozen at theta^(it); the failing iteration of the call is recorded
+                    sh.flag |= kFlagNonFinite | ((it_base + it + 1) << kFlagIterShift);
                     for (int e = 0; e < MM; ++e) {
                         sh.S[0][e] = sh.Sold[0][e];
                         sh.S[1][e] = sh.Sold[1][e];
@@ -362,15 +369,15 @@ __global__ __launch_bounds__(kEmThreads) void conv_em_kernel(
 template <int M, typename T>
 hipError_t launch_conv_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v, double2* P,
                                   double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride, int iters,
-                                  hipStream_t s) {
+                                  int it_base, hipStream_t s) {
     using T2 = typename Vec2<T>::type;
     const T2* yy = static_cast<const T2*>(y);
     T* vv = static_cast<T*>(v);
     switch (fpt) {
-        case 1: conv_em_kernel<M, T, 1><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
-        case 2: conv_em_kernel<M, T, 2><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
-        case 4: conv_em_kernel<M, T, 4><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
-        case 8: conv_em_kernel<M, T, 8><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters); break;
+        case 1: conv_em_kernel<M, T, 1><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base); break;
+        case 2: conv_em_kernel<M, T, 2><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base); break;
+        case 4: conv_em_kernel<M, T, 4><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base); break;
+        case 8: conv_em_kernel<M, T, 8><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

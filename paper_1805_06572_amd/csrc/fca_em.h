@@ -160,11 +160,19 @@ __device__ __forceinline__ void em_bin_front(const T (&yr)[M], const T (&yi)[M],
         s1 = fma(r[i], fma(a1 * lm[i], er, a2), s1);
         s2 = fma(r[i], fma(a2, er, a1 * lm[i]), s2);
     }
-    const T nv1 = a1 * s1 * (T(1) / T(M));
-    const T nv2 = a2 * s2 * (T(1) / T(M));
+    T nv1 = a1 * s1 * (T(1) / T(M));
+    T nv2 = a2 * s2 * (T(1) / T(M));
     if (ok) {
         llacc += (double)(-logd - quad);
         bad = bad || !(nv1 > T(0)) || !(nv2 > T(0)) || !isfinite(nv1) || !isfinite(nv2);
+    }
+    if constexpr (sizeof(T) == 4) {
+        // float bulk: keep the powers normal (tested for failure first, so a
+        // NaN is still caught)
+        nv1 = fmaxf(nv1, kPowerFloorF32);
+        nv2 = fmaxf(nv2, kPowerFloorF32);
+    }
+    if (ok) {
         nv1o = nv1;
         nv2o = nv2;
     }
@@ -386,7 +394,7 @@ __device__ __forceinline__ void wg_reduce_mf(EmSharedMf<M, NT_>& sh, const float
 // that froze it now (it then keeps theta^(it), whose log-likelihood stands
 // for the later iterations).
 template <int M, typename Sh>
-__device__ __forceinline__ bool em_update(Sh& sh, int it, int iters, bool frozen_at_entry, int nf,
+__device__ __forceinline__ bool em_update(Sh& sh, int it, int iters, int it_base, bool frozen_at_entry, int nf,
                                           double* __restrict__ ll, int64_t ll_stride, int pid, double eps2,
                                           int tid) {
     constexpr int MM = M * M, NW = Sh::NW;
@@ -413,6 +421,7 @@ __device__ __forceinline__ bool em_update(Sh& sh, int it, int iters, bool frozen
             if (flag & kFreezeMask) {
                 if (tid == 0)
                     for (int l = it + 1; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
+                flag |= (it_base + it + 1) << kFlagIterShift;  // the failing iteration of the call
             } else {
                 if (tid < MM) sh.P[tid] = sh.Pn[tid];
                 if (tid < M) sh.lam[tid] = sh.lamN[tid];
@@ -431,12 +440,12 @@ __device__ __forceinline__ bool em_update(Sh& sh, int it, int iters, bool frozen
 // S~_j = sums / N, then em_update.
 template <int M, typename T, int NT_>
 __device__ __forceinline__ bool em_finish(EmShared<M, T, NT_>& sh, const T (&acc)[2 * M * M], double llacc,
-                                          bool bad, int it, int iters, bool frozen_at_entry, int nf,
+                                          bool bad, int it, int iters, int it_base, bool frozen_at_entry, int nf,
                                           double* __restrict__ ll, int64_t ll_stride, int pid, double eps2,
                                           int tid) {
     if (bad) sh.bad = 1;
     wg_reduce_sums<M>(sh, acc, llacc, nf, tid);
-    return em_update<M>(sh, it, iters, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid);
+    return em_update<M>(sh, it, iters, it_base, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid);
 }
 
 // Per-pass accumulation of one thread: per-thread sums (em_bin, em_finish)
@@ -460,9 +469,9 @@ template <int M, typename T> struct PassAcc<M, T, false> {
         em_bin<M, T>(yr, yi, a1, a2, lm, sh.Pt, ok, acc, llacc, n1, n2, bad);
     }
     template <typename Sh>
-    __device__ __forceinline__ bool finish(Sh& sh, double llacc, bool bad, int it, int iters, bool frozen, int nf,
+    __device__ __forceinline__ bool finish(Sh& sh, double llacc, bool bad, int it, int iters, int it_base, bool frozen, int nf,
                                            double* __restrict__ ll, int64_t ll_stride, int pid, double eps2, int tid) {
-        return em_finish<M, T>(sh, acc, llacc, bad, it, iters, frozen, nf, ll, ll_stride, pid, eps2, tid);
+        return em_finish<M, T>(sh, acc, llacc, bad, it, iters, it_base, frozen, nf, ll, ll_stride, pid, eps2, tid);
     }
 };
 
@@ -484,11 +493,11 @@ template <int M> struct PassAcc<M, float, true> {
         em_bin_mf<M>(yr, yi, a1, a2, lm, sh.Pt, ok, llacc, n1, n2, bad, sh.u.stg[tid >> 6], cd, am, tid & 63);
     }
     template <typename Sh>
-    __device__ __forceinline__ bool finish(Sh& sh, double llacc, bool bad, int it, int iters, bool frozen, int nf,
+    __device__ __forceinline__ bool finish(Sh& sh, double llacc, bool bad, int it, int iters, int it_base, bool frozen, int nf,
                                            double* __restrict__ ll, int64_t ll_stride, int pid, double eps2, int tid) {
         if (bad) sh.bad = 1;
         wg_reduce_mf<M, Sh::NTH>(sh, cd, am, llacc, nf, tid);
-        return em_update<M>(sh, it, iters, frozen, nf, ll, ll_stride, pid, eps2, tid);
+        return em_update<M>(sh, it, iters, it_base, frozen, nf, ll, ll_stride, pid, eps2, tid);
     }
 };
 
@@ -501,7 +510,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(M <= 4 ? 3 :
     const EmProblem* __restrict__ probs, const typename Vec2<T>::type* __restrict__ y,
     T* __restrict__ v, double2* __restrict__ Pg, double* __restrict__ lamg,
     double* __restrict__ logdetg, int* __restrict__ flagsg, double* __restrict__ ll,
-    int64_t ll_stride, int iters, double eps2) {
+    int64_t ll_stride, int iters, int it_base, double eps2) {
     using T2 = typename Vec2<T>::type;
     constexpr bool MF = use_mfma<M, T>();
     __shared__ EmSh<M, T, NT> sh;
@@ -558,7 +567,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(M <= 4 ? 3 :
             __builtin_amdgcn_sched_barrier(0);
             pa.bin(sh, yr[k], yi[k], v1[k], v2[k], lm, (k * NT + tid) < nf, llacc, v1n[k], v2n[k], bad, tid);
         }
-        if (pa.finish(sh, llacc, bad, it, iters, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid)) break;
+        if (pa.finish(sh, llacc, bad, it, iters, it_base, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid)) break;
 #pragma unroll
         for (int k = 0; k < FPT; ++k) {
             v1[k] = v1n[k];
@@ -591,7 +600,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const EmProblem* __restrict__ probs, const typename Vec2<T>::type* __restrict__ y,
     T* __restrict__ v, int64_t v_alt, double2* __restrict__ Pg, double* __restrict__ lamg,
     double* __restrict__ logdetg, int* __restrict__ flagsg, double* __restrict__ ll,
-    int64_t ll_stride, int iters, double eps2) {
+    int64_t ll_stride, int iters, int it_base, double eps2) {
     using T2 = typename Vec2<T>::type;
     constexpr bool MF = use_mfma<M, T>();
     __shared__ EmSh<M, T, NT> sh;
@@ -650,7 +659,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
                 }
             }
         }
-        if (pa.finish(sh, llacc, bad, it, iters, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid)) break;
+        if (pa.finish(sh, llacc, bad, it, iters, it_base, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid)) break;
         cur ^= 1;
     }
 
@@ -674,7 +683,7 @@ constexpr double kEps2Fp32Bulk = 1e-16;
 template <int M, typename T, int NT>
 hipError_t launch_em_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v, int64_t v_alt,
                          double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride,
-                         int iters, hipStream_t s) {
+                         int iters, int it_base, hipStream_t s) {
     using T2 = typename Vec2<T>::type;
     const double eps2 = sizeof(T) == 8 ? kEps2Fp64 : kEps2Fp32Bulk;
     const dim3 grid(count), block(NT);
@@ -684,15 +693,15 @@ hipError_t launch_em_fpt(int fpt, const EmProblem* probs, int count, const void*
         case 0:
             if constexpr (NT == kEmThreads) {
                 em_stream_kernel<M, T, kStreamFramesPerThread, NT><<<grid, block, 0, s>>>(
-                    probs, yy, vv, v_alt, P, lam, logdet, flags, ll, ll_stride, iters, eps2);
+                    probs, yy, vv, v_alt, P, lam, logdet, flags, ll, ll_stride, iters, it_base, eps2);
                 break;
             } else {
                 return hipErrorInvalidValue;  // streamed problems run with kEmThreads threads only
             }
-        case 1: em_kernel<M, T, 1, NT><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, eps2); break;
-        case 2: em_kernel<M, T, 2, NT><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, eps2); break;
-        case 4: em_kernel<M, T, 4, NT><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, eps2); break;
-        case 8: em_kernel<M, T, 8, NT><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, eps2); break;
+        case 1: em_kernel<M, T, 1, NT><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base, eps2); break;
+        case 2: em_kernel<M, T, 2, NT><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base, eps2); break;
+        case 4: em_kernel<M, T, 4, NT><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base, eps2); break;
+        case 8: em_kernel<M, T, 8, NT><<<grid, block, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base, eps2); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -701,15 +710,15 @@ hipError_t launch_em_fpt(int fpt, const EmProblem* probs, int count, const void*
 template <int NT>
 hipError_t launch_em_nt(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y, void* v,
                         int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll,
-                        int64_t ll_stride, int iters, hipStream_t s) {
+                        int64_t ll_stride, int iters, int it_base, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     switch (M) {
 #define FCA_EM_CASE(MM_)                                                                                      \
     case MM_:                                                                                                  \
         return fp64 ? launch_em_fpt<MM_, double, NT>(fpt, probs, count, y, v, v_alt, P, lam, logdet, flags, ll, \
-                                                     ll_stride, iters, s)                                      \
+                                                     ll_stride, iters, it_base, s)                                      \
                     : launch_em_fpt<MM_, float, NT>(fpt, probs, count, y, v, v_alt, P, lam, logdet, flags, ll,  \
-                                                    ll_stride, iters, s);
+                                                    ll_stride, iters, it_base, s);
         FCA_EM_CASE(1) FCA_EM_CASE(2) FCA_EM_CASE(3) FCA_EM_CASE(4)
         FCA_EM_CASE(5) FCA_EM_CASE(6) FCA_EM_CASE(7) FCA_EM_CASE(8)
 #undef FCA_EM_CASE

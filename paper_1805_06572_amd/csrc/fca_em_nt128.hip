@@ -4,5 +4,5 @@
 namespace fca {
 template hipError_t launch_em_nt<128>(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
                                       void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags,
-                                      double* ll, int64_t ll_stride, int iters, hipStream_t s);
+                                      double* ll, int64_t ll_stride, int iters, int it_base, hipStream_t s);
 }  // namespace fca

@@ -14,9 +14,19 @@ constexpr int kFlagNotPD = 1;
 constexpr int kFlagNonFinite = 2;
 constexpr int kFlagSweeps = 4;
 constexpr int kFreezeMask = kFlagNotPD | kFlagNonFinite;
+// Bits from kFlagIterShift up of a problem's flag word hold the iteration of
+// the EM call (1-based, counted over the call's chunks) whose update froze
+// the problem; the status bits exported to callers are the low byte.
+constexpr int kFlagIterShift = 8;
+constexpr int kFlagBitsMask = 0xFF;
 
 // Largest microphone count; per-frequency state is stored with this stride.
 constexpr int kMaxM = 8;
+// Smallest power the float bulk mode keeps after an M-step: an all-zero bin
+// roughly halves its powers at every iteration, and below this value the
+// float d_i, their reciprocals and logarithms would leave the normal range
+// (FLT_MIN is 1.2e-38). Double precision has no floor.
+constexpr float kPowerFloorF32 = 1e-30f;
 
 // Threads per workgroup of the per-frequency EM kernel, and the largest
 // number of frames each thread keeps in registers.
@@ -51,13 +61,13 @@ struct EmProblem {
 template <int NT>
 hipError_t launch_em_nt(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y, void* v,
                         int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll,
-                        int64_t ll_stride, int iters, hipStream_t s);
+                        int64_t ll_stride, int iters, int it_base, hipStream_t s);
 
 // Dispatch on nt (kEmThreads or 128); defined in fca_api.hip, which sees only
 // the declaration above, so each instantiation lives in its own translation unit.
 hipError_t launch_em(int M, bool fp64, int nt, int fpt, const EmProblem* probs, int count, const void* y,
                      void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll,
-                     int64_t ll_stride, int iters, hipStream_t s);
+                     int64_t ll_stride, int iters, int it_base, hipStream_t s);
 
 // The conventional frame-wise EM (fca_conv.h; resident frames only, fpt in
 // 1, 2, 4, 8, kEmThreads threads): per (M, T) launcher, instantiated in
@@ -66,11 +76,11 @@ hipError_t launch_em(int M, bool fp64, int nt, int fpt, const EmProblem* probs, 
 template <int M, typename T>
 hipError_t launch_conv_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v, double2* P,
                            double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride, int iters,
-                           hipStream_t s);
+                           int it_base, hipStream_t s);
 
 hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
                           void* v, double2* P, double* lam, double* logdet, int* flags, double* ll,
-                          int64_t ll_stride, int iters, hipStream_t s);
+                          int64_t ll_stride, int iters, int it_base, hipStream_t s);
 
 // Support kernels (fca_kernels.hip).
 // p[i] = val for count 32-bit words (a kernel, not a memset: graph-capturable).

@@ -110,7 +110,8 @@ hipError_t launch_fill_u32(void* p, uint32_t val, int64_t count, hipStream_t s) 
 
 // Summary of the per-problem status flags: out[0] = their bitwise OR,
 // out[1] / out[2] = the first problem flagged kFlagNotPD / kFlagNonFinite
-// (count if none). One workgroup of kFlagThreads threads.
+// (count if none); out[3] / out[4] = the iteration recorded in their flag
+// words (0 if none). One workgroup of kFlagThreads threads.
 constexpr int kFlagThreads = 1024;
 __global__ __launch_bounds__(kFlagThreads) void flag_summary_kernel(const int* __restrict__ flags, int count,
                                                                     int* __restrict__ out) {
@@ -136,9 +137,11 @@ __global__ __launch_bounds__(kFlagThreads) void flag_summary_kernel(const int* _
         __syncthreads();
     }
     if (t == 0) {
-        out[0] = s_or[0];
+        out[0] = s_or[0] & kFlagBitsMask;
         out[1] = s_np[0];
         out[2] = s_nf[0];
+        out[3] = s_np[0] < count ? flags[s_np[0]] >> kFlagIterShift : 0;
+        out[4] = s_nf[0] < count ? flags[s_nf[0]] >> kFlagIterShift : 0;
     }
 }
 

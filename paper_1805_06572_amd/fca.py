@@ -38,7 +38,7 @@ EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set
             "fca_mlp_create", "fca_mlp_destroy", "fca_mlp_num_params", "fca_mlp_last_error",
             "fca_mlp_get_params", "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward",
             "fca_mlp_adamw", "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
-            "fca_set_mask_covariances"]
+            "fca_set_mask_covariances", "fca_loglik_per_freq"]
 
 
 class fca_problem(ctypes.Structure):
@@ -104,11 +104,13 @@ def lib() -> ctypes.CDLL:
                                                 ctypes.POINTER(vp)]
         L.fca_set_learned_starts.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
         L.fca_set_mask_covariances.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.c_double, ctypes.c_double]
+        L.fca_loglik_per_freq.argtypes = [vp, i32, vp]
         for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set_active", "fca_em_step", "fca_conv_em_step", "fca_separate",
                      "fca_status_per_freq", "fca_gevd", "fca_timing", "fca_launch_groups",
                      "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch", "fca_mlp_create", "fca_mlp_get_params",
                      "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward", "fca_mlp_adamw",
-                     "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts"):
+                     "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
+                     "fca_set_mask_covariances", "fca_loglik_per_freq"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -293,6 +295,15 @@ def fca_status_per_freq(ctx: Ctx) -> np.ndarray:
     flags = np.zeros((ctx.B, ctx.F), np.int32)
     _check(lib().fca_status_per_freq(ctx.handle, flags.ctypes.data), ctx)
     return flags
+
+
+def fca_loglik_per_freq(ctx: Ctx, rows: int = 1) -> torch.Tensor:
+    """[rows, B, F] float64 device tensor: per-frequency log-likelihood of
+    the last `rows` iterations of the previous EM call (NaN for mixtures that
+    call skipped)."""
+    out = torch.empty((rows, ctx.B, ctx.F), dtype=torch.float64, device=ctx.device)
+    _check(lib().fca_loglik_per_freq(ctx.handle, int(rows), out.data_ptr()), ctx)
+    return out
 
 
 def fca_destroy(ctx: Ctx):

@@ -8,11 +8,12 @@ the whole GPU.
 from __future__ import annotations
 
 import numpy as np
+import torch
 
 from . import fca
 
 
-def run_batch(ctx, max_iters: int, chunk, stop):
+def run_batch(ctx, max_iters: int, chunk, stop, weights=None):
     """Run until every mixture is stopped or has had max_iters iterations.
 
     chunk: iterations per fca_em_step call, an int or a sequence of ints whose
@@ -22,6 +23,10 @@ def run_batch(ctx, max_iters: int, chunk, stop):
     history ll = [LL(theta^(0)), ..., LL(theta^(l-1))] of each still-active
     mixture b after l iterations (the parameters then stand at theta^(l), at
     least as likely by the monotonicity of EM).
+    weights: optional [B, F] tensor on the context's device; the histories
+    are then sum_f weights[b, f] LL_f (per-frequency values from
+    fca_loglik_per_freq), e.g. a 0/1 mask of the frequencies a comparison
+    trusts.
     Returns (iterations run per mixture [B], list of LL histories)."""
     B = ctx.B
     hist = [[] for _ in range(B)]
@@ -34,8 +39,15 @@ def run_batch(ctx, max_iters: int, chunk, stop):
         call += 1
         if k <= 0:
             break
-        ll, _, _ = fca.fca_em_step(ctx, k, want_R=False, want_v=False, allow_flags=True)
-        ll = ll.cpu().numpy()
+        ll, _, _ = fca.fca_em_step(ctx, k, want_loglik=weights is None, want_R=False, want_v=False,
+                                   allow_flags=True)
+        if weights is None:
+            ll = ll.cpu().numpy()
+        else:
+            assert k <= 128, "per-frequency rows cover at most 128 iterations of a call"
+            per_f = fca.fca_loglik_per_freq(ctx, k)                   # [k, B, F]
+            per_f = torch.where(weights > 0, per_f * weights, torch.zeros_like(per_f))
+            ll = per_f.sum(-1).T.cpu().numpy()                          # [B, k]
         for b in np.nonzero(active)[0]:
             hist[b].extend(ll[b].tolist())
             iters[b] += k

@@ -117,6 +117,37 @@ def test_fp64_degenerate_mixtures(fca, case):
         assert not np.any(gx)
 
 
+@pytest.mark.parametrize("case", ["silent", "one_bin"])
+def test_fp32_degenerate_mixtures(fca, case):
+    """Float bulk on the degenerate mixtures: the powers of all-zero bins
+    roughly halve at every iteration. Against the oracle (same start) while
+    they stay above the float path's floor (1e-30): 40 iterations; then 100
+    iterations, where the oracle's smallest powers fall below 1e-30: no flag,
+    everything finite, powers at or above the floor, the log-likelihood never
+    decreasing."""
+    y = np.zeros((3, 70, 2), np.complex64)
+    if case == "one_bin":
+        y[1, 3, 0] = 1.0
+    y64 = y.astype(np.complex128)
+    S0, v0 = oracle.default_init(y64)
+    S, v, ll, flags = oracle.em(y64, S0, v0, 40, threads=8)
+    assert not flags.any() and v.min() > 1e-28
+    gll, gR, gv, gflags, gx = run_gpu(fca, y, fca.FCA_FP32_BULK, 40)
+    assert not gflags.any()
+    assert per_freq_rel(gv.astype(np.float64), v, (-1,)).max() < 1e-4
+    assert per_freq_rel(gR, S, (-2, -1)).max() < 1e-4
+    np.testing.assert_allclose(gll, ll[:40].sum(1), rtol=1e-4)
+    gll, gR, gv, gflags, gx = run_gpu(fca, y, fca.FCA_FP32_BULK, 100)
+    _, vo, _, _ = oracle.em(y64, S0, v0, 100, threads=8)
+    assert vo.min() < 1e-30
+    assert not gflags.any()
+    assert np.all(np.isfinite(gv)) and np.all(np.isfinite(gR)) and np.all(np.isfinite(gll))
+    assert gv.min() >= np.float32(1e-30)
+    assert np.all(np.diff(gll) >= -1e-6 * np.abs(gll[1:]))
+    if case == "silent":
+        assert not np.any(gx)
+
+
 def test_fp64_user_start(fca):
     """Caller-supplied R0 and v0 (the generator's truth scaled)."""
     mx = synth.random_mixture(3, 6, 120, 12)
@@ -148,16 +179,19 @@ def test_fp32_array_workload_full_size(fca, array_workload):
     mx, S, v, ll, oflags = array_workload
     gll, gR, gv, gflags, gx = run_gpu(fca, mx.y, fca.FCA_FP32_BULK, 50, allow_flags=True)
     kappa = synth.condition_numbers(mx.R)
-    gate = (kappa <= 1e3) & (oflags == 0) & (gflags == 0)
+    gate = (kappa <= 1e3) & (oflags == 0)
     assert gate.sum() > 300
+    # inside the gate the GPU flags nothing the oracle does not flag
+    assert not gflags[gate].any()
     assert np.all(np.isfinite(gv)) and np.all(np.isfinite(gll))
+    # measured maxima on the gate: v 2.3e-6, R 1.7e-6, x 2.0e-6
     err_v = per_freq_rel(gv.astype(np.float64), v, (-1,))
     assert err_v[:, gate].max() < 1e-4
     err_R = per_freq_rel(gR, S, (-2, -1))
-    assert err_R[:, gate].max() < 1e-2
+    assert err_R[:, gate].max() < 1e-4
     x = oracle.mmse(mx.y.astype(np.complex128), S, v)
     err_x = per_freq_rel(gx.astype(np.complex128), x, (-2, -1))
-    assert err_x[:, gate].max() < 1e-3
+    assert err_x[:, gate].max() < 1e-4
 
 
 def test_fp32_loglik_per_iteration(fca, array_workload):
@@ -189,7 +223,7 @@ def test_large_workload_subsample(fca):
     kappa = synth.condition_numbers(mx.R)
     gate = (kappa <= 1e3) & (oflags == 0)
     gll, gR, gv, gflags, _ = run_gpu(fca, mx.y, fca.FCA_FP32_BULK, 30, separate=False, allow_flags=True)
-    gate &= gflags == 0
+    assert not gflags[gate].any()
     assert gate.sum() >= 5
     assert per_freq_rel(gv.astype(np.float64), v, (-1,))[:, gate].max() < 1e-4
     # FP64 on the frequencies with kappa(R_true) <= 1e3 (the grid's lowest
@@ -230,8 +264,9 @@ def test_fp32_mfma_accumulation_matches_oracle(fca, M, N, threads):
     finally:
         fca.fca_destroy(ctx)
     gv = gv[0].double().cpu().numpy()
+    # measured maxima over these shapes: v 7.9e-7, R 1.0e-6, LL 2.2e-6
     assert per_freq_rel(gv, v, (-1,)).max() < 1e-4
-    assert per_freq_rel(gR[0].cpu().numpy(), S, (-2, -1)).max() < 1e-3
+    assert per_freq_rel(gR[0].cpu().numpy(), S, (-2, -1)).max() < 1e-4
     # relative to the summed magnitudes of the per-frequency terms: the total
     # itself crosses zero during these iterations
     want, scale = ll[:12].sum(1), np.abs(ll[:12]).sum(1)
@@ -451,6 +486,8 @@ def test_nonfinite_bin_freezes_only_its_frequency(fca):
         with pytest.raises(fca.FcaError) as ei:
             fca.fca_em_step(ctx, 5)
         assert ei.value.status in (fca.FCA_E_NONFINITE, fca.FCA_E_NOT_PD)
+        # the error names the first failing problem and the iteration of the call
+        assert "mixture 0, frequency 3" in str(ei.value) and "iteration 1 of the call" in str(ei.value)
         flags = fca.fca_status_per_freq(ctx)[0]
         _, R, v = fca.fca_em_step(ctx, 0, allow_flags=True)
     finally:
@@ -576,5 +613,42 @@ def test_conventional_kernel_rejects_streamed_mixtures(fca):
         with pytest.raises(fca.FcaError) as ei:
             fca.fca_conv_em_step(ctx, 1)
         assert ei.value.status == fca.FCA_E_ARG
+    finally:
+        fca.fca_destroy(ctx)
+
+
+def test_loglik_per_freq_matches_oracle(fca):
+    """fca_loglik_per_freq: per-frequency LL(theta^l) of the last call's
+    final rows against the oracle's per-frequency values (FP64, 1e-10);
+    their sums are the per-mixture values; a skipped mixture reads NaN; row
+    counts beyond the call are refused."""
+    mxs = [synth.random_mixture(2, 7, 90, 71), synth.random_mixture(2, 7, 130, 72)]
+    ctx = fca.fca_init_batch([torch.from_numpy(m.y).to(DEV) for m in mxs], prec=fca.FCA_FP64)
+    try:
+        with pytest.raises(fca.FcaError) as ei:
+            fca.fca_loglik_per_freq(ctx, 1)
+        assert ei.value.status == fca.FCA_E_STATE
+        ll, _, _ = fca.fca_em_step(ctx, 6, want_R=False, want_v=False)
+        got = fca.fca_loglik_per_freq(ctx, 4).cpu().numpy()
+        np.testing.assert_allclose(got.sum(-1).T, ll.cpu().numpy()[:, 2:], rtol=1e-13)
+        host = np.zeros((4, 2, 7))
+        assert fca.lib().fca_loglik_per_freq(ctx.handle, 4, host.ctypes.data) == fca.FCA_OK
+        np.testing.assert_array_equal(host, got)
+        for b, m in enumerate(mxs):
+            S0, v0 = oracle.default_init(m.y)
+            _, _, oll, _ = oracle.em(m.y, S0, v0, 6, threads=8)
+            np.testing.assert_allclose(got[:, b], oll[2:6], rtol=1e-10)
+        for rows in (0, 7):
+            with pytest.raises(fca.FcaError) as ei:
+                fca.fca_loglik_per_freq(ctx, rows)
+            assert ei.value.status == fca.FCA_E_ARG
+        fca.fca_set_active(ctx, 0, False)
+        fca.fca_em_step(ctx, 2, want_loglik=False, want_R=False, want_v=False)
+        got = fca.fca_loglik_per_freq(ctx, 2).cpu().numpy()
+        assert np.all(np.isnan(got[:, 0])) and np.all(np.isfinite(got[:, 1]))
+        fca.fca_set_active(ctx, 0, True)
+        ll0, _, _ = fca.fca_em_step(ctx, 0, want_R=False, want_v=False)
+        np.testing.assert_allclose(fca.fca_loglik_per_freq(ctx, 1).cpu().numpy()[0].sum(-1),
+                                   ll0.cpu().numpy()[:, 0], rtol=1e-13)
     finally:
         fca.fca_destroy(ctx)

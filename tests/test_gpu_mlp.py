@@ -1,8 +1,12 @@
 """GPU checks of the learned-initialisation network kernels against the FP64
-reference (oracle/mlp.py) on the same BF16-rounded weights. Tolerances follow
-from BF16 storage of weights and activations (8-bit significand, relative
-rounding 2^-9 per value, a few roundings per path): 2e-2 on r, 5e-2 on the
-relative norm of each gradient block."""
+reference (oracle/mlp.py) evaluated with the kernels' BF16 storage (weights,
+features, hidden activations and backward deltas rounded where the kernels
+round them). What remains is the GPU's polynomial GELU (|error| <= 2.1e-4
+per activation), FP32 accumulation, and the BF16 roundings those small
+differences flip to a neighbouring value (2^-8 relative): measured at most
+4.3e-3 on r over the widths, microphone counts and bins below (2 of 2210
+bins of the fused kernel at M = 8, H = 32 above 3e-3) and 2.0e-3 on the
+relative norm of a gradient block; the tests allow 6e-3 and 5e-3."""
 from __future__ import annotations
 
 import numpy as np
@@ -46,10 +50,9 @@ def test_forward_matches_reference(fca, M, H):
     rng = np.random.default_rng(M)
     y, fpos, r = synth.array_bins(1000, M, 513, rng)
     got = fca.fca_mlp_forward(net, y, fpos).cpu().numpy()
-    p = ref.bf16_round(fca.fca_mlp_get_params(net))
-    want, _ = ref.forward(p, ref.features(y, fpos))
-    np.testing.assert_allclose(got, want, atol=2e-2)
-    assert np.corrcoef(got, want)[0, 1] > 0.99
+    p = fca.fca_mlp_get_params(net).astype(np.float64)
+    want, _ = ref.forward(p, ref.features(y, fpos), bf16=True)
+    np.testing.assert_allclose(got, want, rtol=0, atol=6e-3)
 
 
 @pytest.mark.parametrize("H", [256, 64, 32])
@@ -59,13 +62,13 @@ def test_backward_matches_reference(fca, H):
     rng = np.random.default_rng(11)
     y, fpos, r = synth.array_bins(1024, M, 513, rng)
     loss, g = fca.fca_mlp_backward(net, y, fpos, r, want_grads=True)
-    p = ref.bf16_round(fca.fca_mlp_get_params(net))
-    want_loss, want_g = ref.loss_and_grad(p, ref.features(y, fpos), r.astype(np.float64))
-    assert abs(loss - want_loss) < 1e-2 * abs(want_loss)
+    p = fca.fca_mlp_get_params(net).astype(np.float64)
+    want_loss, want_g = ref.loss_and_grad(p, ref.features(y, fpos), r.astype(np.float64), bf16=True)
+    assert abs(loss - want_loss) < 1e-4 * abs(want_loss)
     gb, wb = blocks(g.astype(np.float64), H), blocks(want_g, H)
     for name in gb:
         err = np.linalg.norm(gb[name] - wb[name]) / max(np.linalg.norm(wb[name]), 1e-30)
-        assert err < 5e-2, (name, err)
+        assert err < 5e-3, (name, err)
     # the padded input columns of the first layer get no gradient
     W1 = gb["W1"].reshape(H, 32)
     assert np.all(W1[:, 3 * M - 1:] == 0)
@@ -178,9 +181,9 @@ def test_fused_learned_start_matches_forward_and_reference(fca, M, F, N, H):
     r_fwd = np.concatenate([fca.fca_mlp_forward(net, ybins[i:i + 4096], fpos[i:i + 4096]).cpu().numpy()
                             for i in range(0, F * N, 4096)]).astype(np.float64)
     np.testing.assert_allclose(r_gpu, np.clip(r_fwd, 1e-6, 1 - 1e-6), atol=2e-5)
-    p = ref.bf16_round(fca.fca_mlp_get_params(net))
-    want, _ = ref.forward(p, ref.features(ybins, fpos))
-    np.testing.assert_allclose(r_gpu, want, atol=2e-2)
+    p = fca.fca_mlp_get_params(net).astype(np.float64)
+    want, _ = ref.forward(p, ref.features(ybins, fpos), bf16=True)
+    np.testing.assert_allclose(r_gpu, want, rtol=0, atol=6e-3)
 
 
 @pytest.mark.parametrize("H", [32, 64, 256])
@@ -300,3 +303,42 @@ def test_run_batch_chunk_schedule(fca):
     assert list(it_a) == [7, 8] and list(it_b) == [11, 11]
     for k in range(2):
         np.testing.assert_array_equal(h_a[k], h_b[k][:len(h_a[k])])
+
+
+def test_learned_start_reaches_the_target_in_fewer_iterations(fca):
+    """What the network buys: on 8 held-out mixtures with AR(1) powers (seeds
+    apart from the training draws), a briefly trained network (600 steps)
+    with the mask-based R reaches each mixture's target in fewer EM
+    iterations on average than the plain start. Target: the log-likelihood,
+    summed over the frequencies with cond(R_true) <= 1e3, that the plain start
+    reaches after 50 iterations; reached at 99.9 % of the plain start's rise.
+    The run_batch histories are those masked sums (fca_loglik_per_freq)."""
+    from paper_1805_06572_amd import learned_init, schedule
+    M, F, N, L, K = 4, 129, 400, 50, 8
+    net, _ = learned_init.train(M=M, F=513, steps=600, batch=4096, chunk_steps=100, seed=6, hidden=32)
+    mixes = [synth.array_mixture(M, F, N, seed=3100 + k, v=synth.ar1_log_powers(np.random.default_rng(3100 + k), F, N),
+                                 complex64=True) for k in range(K)]
+    ys = [torch.from_numpy(m.y).cuda() for m in mixes]
+    w = torch.from_numpy(np.stack([(synth.condition_numbers(m.R) <= 1e3).astype(np.float64)
+                                   for m in mixes])).cuda()
+    plain = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+    try:
+        _, hist_p = schedule.run_batch(plain, L + 1, L + 1, lambda b, ll: False, weights=w)
+    finally:
+        fca.fca_destroy(plain)
+    hist_p = np.array(hist_p)                              # LL(theta^0 .. theta^L) per mixture
+    thr = hist_p[:, L] - 1e-3 * (hist_p[:, L] - hist_p[:, 0])
+    its_plain = [int(np.nonzero(h >= t)[0][0]) for h, t in zip(hist_p, thr)]
+    ctx = fca.fca_init_batch(ys, prec=fca.FCA_FP32_BULK)
+    try:
+        fca.fca_set_learned_starts(ctx, net)
+        fca.fca_set_mask_covariances(ctx, sharpen=3.0)
+        _, hist_l = schedule.run_batch(ctx, L + 1, L + 1, lambda b, ll: False, weights=w)
+    finally:
+        fca.fca_destroy(ctx)
+    its_learned = []
+    for h, t in zip(np.array(hist_l), thr):
+        hit = np.nonzero(h >= t)[0]
+        its_learned.append(int(hit[0]) if len(hit) else L + 1)
+    print(f"iterations to target: plain {np.mean(its_plain):.1f}, learned {np.mean(its_learned):.1f}")
+    assert np.mean(its_learned) < np.mean(its_plain)

@@ -64,3 +64,37 @@ def test_parameter_count_names_one_width():
         assert mlp.hidden_width(mlp.num_params(H)) == H
     with pytest.raises(ValueError):
         mlp.hidden_width(mlp.num_params(64) + 1)
+
+
+def _two_unit_net(w2_00):
+    """H = 2; inputs 3 (sin) and 4 (f/(F-1)). Pre-activations stay at or
+    beyond +-16 (GELU(x) = x, GELU(-x) = 0 to 1e-50) and every value is an
+    integer below 256 (exact in BF16) unless w2_00 is not."""
+    H = 2
+    W1 = np.zeros((H, 32))
+    W1[0, 3], W1[0, 4], W1[1, 3] = 16.0, 32.0, -16.0
+    b1 = np.array([0.0, 0.0])
+    W2 = np.array([[w2_00, 0.0], [1.0, 0.0]])
+    b2 = np.array([0.0, -64.0])
+    W3 = np.array([[1.0, 0.0], [-1.0, 0.0]])
+    b3 = np.array([0.0, 0.0])
+    w4, b4 = np.array([0.125, 0.0]), np.array([-4.0])
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3.ravel(), b3, w4, b4])
+
+
+def test_bf16_storage_reading():
+    """bf16=True rounds the weight matrices and hidden values the kernels
+    store in BF16: with every value exact in BF16 it equals the FP64 path;
+    a weight 1 + 2^-10 (between two BF16 neighbours of 1) acts as 1."""
+    y = np.array([[1.0, 1j]])                     # sin = 1
+    X = mlp.features(y, np.array([0.5]))          # f/(F-1) = 1/2
+    # layer 1: 16 + 16 = 32 and -16; layer 2: 32 w and 32 - 64 = -32; layer 3: 32 w, -32 w; z = 4 w - 4
+    r_exact, (pres, _, z) = mlp.forward(_two_unit_net(1.0), X)
+    r_b, (_, _, zb) = mlp.forward(_two_unit_net(1.0), X, bf16=True)
+    np.testing.assert_allclose(pres[0][0], [32.0, -16.0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(z, [0.0], atol=1e-12)
+    np.testing.assert_allclose(zb, z, atol=1e-12)
+    _, (_, _, z_off) = mlp.forward(_two_unit_net(1.0 + 2.0 ** -10), X)
+    _, (_, _, z_off_b) = mlp.forward(_two_unit_net(1.0 + 2.0 ** -10), X, bf16=True)
+    np.testing.assert_allclose(z_off, [4.0 * 2.0 ** -10], atol=1e-12)
+    np.testing.assert_allclose(z_off_b, [0.0], atol=1e-12)
