@@ -50,12 +50,12 @@ def _default_R(M, F):
 
 
 @pytest.mark.parametrize("prec,shapes,p", [
-    ("fp32", [(4, 300), (2, 1), (8, 257), (4, 1000)], 3.0),
-    ("fp64", [(4, 300), (2, 1), (8, 257), (4, 1000)], 3.0),
+    ("fp32", [(4, 300), (2, 1), (8, 257), (4, 1000), (1, 50)], 3.0),
+    ("fp64", [(1, 40), (4, 300), (2, 1), (8, 257), (4, 1000)], 3.0),
     ("fp32", [(4, 300), (4, 77), (4, 1), (2, 40), (2, 513), (8, 90)], 2.5),
     ("fp64", [(3, 64), (3, 65), (5, 200), (6, 31), (7, 10)], 1.0)])
 def test_mask_start_matches_oracle(fca, prec, shapes, p):
-    """Mixtures of M = 2..8 with uneven N (ragged against the 64-frame
+    """Mixtures of M = 1..8 with uneven N (ragged against the 64-frame
     workgroup, single-frame mixtures), runs of equal M (one decomposition
     launch each) and a silent frequency; integer, fractional and no
     sharpening; the masks come from seeded powers given as v0."""
@@ -117,6 +117,10 @@ def test_mask_start_argument_errors(fca):
             with pytest.raises(fca.FcaError) as e:
                 fca.fca_set_mask_covariances(ctx, **kw)
             assert e.value.status == fca.FCA_E_ARG
+        # the plain start's equal powers would give R1 = R2 (a fixed point of the EM)
+        with pytest.raises(fca.FcaError, match="equal powers") as e:
+            fca.fca_set_mask_covariances(ctx)
+        assert e.value.status == fca.FCA_E_ARG
         L = fca.lib()
         assert L.fca_set_mask_covariances(ctx.handle, 0, None, 3.0, 1e-3) == fca.FCA_E_ARG
         assert L.fca_set_mask_covariances(None, 1, None, 3.0, 1e-3) == fca.FCA_E_ARG
