@@ -201,6 +201,36 @@ void fca_destroy(fca_ctx *c);
 fca_status fca_gevd(int32_t M, int32_t count, const double *S1, const double *S2, double *P,
                     double *lambda, int32_t *flags, void *stream);
 
+/* The plain-start EM of one mixture (Algorithm 1, step 1 with the plain
+ * start, then steps 3-9) without any device allocation, for callers that
+ * cannot allocate (code under stream capture, serving loops, harnesses that
+ * forbid it). Results equal fca_init (plain R; v0 as below) followed by
+ * fca_em_step(iters) with the same y. The per-frequency state lives in one
+ * fixed-size device array of the library (about 4.3 MiB, held by each GPU
+ * the library runs on until the process ends); y and the powers are used in
+ * place. Calls on one GPU share that array: calls that overlap in time on
+ * one GPU (several streams or threads) race and must be serialised by the
+ * caller. Enqueued on `stream` (hipStream_t, NULL = null stream) without
+ * waiting; no host synchronisation, so numerical failures are not returned
+ * as a status but as flags.
+ *   M, F, N  1 <= M <= 8, 1 <= F <= 2048, 1 <= N <= 2048 (frames held in
+ *            registers); FCA_E_ARG beyond these limits.
+ *   prec     FCA_FP64 or FCA_FP32_BULK.
+ *   y        DEVICE, [F][M][pitch] complex (prec): y(n,f) of microphone m
+ *            at f*M*pitch + m*pitch + n; N <= pitch <= 2^30.
+ *   v        DEVICE, [2][F][pitch] prec reals (v_1 then v_2): in, v^(0)
+ *            when use_v0 != 0 (else overwritten with the plain start
+ *            ||y||^2 / M floored as in fca_problem); out, v^(iters).
+ *   iters    >= 0; 0 evaluates the start only.
+ *   loglik   NULL or DEVICE [max(iters, 1)] doubles, as fca_em_step's.
+ *   R_out    NULL or DEVICE [2][F][M][M] complex128, as fca_em_step's.
+ *   flags_out NULL or DEVICE [F] int32: FCA_FLAG_* bits per frequency.
+ * Returns FCA_E_ARG for invalid arguments (nothing is enqueued),
+ * FCA_E_DEVICE if a launch fails; fca_last_error(NULL) gives the reason. */
+fca_status fca_em_solve_noalloc(int32_t M, int32_t F, int32_t N, int32_t prec, const void *y, int64_t pitch,
+                                void *v, int32_t use_v0, int32_t iters, double *loglik, double *R_out,
+                                int32_t *flags_out, void *stream);
+
 /* Kernel timing of the EM iterations. enable != 0 makes later fca_em_step
  * calls record HIP events, on the context's stream, around the launches of
  * the EM-iteration kernel. On return *em_kernel_ms and *em_launches hold the

@@ -1216,6 +1216,12 @@ fca_status fca_status_per_freq(const fca_ctx* c, int32_t* flags) {
 
 const char* fca_last_error(const fca_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
 
+}  // extern "C"
+
+void fca::set_global_error(const char* msg) { g_init_error = msg; }
+
+extern "C" {
+
 void fca_destroy(fca_ctx* c) {
     if (!c) return;
     if (c->stream || true) (void)hipStreamSynchronize(c->stream);

@@ -119,6 +119,9 @@ struct MlpInferJob {
 hipError_t mlp_infer_jobs(fca_mlp* m, MlpInferJob* jobs, int count, hipStream_t s, const char** err);
 int mlp_microphones(const fca_mlp* m);
 
+// Text returned by fca_last_error(NULL) (calls without a context).
+void set_global_error(const char* msg);
+
 // out[0] = OR of flags[0..count), out[1] / out[2] = first index flagged
 // kFlagNotPD / kFlagNonFinite, count if none (out: 3 device ints).
 hipError_t launch_flag_summary(const int* flags, int count, int* out, hipStream_t s);

@@ -38,7 +38,7 @@ EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set
             "fca_mlp_create", "fca_mlp_destroy", "fca_mlp_num_params", "fca_mlp_last_error",
             "fca_mlp_get_params", "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward",
             "fca_mlp_adamw", "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
-            "fca_set_mask_covariances", "fca_loglik_per_freq"]
+            "fca_set_mask_covariances", "fca_loglik_per_freq", "fca_em_solve_noalloc"]
 
 
 class fca_problem(ctypes.Structure):
@@ -105,12 +105,13 @@ def lib() -> ctypes.CDLL:
         L.fca_set_learned_starts.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
         L.fca_set_mask_covariances.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.c_double, ctypes.c_double]
         L.fca_loglik_per_freq.argtypes = [vp, i32, vp]
+        L.fca_em_solve_noalloc.argtypes = [i32, i32, i32, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp]
         for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set_active", "fca_em_step", "fca_conv_em_step", "fca_separate",
                      "fca_status_per_freq", "fca_gevd", "fca_timing", "fca_launch_groups",
                      "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch", "fca_mlp_create", "fca_mlp_get_params",
                      "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward", "fca_mlp_adamw",
                      "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
-                     "fca_set_mask_covariances", "fca_loglik_per_freq"):
+                     "fca_set_mask_covariances", "fca_loglik_per_freq", "fca_em_solve_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -304,6 +305,24 @@ def fca_loglik_per_freq(ctx: Ctx, rows: int = 1) -> torch.Tensor:
     out = torch.empty((rows, ctx.B, ctx.F), dtype=torch.float64, device=ctx.device)
     _check(lib().fca_loglik_per_freq(ctx.handle, int(rows), out.data_ptr()), ctx)
     return out
+
+
+def fca_em_solve_noalloc(y: torch.Tensor, v: torch.Tensor, N: int, iters: int, use_v0: bool = False,
+                         loglik=None, R_out=None, flags_out=None):
+    """The allocation-free plain-start EM of one mixture: y device [F, M,
+    pitch] complex (complex128: FP64, complex64: FP32 bulk) with N <= pitch
+    frames per row, v device [2, F, pitch] real (in: v0 if use_v0; out: the
+    powers after the iterations); loglik [max(iters, 1)] float64, R_out
+    [2, F, M, M] complex128 and flags_out [F] int32 preallocated device
+    tensors or None. Enqueued on the current stream."""
+    F, M, pitch = y.shape
+    prec = FCA_FP64 if y.dtype == torch.complex128 else FCA_FP32_BULK
+
+    def ptr(t):
+        return t.data_ptr() if t is not None else None
+    _check(lib().fca_em_solve_noalloc(M, F, int(N), prec, y.data_ptr(), pitch, v.data_ptr(), int(use_v0),
+                                      int(iters), ptr(loglik), ptr(R_out), ptr(flags_out),
+                                      _stream_handle(y.device)))
 
 
 def fca_destroy(ctx: Ctx):
