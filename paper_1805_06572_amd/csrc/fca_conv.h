@@ -38,7 +38,8 @@ template <int M, typename T> struct ConvShared {
     int flag, bad;
     double fin[NV];
     T red[kEmThreads * (CH + 1)];
-    double red2[G * CH];
+    double wh[NW][64];
+    double wp[NW][NV];
     double LL[NW];
     double2 Id[MM], Pn[MM];
     double lamN[M];
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(kEmThreads) void conv_em_kernel(
                            acc, llacc, v1n[k], v2n[k], bad);
         }
         if (bad) sh.bad = 1;
-        wg_reduce_sums<M>(sh, acc, llacc, nf, tid);
+        wg_reduce_sums<M>(sh, acc, llacc, nf, tid, nullptr);
         if (tid == 0) {
             double tot = 0.0;
             for (int w = 0; w < NW; ++w) tot += sh.LL[w];

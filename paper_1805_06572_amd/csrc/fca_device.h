@@ -137,58 +137,91 @@ template <> struct Math<double> {
     static __device__ __forceinline__ double log(double x) { return ::log(x); }
 };
 
+// Orders the LDS accesses of one wavefront: a wave executes its LDS
+// instructions in issue order, so after this point every lane sees what the
+// other lanes of the same wave stored before it. Also a compiler barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Workgroup sums of the per-thread accumulators (FP64 across threads, fixed
 // order) into S~_j = sums / N as full Hermitian matrices in sh.S, and of the
 // per-thread log-likelihood terms into sh.LL (one value per wave). The
 // accumulator layout per source j (offset j M^2): diagonal i at i, the
 // off-diagonal pair (i < k) at M + 2 pair_index(M, i, k) (+1 imaginary).
-// Sh provides red, red2, fin, LL, S and the constants NTH (threads), CH,
-// NCH, G, NV.
+// With lam1 != NULL the sums of source 1 are scaled to entry (i, k) times
+// lam1[i] lam1[k] (off the diagonal) or lam1[i] (on it).
+// Each wave first sums its own 64 rows (no workgroup barrier: a wave starts
+// as soon as its own frames are done), in chunks of CH values: lane (h, c)
+// adds rows h, h + H, ... of column c (H = 64 / CH lanes per column, four
+// interleaved partial sums), then the H partials of a column. One workgroup
+// barrier, then wave 0 adds the per-wave sums (in wave order) and assembles
+// S: on return sh.S and sh.LL are complete for wave 0 only (the caller's
+// next workgroup barrier publishes them).
+// Sh provides red, wh, wp, fin, LL, S and the constants CH, NCH, NV, NW.
 template <int M, typename Sh, typename T>
-__device__ __forceinline__ void wg_reduce_sums(Sh& sh, const T (&acc)[2 * M * M], double llacc, int nf, int tid) {
-    constexpr int MM = M * M, NV = Sh::NV, CH = Sh::CH, NCH = Sh::NCH, G = Sh::G;
-    constexpr int NT = Sh::NTH;
+__device__ __forceinline__ void wg_reduce_sums(Sh& sh, const T (&acc)[2 * M * M], double llacc, int nf, int tid,
+                                               const double* lam1) {
+    constexpr int MM = M * M, NV = Sh::NV, CH = Sh::CH, NCH = Sh::NCH, NW = Sh::NW;
+    constexpr int H = 64 / CH;
+    const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) llacc += __shfl_xor(llacc, off, 64);
-    if ((tid & 63) == 0) sh.LL[tid >> 6] = llacc;
+    if (lane == 0) sh.LL[w] = llacc;
+    T* __restrict__ red = sh.red + w * 64 * (CH + 1);
+    const int c = lane % CH, h = lane / CH;
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
 #pragma unroll
-        for (int c = 0; c < CH; ++c)
-            if (ch * CH + c < NV) sh.red[tid * (CH + 1) + c] = acc[ch * CH + c];
-        __syncthreads();
-        for (int task = tid; task < CH * G; task += NT) {
-            const int c = task % CH, g = task / CH;
-            double s = 0.0;
-#pragma unroll 8
-            for (int rr = 0; rr < 32; ++rr) s += (double)sh.red[(g * 32 + rr) * (CH + 1) + c];
-            sh.red2[g * CH + c] = s;
-        }
-        __syncthreads();
-        if (tid < CH && ch * CH + tid < NV) {
-            double s = 0.0;
+        for (int q = 0; q < CH; ++q)
+            if (ch * CH + q < NV) red[lane * (CH + 1) + q] = acc[ch * CH + q];
+        wave_lds_sync();
+        if (h < H) {
+            double p[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int g = 0; g < G; ++g) s += sh.red2[g * CH + tid];
-            sh.fin[ch * CH + tid] = s;
+            for (int k = 0; k * H < 64; ++k) {
+                const int r = h + k * H;
+                if (r < 64) p[k & 3] += (double)red[r * (CH + 1) + c];
+            }
+            sh.wh[w][h * CH + c] = (p[0] + p[1]) + (p[2] + p[3]);
         }
-        __syncthreads();
+        wave_lds_sync();
+        if (lane < CH && ch * CH + lane < NV) {
+            double sum = 0.0;
+#pragma unroll
+            for (int hh = 0; hh < H; ++hh) sum += sh.wh[w][hh * CH + lane];
+            sh.wp[w][ch * CH + lane] = sum;
+        }
+        wave_lds_sync();
     }
-    if (tid < NV) {
-        const int j = tid / MM, ent = tid % MM, i = ent / M, q = ent % M;
-        const double invn = 1.0 / (double)nf;
+    __syncthreads();
+    if (w != 0) return;
+    for (int e = lane; e < NV; e += 64) {
+        double sum = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) sum += sh.wp[ww][e];
+        sh.fin[e] = sum;
+    }
+    wave_lds_sync();
+    for (int t = lane; t < NV; t += 64) {
+        const int j = t / MM, ent = t % MM, i = ent / M, q = ent % M;
+        double sc = 1.0 / (double)nf;
+        if (lam1 && j == 0) sc *= (i == q) ? lam1[i] : lam1[i] * lam1[q];
         const double* f = sh.fin + j * MM;
         double2 val;
-        if (i == q) val = make_double2(f[i] * invn, 0.0);
+        if (i == q) val = make_double2(f[i] * sc, 0.0);
         else if (i < q) {
             const int o = M + 2 * pair_index(M, i, q);
-            val = make_double2(f[o] * invn, f[o + 1] * invn);
+            val = make_double2(f[o] * sc, f[o + 1] * sc);
         } else {
             const int o = M + 2 * pair_index(M, q, i);
-            val = make_double2(f[o] * invn, -f[o + 1] * invn);
+            val = make_double2(f[o] * sc, -f[o + 1] * sc);
         }
         sh.S[j][ent] = val;
     }
-    __syncthreads();
+    wave_lds_sync();
 }
 
 // ---------------------------------------------------------------- FP64 helpers
@@ -217,15 +250,6 @@ __device__ __forceinline__ double rcp_nr1(double x) {
 __device__ __forceinline__ double rsqrt_nr1(double x) {
     double r = __builtin_amdgcn_rsq(x);
     return r * fma(-0.5 * x * r, r, 1.5);
-}
-
-// Orders the LDS accesses of one wavefront: a wave executes its LDS
-// instructions in issue order, so after this point every lane sees what the
-// other lanes of the same wave stored before it. Also a compiler barrier.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------- GEVD (FP64)

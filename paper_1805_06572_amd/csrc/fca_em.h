@@ -52,7 +52,8 @@ template <int M, typename T, int NT_ = kEmThreads> struct EmShared {
     double2 S[2][MM];   // S~1, S~2 (full Hermitian, FP64)
     double fin[NV];
     T red[NT_ * (CH + 1)];
-    double red2[G * CH];
+    double wh[NW][64];  // per-wave partial column sums
+    double wp[NW][NV];  // per-wave sums
     double LL[NW];
     GevdScratch ws;
 };
@@ -100,17 +101,20 @@ __device__ __forceinline__ void em_prepare(Sh& sh, int tid) {
 //   mu~1_i = v1 lam_i y~_i / d_i, mu~2_i = v2 y~_i / d_i          eq. (MMSEtilde)
 //   c_i = v1 v2 lam_i / d_i  (diagonal of Phi~_j - mu~_j mu~_j^H)  eq. (updatePhitildeeff)
 //   v1' = tr(Lambda^-1 Phi~1)/M, v2' = tr(Phi~2)/M                  eq. (updateveff)
-//   Phi~_j / v_j' = u_j u_j^H + diag(c) / v_j', u_j = mu~_j / sqrt(v_j')
-//                                                                  eq. (updateStildeeff)
+//       = (v1/M) sum_i t1_i,  v2' = (v2/M) sum_i t2_i  with
+//         t1_i = r_i (v1 lam_i e_i r_i + v2), t2_i = r_i (v2 e_i r_i + v1 lam_i),
+//         e_i = |y~_i|^2, r_i = 1 / d_i
+//   Phi~_j / v_j'  (eq. updateStildeeff), summed over the frames
 //   llacc += -sum_i log d_i - sum_i |y~_i|^2 / d_i   (log-likelihood of theta^(l))
 // `ok` masks padding frames (no contribution, powers unchanged).
-// em_bin_front: everything up to u_j; leaves y~ (ytr, yti), e_i = |y~_i|^2,
-// r_i = 1 / d_i and w_j = 1 / sqrt(v_j') (0 for padding).
+// em_bin_front: everything up to the new powers; leaves y~ (ytr, yti), e_i,
+// r_i, t1_i, t2_i and the new powers nv1, nv2 (also in nv1o, nv2o unless
+// padding).
 template <int M, typename T>
 __device__ __forceinline__ void em_bin_front(const T (&yr)[M], const T (&yi)[M], T a1, T a2, const T (&lm)[M],
                                              const typename Vec2<T>::type* Pt, bool ok, double& llacc, T& nv1o,
                                              T& nv2o, bool& bad, T (&ytr)[M], T (&yti)[M], T (&e)[M], T (&r)[M],
-                                             T& w1, T& w2) {
+                                             T (&t1)[M], T (&t2)[M], T& nv1, T& nv2) {
     using T2 = typename Vec2<T>::type;
     using MT = Math<T>;
 #pragma unroll
@@ -152,16 +156,18 @@ __device__ __forceinline__ void em_bin_front(const T (&yr)[M], const T (&yi)[M],
             logd += MT::log(pd);
         }
     }
-    // v1' = (v1/M) sum r_i (v1 lam_i e_i r_i + v2), v2' = (v2/M) sum r_i (v2 e_i r_i + v1 lam_i)
     T s1 = T(0), s2 = T(0);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         const T er = e[i] * r[i];
-        s1 = fma(r[i], fma(a1 * lm[i], er, a2), s1);
-        s2 = fma(r[i], fma(a2, er, a1 * lm[i]), s2);
+        const T a1l = a1 * lm[i];
+        t1[i] = r[i] * fma(a1l, er, a2);
+        t2[i] = r[i] * fma(a2, er, a1l);
+        s1 += t1[i];
+        s2 += t2[i];
     }
-    T nv1 = a1 * s1 * (T(1) / T(M));
-    T nv2 = a2 * s2 * (T(1) / T(M));
+    nv1 = a1 * s1 * (T(1) / T(M));
+    nv2 = a2 * s2 * (T(1) / T(M));
     if (ok) {
         llacc += (double)(-logd - quad);
         bad = bad || !(nv1 > T(0)) || !(nv2 > T(0)) || !isfinite(nv1) || !isfinite(nv2);
@@ -176,44 +182,47 @@ __device__ __forceinline__ void em_bin_front(const T (&yr)[M], const T (&yi)[M],
         nv1o = nv1;
         nv2o = nv2;
     }
-    w1 = ok ? MT::rsqrt(nv1) : T(0);
-    w2 = ok ? MT::rsqrt(nv2) : T(0);
 }
 
-// The bin with the sums of Phi~_j / v_j' kept per thread: the diagonal of
-// source j at acc[j M^2 + i], the upper-triangle pair (i < k) at
-// acc[j M^2 + M + 2 pair_index(M, i, k)] (+1 imaginary).
+// The bin with the sums of Phi~_j / v_j' kept per thread. With
+// z_i = r_i y~_i, k_j = v_j / v_j', alpha = v1 k_1, beta = v2 k_2:
+//   (Phi~1 / v1')_ik = lam_i lam_k alpha z_i conj(z_k)    (i != k)
+//   (Phi~1 / v1')_ii = lam_i k_1 t1_i
+//   (Phi~2 / v2')_ik = beta z_i conj(z_k),   (Phi~2 / v2')_ii = k_2 t2_i
+// so the per-thread sums leave out the lam factors of source 1 (constant
+// per frequency; applied to the workgroup totals, wg_reduce_sums). Layout:
+// the diagonal of source j at acc[j M^2 + i], the upper-triangle pair (i < k)
+// at acc[j M^2 + M + 2 pair_index(M, i, k)] (+1 imaginary).
 template <int M, typename T>
 __device__ __forceinline__ void em_bin(const T (&yr)[M], const T (&yi)[M], T a1, T a2, const T (&lm)[M],
                                        const typename Vec2<T>::type* Pt, bool ok, T (&acc)[2 * M * M],
                                        double& llacc, T& nv1o, T& nv2o, bool& bad) {
+    using MT = Math<T>;
     constexpr int MM = M * M;
-    T ytr[M], yti[M], e[M], r[M], w1, w2;
-    em_bin_front<M, T>(yr, yi, a1, a2, lm, Pt, ok, llacc, nv1o, nv2o, bad, ytr, yti, e, r, w1, w2);
-    const T iv1 = w1 * w1, iv2 = w2 * w2;
-    T u1r[M], u1i[M], u2r[M], u2i[M];
+    T ytr[M], yti[M], e[M], r[M], t1[M], t2[M], nv1, nv2;
+    em_bin_front<M, T>(yr, yi, a1, a2, lm, Pt, ok, llacc, nv1o, nv2o, bad, ytr, yti, e, r, t1, t2, nv1, nv2);
+    const T k1 = ok ? a1 * MT::rcp(nv1) : T(0);
+    const T k2 = ok ? a2 * MT::rcp(nv2) : T(0);
+    const T al = k1 * a1, be = k2 * a2;
+    T zr[M], zi[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        const T g1 = a1 * lm[i] * r[i];
-        const T g2 = a2 * r[i];
-        const T c = g1 * a2;
-        const T s1i = g1 * w1, s2i = g2 * w2;
-        u1r[i] = s1i * ytr[i];
-        u1i[i] = s1i * yti[i];
-        u2r[i] = s2i * ytr[i];
-        u2i[i] = s2i * yti[i];
-        acc[i] = fma(s1i * s1i, e[i], fma(c, iv1, acc[i]));
-        acc[MM + i] = fma(s2i * s2i, e[i], fma(c, iv2, acc[MM + i]));
+        zr[i] = r[i] * ytr[i];
+        zi[i] = r[i] * yti[i];
+        acc[i] = fma(k1, t1[i], acc[i]);
+        acc[MM + i] = fma(k2, t2[i], acc[MM + i]);
     }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
 #pragma unroll
         for (int q = i + 1; q < M; ++q) {
             const int o = M + 2 * pair_index(M, i, q);
-            acc[o] = fma(u1r[i], u1r[q], fma(u1i[i], u1i[q], acc[o]));
-            acc[o + 1] = fma(u1i[i], u1r[q], fma(-u1r[i], u1i[q], acc[o + 1]));
-            acc[MM + o] = fma(u2r[i], u2r[q], fma(u2i[i], u2i[q], acc[MM + o]));
-            acc[MM + o + 1] = fma(u2i[i], u2r[q], fma(-u2r[i], u2i[q], acc[MM + o + 1]));
+            const T pr = fma(zr[i], zr[q], zi[i] * zi[q]);
+            const T pi = fma(zi[i], zr[q], -zr[i] * zi[q]);
+            acc[o] = fma(al, pr, acc[o]);
+            acc[o + 1] = fma(al, pi, acc[o + 1]);
+            acc[MM + o] = fma(be, pr, acc[MM + o]);
+            acc[MM + o + 1] = fma(be, pi, acc[MM + o + 1]);
         }
     }
 }
@@ -290,8 +299,10 @@ __device__ __forceinline__ void em_bin_mf(const float (&yr)[M], const float (&yi
                                           const float (&lm)[M], const float2* Pt, bool ok, double& llacc,
                                           float& nv1o, float& nv2o, bool& bad, float* __restrict__ stg,
                                           float (&cd)[2 * M], f32x4 (&am)[2], int lane) {
-    float ytr[M], yti[M], e[M], r[M], w1, w2;
-    em_bin_front<M, float>(yr, yi, a1, a2, lm, Pt, ok, llacc, nv1o, nv2o, bad, ytr, yti, e, r, w1, w2);
+    float ytr[M], yti[M], e[M], r[M], t1[M], t2[M], nv1, nv2;
+    em_bin_front<M, float>(yr, yi, a1, a2, lm, Pt, ok, llacc, nv1o, nv2o, bad, ytr, yti, e, r, t1, t2, nv1, nv2);
+    const float w1 = ok ? __builtin_amdgcn_rsqf(nv1) : 0.0f;
+    const float w2 = ok ? __builtin_amdgcn_rsqf(nv2) : 0.0f;
     const float iv1 = w1 * w1, iv2 = w2 * w2;
     float* __restrict__ c1 = stg + (lane & 3) * 16 + (lane >> 2);
     float* __restrict__ c2 = c1 + kStgSrc;
@@ -444,7 +455,7 @@ __device__ __forceinline__ bool em_finish(EmShared<M, T, NT_>& sh, const T (&acc
                                           double* __restrict__ ll, int64_t ll_stride, int pid, double eps2,
                                           int tid) {
     if (bad) sh.bad = 1;
-    wg_reduce_sums<M>(sh, acc, llacc, nf, tid);
+    wg_reduce_sums<M>(sh, acc, llacc, nf, tid, sh.lam);
     return em_update<M>(sh, it, iters, it_base, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid);
 }
 
