@@ -239,6 +239,31 @@ fca_status fca_em_solve_noalloc(int32_t M, int32_t F, int32_t N, int32_t prec, c
 fca_status fca_timing(fca_ctx *c, int32_t enable, double *em_kernel_ms, int64_t *em_launches);
 
 /* ------------------------------------------------------------------
+ * STFT front and back end (the analysis and resynthesis around the EM in
+ * the experiments of Section 4; Table 1: 16 kHz, frames of 1024 samples,
+ * frame shift 512, square-root Hann window). Frame length L (a power of two,
+ * 16 <= L <= 4096), shift S = L/2, window w(t) = sin(pi t / L), the square
+ * root of the periodic Hann window. Frame n holds samples n S - S + t,
+ * t = 0 .. L-1 (zero outside 0 .. T-1); N = fca_stft_frames(T, L) =
+ * floor((T - 1) / S) + 2 frames, so every sample lies in two frames and,
+ * since w(t)^2 + w(t + S)^2 = 1, fca_istft(fca_stft(x)) = x up to rounding.
+ * Both run in the precision prec (real float/complex64 or double/
+ * complex128), take DEVICE pointers only, are enqueued on `stream`
+ * (hipStream_t, NULL = null stream) without waiting and allocate nothing;
+ * FCA_E_ARG (nothing enqueued, reason in fca_last_error(NULL)) for invalid
+ * sizes or host pointers.
+ * ------------------------------------------------------------------ */
+int64_t fca_stft_frames(int64_t T, int32_t L);   /* 0 for T < 1 */
+/* x: [M][T] real signals. X: [F][N][M] complex, F = L/2 + 1:
+ * X[f][n][m] = sum_t w(t) x_m(n S - S + t) exp(-2 pi i f t / L), the layout
+ * fca_problem.y takes (y_stride_f = N M, y_stride_n = M, y_stride_m = 1). */
+fca_status fca_stft(int32_t M, int64_t T, int32_t L, int32_t prec, const void *x, void *X, void *stream);
+/* X: [F][N][M] complex (e.g. one source image of fca_separate's output).
+ * x: [M][T] real: the overlap-add of each frame's inverse DFT over the
+ * Hermitian extension X[L - k] = conj(X[k]) (real part), windowed by w. */
+fca_status fca_istft(int32_t M, int64_t T, int32_t L, int32_t prec, const void *X, void *x, void *stream);
+
+/* ------------------------------------------------------------------
  * Orchestration of batched runs: launch shapes, autotuning, captured steps.
  * The problems of a context are launched in groups of equal M and frames-
  * per-thread class (one launch per group and chunk of iterations; the groups

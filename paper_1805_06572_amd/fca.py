@@ -38,7 +38,8 @@ EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set
             "fca_mlp_create", "fca_mlp_destroy", "fca_mlp_num_params", "fca_mlp_last_error",
             "fca_mlp_get_params", "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward",
             "fca_mlp_adamw", "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
-            "fca_set_mask_covariances", "fca_loglik_per_freq", "fca_em_solve_noalloc"]
+            "fca_set_mask_covariances", "fca_loglik_per_freq", "fca_em_solve_noalloc", "fca_stft", "fca_istft",
+            "fca_stft_frames"]
 
 
 class fca_problem(ctypes.Structure):
@@ -106,12 +107,17 @@ def lib() -> ctypes.CDLL:
         L.fca_set_mask_covariances.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.c_double, ctypes.c_double]
         L.fca_loglik_per_freq.argtypes = [vp, i32, vp]
         L.fca_em_solve_noalloc.argtypes = [i32, i32, i32, i32, vp, i64, vp, i32, i32, vp, vp, vp, vp]
+        L.fca_stft_frames.argtypes = [i64, i32]
+        L.fca_stft_frames.restype = i64
+        L.fca_stft.argtypes = [i32, i64, i32, i32, vp, vp, vp]
+        L.fca_istft.argtypes = [i32, i64, i32, i32, vp, vp, vp]
         for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set_active", "fca_em_step", "fca_conv_em_step", "fca_separate",
                      "fca_status_per_freq", "fca_gevd", "fca_timing", "fca_launch_groups",
                      "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch", "fca_mlp_create", "fca_mlp_get_params",
                      "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward", "fca_mlp_adamw",
                      "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
-                     "fca_set_mask_covariances", "fca_loglik_per_freq", "fca_em_solve_noalloc"):
+                     "fca_set_mask_covariances", "fca_loglik_per_freq", "fca_em_solve_noalloc", "fca_stft",
+                     "fca_istft"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -323,6 +329,33 @@ def fca_em_solve_noalloc(y: torch.Tensor, v: torch.Tensor, N: int, iters: int, u
     _check(lib().fca_em_solve_noalloc(M, F, int(N), prec, y.data_ptr(), pitch, v.data_ptr(), int(use_v0),
                                       int(iters), ptr(loglik), ptr(R_out), ptr(flags_out),
                                       _stream_handle(y.device)))
+
+
+def fca_stft_frames(T: int, L: int = 1024) -> int:
+    return int(lib().fca_stft_frames(int(T), int(L)))
+
+
+def fca_stft(x: torch.Tensor, L: int = 1024) -> torch.Tensor:
+    """STFT of real device signals x [M, T] (float32: complex64 out, float64:
+    complex128 out) -> X [F, N, M] (F = L/2 + 1), the EM's mixture layout."""
+    M, T = x.shape
+    x = x.contiguous()
+    prec = FCA_FP64 if x.dtype == torch.float64 else FCA_FP32_BULK
+    cdt = torch.complex128 if prec == FCA_FP64 else torch.complex64
+    X = torch.empty((L // 2 + 1, fca_stft_frames(T, L), M), dtype=cdt, device=x.device)
+    _check(lib().fca_stft(M, T, L, prec, x.data_ptr(), X.data_ptr(), _stream_handle(x.device)))
+    return X
+
+
+def fca_istft(X: torch.Tensor, T: int, L: int = 1024) -> torch.Tensor:
+    """Overlap-add synthesis of device spectra X [F, N, M] -> x [M, T] real."""
+    F, N, M = X.shape
+    X = X.contiguous()
+    prec = FCA_FP64 if X.dtype == torch.complex128 else FCA_FP32_BULK
+    rdt = torch.float64 if prec == FCA_FP64 else torch.float32
+    x = torch.empty((M, T), dtype=rdt, device=X.device)
+    _check(lib().fca_istft(M, T, L, prec, X.data_ptr(), x.data_ptr(), _stream_handle(X.device)))
+    return x
 
 
 def fca_destroy(ctx: Ctx):

@@ -1,0 +1,126 @@
+"""GPU STFT analysis and synthesis (fca_stft, fca_istft) against the FP64
+oracle written from the definitions (oracle/stft.py), perfect
+reconstruction, argument checks, and an end-to-end separation of a
+synthetic convolutive mixture: STFT, FastFCA EM, MMSE images, overlap-add
+synthesis, with the time-domain SNR of each source image against the input.
+Tolerances: relative to the largest magnitude, 1e-12 in FP64 and 1e-5 in
+FP32 (FFT rounding grows with log2 L; measured below 2e-6 in FP32)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import stft as ostft
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def fca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_06572_amd import fca as mod
+    mod.lib()
+    return mod
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("prec,L,M,T", [
+    ("fp64", 1024, 2, 5000), ("fp32", 1024, 2, 5000),
+    ("fp64", 16, 3, 1), ("fp32", 16, 1, 7),          # shorter than a frame
+    ("fp32", 256, 4, 999), ("fp64", 4096, 1, 9000),  # largest frame (FP64: 112 KB of LDS)
+    ("fp32", 4096, 2, 4097),
+])
+def test_stft_and_istft_match_oracle(fca, prec, L, M, T):
+    rng = np.random.default_rng(L + M + T)
+    x = rng.standard_normal((M, T))
+    dt, tol = (torch.float64, 1e-12) if prec == "fp64" else (torch.float32, 1e-5)
+    xd = torch.from_numpy(x).to(DEV, dt)
+    X = fca.fca_stft(xd, L)
+    want = ostft.stft(xd.double().cpu().numpy(), L)
+    assert X.shape == want.shape == (L // 2 + 1, fca.fca_stft_frames(T, L), M)
+    assert rel(X.cpu().numpy(), want) < tol
+    # synthesis of an arbitrary spectrum (complex DC and Nyquist bins too)
+    Z = rng.standard_normal(want.shape) + 1j * rng.standard_normal(want.shape)
+    Zd = torch.from_numpy(Z).to(DEV, torch.complex128 if prec == "fp64" else torch.complex64)
+    z = fca.fca_istft(Zd, T, L)
+    assert rel(z.cpu().numpy(), ostft.istft(Zd.cpu().numpy(), T, L)) < tol
+    # perfect reconstruction
+    back = fca.fca_istft(X, T, L).cpu().numpy()
+    np.testing.assert_allclose(back, xd.cpu().numpy(), rtol=0, atol=tol * np.abs(x).max() * 10)
+
+
+def test_stft_argument_errors(fca):
+    L = fca.lib()
+    x = torch.zeros((2, 100), dtype=torch.float32, device=DEV)
+    X = torch.zeros((513, 4, 2), dtype=torch.complex64, device=DEV)
+    for (M, T, Lf) in ((2, 100, 1000), (2, 100, 8), (2, 100, 8192), (0, 100, 64), (2, 0, 64)):
+        assert L.fca_stft(M, T, Lf, fca.FCA_FP32_BULK, x.data_ptr(), X.data_ptr(), None) == fca.FCA_E_ARG
+        assert L.fca_istft(M, T, Lf, fca.FCA_FP32_BULK, X.data_ptr(), x.data_ptr(), None) == fca.FCA_E_ARG
+    xh = np.zeros((2, 100), np.float32)
+    assert L.fca_stft(2, 100, 64, fca.FCA_FP32_BULK, xh.ctypes.data, X.data_ptr(), None) == fca.FCA_E_ARG
+    assert "device" in fca.fca_last_error()
+    assert fca.fca_stft_frames(0, 1024) == 0 and fca.fca_stft_frames(128000, 1024) == 251
+
+
+# ------------------------------------------------------------------ end to end
+def convolutive_mixture(rng, T, M, fs=16000):
+    """Two sources with speech-like power fluctuation (white noise shaped by
+    a random 32-tap filter, amplitude modulated by a smoothed random
+    envelope at a 50 Hz rate), each reaching the M microphones through its
+    own room response: a direct path with an integer inter-microphone delay
+    of the source's direction, plus an exponentially decaying random tail
+    (time constant 460 samples, about 0.2 s reverberation time, 2048 taps).
+    Returns (mixture [M, T], source images [2, M, T])."""
+    images = np.zeros((2, M, T))
+    for j in range(2):
+        e = np.convolve(rng.standard_normal(T + 31), rng.standard_normal(32), mode="valid")[:T]
+        env_pts = np.exp(rng.standard_normal(T // 320 + 2))
+        env = np.interp(np.arange(T), np.arange(len(env_pts)) * 320, env_pts)
+        s = e * env
+        step = (1, -1)[j]
+        for m in range(M):
+            h = np.zeros(2048)
+            h[2 + (m if step > 0 else M - 1 - m)] = 1.0
+            t = np.arange(2048)
+            h += 0.3 * rng.standard_normal(2048) * np.exp(-t / 460.0) * (t > 8)
+            images[j, m] = np.convolve(s, h)[:T]
+    return images.sum(0), images
+
+
+def test_separation_of_a_convolutive_mixture_improves_snr(fca):
+    """STFT (L = 1024, shift 512) -> FastFCA EM (FP32 bulk, plain start, 40
+    iterations) -> MMSE images -> synthesis. The EM leaves the source order
+    free per frequency (the paper's experiments align it with Sawada's
+    method, not built here): each frequency's order is taken from the true
+    images (ideal alignment). Each source image at microphone 1 must beat the
+    mixture's SNR by at least 3 dB."""
+    rng = np.random.default_rng(7)
+    T, M, L = 4 * 16000, 3, 1024
+    y, images = convolutive_mixture(rng, T, M)
+    yd = torch.from_numpy(y).to(DEV, torch.float32)
+    Y = fca.fca_stft(yd, L)
+    ctx = fca.fca_init(Y, prec=fca.FCA_FP32_BULK)
+    try:
+        fca.fca_em_step(ctx, 40, want_loglik=False, want_R=False, want_v=False, allow_flags=True)
+        Xh = fca.fca_separate(ctx)[0]                              # [2, F, N, M]
+    finally:
+        fca.fca_destroy(ctx)
+    Xt = torch.stack([fca.fca_stft(torch.from_numpy(images[j]).to(DEV, torch.float32), L) for j in range(2)])
+    err_keep = ((Xh - Xt).abs() ** 2).sum(dim=(2, 3))              # [2, F]
+    err_swap = ((Xh.flip(0) - Xt).abs() ** 2).sum(dim=(2, 3))
+    swap = (err_swap.sum(0) < err_keep.sum(0))[None, :, None, None]
+    Xa = torch.where(swap, Xh.flip(0), Xh).contiguous()
+    for j in range(2):
+        xh = fca.fca_istft(Xa[j], T, L).double().cpu().numpy()
+        ref = images[j, 0]
+        snr_in = 10 * np.log10(np.sum(ref ** 2) / np.sum((y[0] - ref) ** 2))
+        snr_out = 10 * np.log10(np.sum(ref ** 2) / np.sum((xh[0] - ref) ** 2))
+        print(f"source {j + 1}: SNR {snr_in:.1f} dB -> {snr_out:.1f} dB")
+        assert snr_out > snr_in + 3.0
