@@ -277,7 +277,13 @@ template <int M> struct GevdShape {
 // Called by all 64 lanes of ONE wavefront (uniform control flow). A, B, Pold
 // are full M x M row-major in LDS (Hermitian inputs; the upper triangle of B
 // is what the factorisation reads). Pnew and lam may be LDS or global.
-// Returns FCA flag bits (0 on success); on failure nothing is written.
+// Returns FCA flag bits (0 on success); when a freezing flag is returned
+// nothing is written. FastAngle computes each rotation angle in float (the
+// rotation itself, its cosine/sine pair and its application stay in double):
+// for the float bulk mode, where the angle's float accuracy is below the
+// per-bin arithmetic's. PnewT and lamT (optional) receive Pnew and lam in
+// the bulk precision Tb as well. Pnew may alias Pold (Pold is read before
+// any output is written).
 //
 // Method: B = L L^H by Cholesky (computed redundantly by every lane, so it is
 // uniform), W = L^-1; lane (i,k) of the MP x MP grid (M padded to a power of
@@ -292,9 +298,10 @@ template <int M> struct GevdShape {
 // off-diagonal entry passes that test. At the end C = diag(lam), V = Pold Q.
 // (The Appendix proof whitens B by its eigendecomposition; a Cholesky factor
 // gives the same eigenvalues and an equally valid Q.)
-template <int M>
+template <int M, bool FastAngle = false, typename Tb = double>
 __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold, GevdScratch& ws,
-                         double2* Pnew, double* lam, double* dlogdet, double eps2) {
+                         double2* Pnew, double* lam, double* dlogdet, double eps2,
+                         typename Vec2<Tb>::type* PnewT = nullptr, Tb* lamT = nullptr) {
     constexpr int MP = GevdShape<M>::MP;
     constexpr int LG = GevdShape<M>::LG;
     const int lane = threadIdx.x & 63;
@@ -377,19 +384,23 @@ __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold
     int flag = 0;
     int sweep = 0;
     for (;; ++sweep) {
-        // convergence test on the current matrix
-        if (act) ws.C[lane] = c;
-        wave_lds_sync();
-        bool open = false;
-        if (in && i < k) {
-            const double a = ws.C[i * MP + i].x, b = ws.C[k * MP + k].x;
-            const double hh = cabs2(c);
-            open = hh > eps2 * fabs(a * b) && hh > 1e-300;
-        }
-        if (!__any(open)) break;
-        if (sweep == kJacobiMaxSweeps) {
-            flag |= kFlagSweeps;
-            break;
+        // convergence test on the current matrix (before the first sweep the
+        // matrix is essentially never diagonal: that sweep always runs, and
+        // its rounds skip the rotations that are not needed)
+        if (sweep > 0) {
+            if (act) ws.C[lane] = c;
+            wave_lds_sync();
+            bool open = false;
+            if (in && i < k) {
+                const double a = ws.C[i * MP + i].x, b = ws.C[k * MP + k].x;
+                const double hh = cabs2(c);
+                open = hh > eps2 * fabs(a * b) && hh > 1e-300;
+            }
+            if (!__any(open)) break;
+            if (sweep == kJacobiMaxSweeps) {
+                flag |= kFlagSweeps;
+                break;
+            }
         }
 #pragma unroll 1
         for (int x = 1; x < MP; ++x) {
@@ -402,6 +413,7 @@ __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold
             double cc = 1.0, th = 0.0;
             double2 g = make_double2(0.0, 0.0);
             double2 cik2 = c, ci2k = c, ci2k2 = c, vik2 = v;
+            bool rot = false;
             if (act) {
                 const int p = k < k2 ? k : k2, q = k ^ k2 ^ p;
                 const double a = ws.C[p * MP + p].x, b = ws.C[q * MP + q].x;
@@ -411,16 +423,27 @@ __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold
                 ci2k2 = ws.C[i2 * MP + k2];
                 vik2 = ws.V[i * MP + k2];
                 const double hh = cabs2(h);
-                if (hh > eps2 * fabs(a * b) && hh > 1e-300) {
-                    // t = sign(tau) / (|tau| + sqrt(1 + tau^2)) written without the
-                    // division by |h|: t = sign(d) 2|h| / (|d| + sqrt(d^2 + 4|h|^2)),
-                    // d = C_qq - C_pp (no overflow, no branch).
+                rot = hh > eps2 * fabs(a * b) && hh > 1e-300;
+                if (rot) {
                     const double rh = rsqrt_nr(hh);          // 1/|h|, exact to rounding (|e| = 1)
                     const double habs = hh * rh;
                     const double d = b - a;
-                    const double w2 = fma(d, d, 4.0 * hh);
-                    const double root = w2 * rsqrt_nr1(w2);
-                    const double t = copysign(2.0 * habs * rcp_nr1(fabs(d) + root), d);
+                    double t;
+                    if constexpr (FastAngle) {
+                        // the angle in float: t = sign(d) / (u + sqrt(u^2 + 1)),
+                        // u = |d| / (2|h|); only (c, s) must be consistent in
+                        // double, which the double rsqrt below makes them
+                        const float u = (float)fmin(fabs(d) * 0.5 * rh, 1e18);
+                        const float tf = __builtin_amdgcn_rcpf(u + __builtin_amdgcn_sqrtf(fmaf(u, u, 1.0f)));
+                        t = copysign((double)tf, d);
+                    } else {
+                        // t = sign(tau) / (|tau| + sqrt(1 + tau^2)) written without the
+                        // division by |h|: t = sign(d) 2|h| / (|d| + sqrt(d^2 + 4|h|^2)),
+                        // d = C_qq - C_pp (no overflow, no branch).
+                        const double w2 = fma(d, d, 4.0 * hh);
+                        const double root = w2 * rsqrt_nr1(w2);
+                        t = copysign(2.0 * habs * rcp_nr1(fabs(d) + root), d);
+                    }
                     cc = rsqrt_nr(fma(t, t, 1.0));             // c^2 + s^2 = 1 to rounding
                     const double s = t * cc * rh;
                     g = make_double2(s * h.x, s * h.y);
@@ -428,6 +451,7 @@ __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold
                 }
                 if (i == 0) ws.prm[k] = make_double4(cc, g.x, g.y, th);
             }
+            if (!__any(rot)) continue;   // no pair of this round rotates: C and V stay
             wave_lds_sync();
             if (act) {
                 const double4 pr = ws.prm[i];
@@ -446,11 +470,13 @@ __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold
     }
 
     bool finite = !in || (cfinite(v) && (i != k || __builtin_isfinite(c.x)));
-    if (in) {
+    if (!__all(finite) || !__builtin_isfinite(ld)) flag |= kFlagNonFinite;
+    if (in && !(flag & kFreezeMask)) {
         Pnew[i * M + k] = v;
         if (i == k) lam[i] = c.x;
+        if (PnewT) PnewT[i * M + k] = make_vec2<Tb>((Tb)v.x, (Tb)v.y);
+        if (lamT && i == k) lamT[i] = (Tb)c.x;
     }
-    if (!__all(finite) || !__builtin_isfinite(ld)) flag |= kFlagNonFinite;
     *dlogdet = -ld;
     return flag;
 }

@@ -424,19 +424,21 @@ __device__ __forceinline__ bool em_update(Sh& sh, int it, int iters, int it_base
             int flag = sh.bad ? kFlagNonFinite : 0;
             double dld = 0.0;
             // the eigendecomposition is this workgroup's critical path: give its
-            // wave issue priority over co-resident waves streaming frames
+            // wave issue priority over co-resident waves streaming frames. It
+            // writes the new basis and eigenvalues in place (FP64 and bulk
+            // copies) unless it fails.
+            using Tb = typename Sh::Tb;
             __builtin_amdgcn_s_setprio(3);
-            if (!flag) flag = gevd_wave<M>(sh.S[0], sh.S[1], sh.P, sh.ws, sh.Pn, sh.lamN, &dld, eps2);
+            if (!flag)
+                flag = gevd_wave<M, sizeof(Tb) == 4, Tb>(sh.S[0], sh.S[1], sh.P, sh.ws, sh.P, sh.lam, &dld, eps2,
+                                                        sh.Pt, sh.lamT);
             __builtin_amdgcn_s_setprio(0);
-            wave_lds_sync();
             if (flag & kFreezeMask) {
                 if (tid == 0)
                     for (int l = it + 1; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
                 flag |= (it_base + it + 1) << kFlagIterShift;  // the failing iteration of the call
-            } else {
-                if (tid < MM) sh.P[tid] = sh.Pn[tid];
-                if (tid < M) sh.lam[tid] = sh.lamN[tid];
-                if (tid == 0) sh.logdet += dld;
+            } else if (tid == 0) {
+                sh.logdet += dld;
             }
             if (tid == 0) sh.flag |= flag;
         }
@@ -550,13 +552,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(M <= 4 ? 3 :
         v1[k] = ok ? v[pr.v_off + n] : T(1);
         v2[k] = ok ? v[pr.v_off + pr.v2_off + n] : T(1);
     }
+    em_prepare<M>(sh, tid);
     __syncthreads();
     const bool frozen_at_entry = (sh.flag & kFreezeMask) != 0;
     const int passes = (iters > 0 && !frozen_at_entry) ? iters : 1;
 
+    // P and Lambda in the bulk precision: prepared here, then rewritten by
+    // each basis update (published by its closing barrier)
     for (int it = 0; it < passes; ++it) {
-        em_prepare<M>(sh, tid);
-        __syncthreads();
         T lm[M];
 #pragma unroll
         for (int a = 0; a < M; ++a) lm[a] = sh.lamT[a];
@@ -623,6 +626,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int pid = pr.pid;
     em_load_state<M>(sh, Pg, lamg, logdetg, flagsg, pid, tid);
     __syncthreads();
+    em_prepare<M>(sh, tid);
+    __syncthreads();
     const bool frozen_at_entry = (sh.flag & kFreezeMask) != 0;
     const int passes = (iters > 0 && !frozen_at_entry) ? iters : 1;
     const bool write_v = iters > 0 && !frozen_at_entry;
@@ -630,8 +635,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     int cur = 0;
 
     for (int it = 0; it < passes; ++it) {
-        em_prepare<M>(sh, tid);
-        __syncthreads();
         T lm[M];
 #pragma unroll
         for (int a = 0; a < M; ++a) lm[a] = sh.lamT[a];
