@@ -106,8 +106,10 @@ def rotate(A, p, q, c, s):
 
 def ajd(Cs, tol):
     """Unitary Jacobi AJD of the Hermitian matrices Cs (list of M x M).
-    Returns (U, rotated matrices, sweeps run); rotations with |s| <= tol are
-    skipped and sweeps stop after one without a rotation."""
+    Returns (U, rotated matrices, sweeps run). A pair is left alone when its
+    off-diagonal entries are already small, sum_j |C_j,pq|^2 <= tol^2
+    sum_j |C_j,pp C_j,qq|, or its rotation is tiny, |s| <= tol; sweeps stop
+    after one without a rotation."""
     Cs = [np.array(C, dtype=np.complex128) for C in Cs]
     M = Cs[0].shape[0]
     MP = 1
@@ -121,6 +123,9 @@ def ajd(Cs, tol):
             for k in range(MP):
                 p, q = k, k ^ x
                 if not (p < q < M):
+                    continue
+                off = sum(abs(C[p, q]) ** 2 for C in Cs)
+                if off <= tol * tol * sum(abs(np.real(C[p, p] * C[q, q])) for C in Cs):
                     continue
                 c, s = cs_rotation(Cs, p, q)
                 if abs(s) <= tol:
