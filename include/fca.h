@@ -264,6 +264,60 @@ fca_status fca_stft(int32_t M, int64_t T, int32_t L, int32_t prec, const void *x
 fca_status fca_istft(int32_t M, int64_t T, int32_t L, int32_t prec, const void *X, void *x, void *stream);
 
 /* ------------------------------------------------------------------
+ * More than two sources (the extension Section 5 leaves open; not the
+ * paper's algorithm, which is exact for J = 2 only). The model of Section 2
+ * with J sources, y = x_1 + .. + x_J, x_j ~ CN(0, v_j R_j), is fitted with
+ * every R_j(f) kept in the jointly diagonalisable form R_j = P^-H Lambda_j
+ * P^-1 (one basis P per frequency, Lambda_j diagonal, Lambda_J = I). The
+ * E-step and power update of each bin run in the basis as in Algorithm 1
+ * (exact for parameters of that form); the new R~_j are then projected back
+ * onto the form: whitening by R~_J (Cholesky) and a unitary Jacobi joint
+ * diagonalisation of the other J - 1 matrices (Cardoso-Souloumiac angles,
+ * rounds of disjoint index pairs, FP64, at most 16 sweeps), whose
+ * off-diagonal remainder is dropped. For J = 2 the projection is the exact
+ * generalized eigendecomposition and the iterates are FastFCA's (eqs.
+ * GEVDeff5 .. updateLambdaeff); for J > 2 the update is an approximation of
+ * the EM (the likelihood is not guaranteed to increase). One mixture per
+ * context; 2 <= J <= 4 sources, 1 <= M <= 4 microphones, 1 <= N <= 2048
+ * frames (kept in registers: all iterations of a call run in one launch
+ * with one workgroup per frequency), FP64 or FP32 bulk (the joint
+ * diagonalisation stays FP64; a pair is rotated only while its rotation
+ * exceeds 1e-15 in FP64, 1e-8 in FP32 bulk).
+ * ------------------------------------------------------------------ */
+typedef struct fca_mctx fca_mctx;
+
+/* Create a J-source context for the mixture p->y (layout and precision as in
+ * fca_problem; p->R0 and p->v0 must be NULL).
+ *   R0  NULL (the plain start R_j = I + 0.5 (j - 1) / (J - 1) e1 e1^H,
+ *       which is fca_init's default for J = 2) or [J][F][M][M] complex128,
+ *       host or device, positive definite Hermitian (upper triangles read).
+ *       It is projected onto the jointly diagonalisable form first (exact
+ *       when it already has that form, as the plain start has).
+ *   v0  NULL (every source starts at ||y(n,f)||^2 / M, floored at 1e-12
+ *       times its mean) or [J][F][N] prec reals, host or device, positive.
+ * FCA_E_ARG (reason in fca_last_error(NULL)) for sizes out of range or an
+ * R0 whose R_J is not positive definite; FCA_E_NOMEM, FCA_E_DEVICE.
+ * Waits for the context's stream. */
+fca_status fca_multi_init(const fca_problem *p, int32_t J, const double *R0, const void *v0, fca_mctx **out);
+/* Run iters >= 0 iterations.
+ *   loglik  NULL or [iters] doubles (host or device): the log-likelihood
+ *           (eq. like with R = sum_j v_j R_j) of theta^(l) at the start of
+ *           iteration l; iters = 0: [1], that of the current parameters.
+ *   R_out   NULL or [J][F][M][M] complex128 (host or device): R_j of the
+ *           parameters after the call, P^-H Lambda_j P^-1.
+ *   v_out   NULL or [J][F][N] prec reals (host or device).
+ * FCA_E_NOT_PD / FCA_E_NONFINITE as fca_em_step (the failing frequency keeps
+ * the parameters of the iteration before; the reason names it). Waits for
+ * the stream. */
+fca_status fca_multi_em_step(fca_mctx *c, int32_t iters, double *loglik, double *R_out, void *v_out);
+/* MMSE source images with the current parameters: x_out (DEVICE) is
+ * [J][F][N][M] complex (prec), x_j = P^-H D_j (sum_k D_k)^-1 P^H y with
+ * D_j = v_j Lambda_j (eq. MMSE in the basis); they sum to y. Waits. */
+fca_status fca_multi_separate(fca_mctx *c, void *x_out);
+const char *fca_multi_last_error(const fca_mctx *c);
+void fca_multi_destroy(fca_mctx *c);   /* NULL is accepted */
+
+/* ------------------------------------------------------------------
  * Orchestration of batched runs: launch shapes, autotuning, captured steps.
  * The problems of a context are launched in groups of equal M and frames-
  * per-thread class (one launch per group and chunk of iterations; the groups

@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfca.so")
 SOURCES = ["fca_conv_m8.hip", "fca_conv_m7.hip", "fca_conv_m6.hip", "fca_conv_m5.hip", "fca_conv_lo.hip",
-           "fca_em_nt256.hip", "fca_em_nt128.hip", "fca_kernels.hip", "fca_mlp.hip", "fca_api.hip", "fca_noalloc.hip", "fca_stft.hip"]
+           "fca_em_nt256.hip", "fca_em_nt128.hip", "fca_kernels.hip", "fca_mlp.hip", "fca_api.hip",
+           "fca_noalloc.hip", "fca_stft.hip", "fca_multi.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -151,8 +151,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // per-thread log-likelihood terms into sh.LL (one value per wave). The
 // accumulator layout per source j (offset j M^2): diagonal i at i, the
 // off-diagonal pair (i < k) at M + 2 pair_index(M, i, k) (+1 imaginary).
-// With lam1 != NULL the sums of source 1 are scaled to entry (i, k) times
-// lam1[i] lam1[k] (off the diagonal) or lam1[i] (on it).
+// NS sources (2 unless given); with lam != NULL the sums of every source
+// j < NS - 1 are scaled to entry (i, k) times lam_j[i] lam_j[k] (off the
+// diagonal) or lam_j[i] (on it), lam_j = lam + j lam_stride.
 // Each wave first sums its own 64 rows (no workgroup barrier: a wave starts
 // as soon as its own frames are done), in chunks of CH values: lane (h, c)
 // adds rows h, h + H, ... of column c (H = 64 / CH lanes per column, four
@@ -161,9 +162,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // S: on return sh.S and sh.LL are complete for wave 0 only (the caller's
 // next workgroup barrier publishes them).
 // Sh provides red, wh, wp, fin, LL, S and the constants CH, NCH, NV, NW.
-template <int M, typename Sh, typename T>
-__device__ __forceinline__ void wg_reduce_sums(Sh& sh, const T (&acc)[2 * M * M], double llacc, int nf, int tid,
-                                               const double* lam1) {
+template <int M, int NS = 2, typename Sh, typename T>
+__device__ __forceinline__ void wg_reduce_sums(Sh& sh, const T (&acc)[NS * M * M], double llacc, int nf, int tid,
+                                               const double* lam, int lam_stride = 0) {
     constexpr int MM = M * M, NV = Sh::NV, CH = Sh::CH, NCH = Sh::NCH, NW = Sh::NW;
     constexpr int H = 64 / CH;
     const int lane = tid & 63, w = tid >> 6;
@@ -208,7 +209,10 @@ __device__ __forceinline__ void wg_reduce_sums(Sh& sh, const T (&acc)[2 * M * M]
     for (int t = lane; t < NV; t += 64) {
         const int j = t / MM, ent = t % MM, i = ent / M, q = ent % M;
         double sc = 1.0 / (double)nf;
-        if (lam1 && j == 0) sc *= (i == q) ? lam1[i] : lam1[i] * lam1[q];
+        if (lam && j < NS - 1) {
+            const double* lj = lam + j * lam_stride;
+            sc *= (i == q) ? lj[i] : lj[i] * lj[q];
+        }
         const double* f = sh.fin + j * MM;
         double2 val;
         if (i == q) val = make_double2(f[i] * sc, 0.0);

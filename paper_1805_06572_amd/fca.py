@@ -39,7 +39,8 @@ EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set
             "fca_mlp_get_params", "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward",
             "fca_mlp_adamw", "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
             "fca_set_mask_covariances", "fca_loglik_per_freq", "fca_em_solve_noalloc", "fca_stft", "fca_istft",
-            "fca_stft_frames"]
+            "fca_stft_frames", "fca_multi_init", "fca_multi_em_step", "fca_multi_separate", "fca_multi_last_error",
+            "fca_multi_destroy"]
 
 
 class fca_problem(ctypes.Structure):
@@ -111,13 +112,20 @@ def lib() -> ctypes.CDLL:
         L.fca_stft_frames.restype = i64
         L.fca_stft.argtypes = [i32, i64, i32, i32, vp, vp, vp]
         L.fca_istft.argtypes = [i32, i64, i32, i32, vp, vp, vp]
+        L.fca_multi_init.argtypes = [ctypes.POINTER(fca_problem), i32, vp, vp, ctypes.POINTER(vp)]
+        L.fca_multi_em_step.argtypes = [vp, i32, vp, vp, vp]
+        L.fca_multi_separate.argtypes = [vp, vp]
+        L.fca_multi_last_error.argtypes = [vp]
+        L.fca_multi_last_error.restype = ctypes.c_char_p
+        L.fca_multi_destroy.argtypes = [vp]
+        L.fca_multi_destroy.restype = None
         for name in ("fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set_active", "fca_em_step", "fca_conv_em_step", "fca_separate",
                      "fca_status_per_freq", "fca_gevd", "fca_timing", "fca_launch_groups",
                      "fca_set_launch_shape", "fca_autotune", "fca_graph_capture", "fca_graph_launch", "fca_mlp_create", "fca_mlp_get_params",
                      "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward", "fca_mlp_adamw",
                      "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
                      "fca_set_mask_covariances", "fca_loglik_per_freq", "fca_em_solve_noalloc", "fca_stft",
-                     "fca_istft"):
+                     "fca_istft", "fca_multi_init", "fca_multi_em_step", "fca_multi_separate"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -356,6 +364,87 @@ def fca_istft(X: torch.Tensor, T: int, L: int = 1024) -> torch.Tensor:
     x = torch.empty((M, T), dtype=rdt, device=X.device)
     _check(lib().fca_istft(M, T, L, prec, X.data_ptr(), x.data_ptr(), _stream_handle(X.device)))
     return x
+
+
+# ------------------------------------------------------------------ J sources
+@dataclass
+class MultiCtx:
+    """Handle of an fca_mctx (one mixture, J sources) plus its shapes."""
+    handle: int
+    J: int
+    M: int
+    F: int
+    N: int
+    prec: int
+    device: torch.device
+
+    @property
+    def real_dtype(self):
+        return torch.float64 if self.prec == FCA_FP64 else torch.float32
+
+    @property
+    def complex_dtype(self):
+        return torch.complex128 if self.prec == FCA_FP64 else torch.complex64
+
+
+def _mcheck(status: int, ctx=None, allow=()):
+    if status != FCA_OK and status not in allow:
+        raise FcaError(status, fca_multi_last_error(ctx))
+    return status
+
+
+def fca_multi_init(y, J: int, R0=None, v0=None, prec=FCA_FP32_BULK) -> MultiCtx:
+    """J-source context for one mixture y[f, n, m]; R0 [J, F, M, M]
+    complex128 and v0 [J, F, N] (prec reals) optional, host or device."""
+    y = _as_tensor(y)
+    device = y.device if y.device.type == "cuda" else torch.device("cuda", torch.cuda.current_device())
+    p, keep, (M, F, N) = _problem(y, None, None, prec, _stream_handle(device))
+    R0 = _as_tensor(R0, torch.complex128)
+    v0 = _as_tensor(v0, torch.float64 if prec == FCA_FP64 else torch.float32)
+    if R0 is not None:
+        R0 = R0.contiguous()
+        if tuple(R0.shape) != (J, F, M, M):
+            raise ValueError("R0 must be [J, F, M, M]")
+    if v0 is not None:
+        v0 = v0.contiguous()
+        if tuple(v0.shape) != (J, F, N):
+            raise ValueError("v0 must be [J, F, N]")
+    h = ctypes.c_void_p()
+    _mcheck(lib().fca_multi_init(ctypes.byref(p), J, R0.data_ptr() if R0 is not None else None,
+                                 v0.data_ptr() if v0 is not None else None, ctypes.byref(h)))
+    del keep
+    return MultiCtx(handle=h.value, J=J, M=M, F=F, N=N, prec=prec, device=device)
+
+
+def fca_multi_em_step(ctx: MultiCtx, iters: int, want_loglik=True, want_R=True, want_v=True, allow_flags=False):
+    """Run `iters` iterations. Returns (loglik [max(iters, 1)] float64,
+    R [J, F, M, M] complex128, v [J, F, N]) on the device (None if not asked)."""
+    dev = ctx.device
+    ll = torch.empty(max(iters, 1), dtype=torch.float64, device=dev) if want_loglik else None
+    R = torch.empty((ctx.J, ctx.F, ctx.M, ctx.M), dtype=torch.complex128, device=dev) if want_R else None
+    v = torch.empty((ctx.J, ctx.F, ctx.N), dtype=ctx.real_dtype, device=dev) if want_v else None
+    allow = (FCA_E_NOT_PD, FCA_E_NONFINITE) if allow_flags else ()
+    _mcheck(lib().fca_multi_em_step(ctx.handle, iters, ll.data_ptr() if ll is not None else None,
+                                    R.data_ptr() if R is not None else None,
+                                    v.data_ptr() if v is not None else None), ctx, allow)
+    return ll, R, v
+
+
+def fca_multi_separate(ctx: MultiCtx) -> torch.Tensor:
+    """MMSE source images [J, F, N, M] complex (prec) on the device."""
+    x = torch.empty((ctx.J, ctx.F, ctx.N, ctx.M), dtype=ctx.complex_dtype, device=ctx.device)
+    _mcheck(lib().fca_multi_separate(ctx.handle, x.data_ptr()), ctx)
+    return x
+
+
+def fca_multi_last_error(ctx: MultiCtx = None) -> str:
+    return lib().fca_multi_last_error(ctx.handle if ctx is not None else None).decode()
+
+
+def fca_multi_destroy(ctx: MultiCtx):
+    if ctx is not None and ctx.handle:
+        lib().fca_multi_destroy(ctx.handle)
+        ctx.handle = None
 
 
 def fca_destroy(ctx: Ctx):
