@@ -36,7 +36,6 @@ template <int M, typename T> struct ConvShared {
     T2 St[2][MM];         // R_j in the bulk precision
     T2 Si[2][MM];         // R_j^-1 in the bulk precision
     int flag, bad;
-    double fin[NV];
     T red[kEmThreads * (CH + 1)];
     double wh[NW][64];
     double wp[NW][NV];

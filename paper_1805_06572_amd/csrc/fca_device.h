@@ -148,7 +148,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Workgroup sums of the per-thread accumulators (FP64 across threads, fixed
 // order) into S~_j = sums / N as full Hermitian matrices in sh.S, and of the
-// per-thread log-likelihood terms into sh.LL (one value per wave). The
+// per-thread log-likelihood terms: per wave into sh.LL, or (DeferLL) stored
+// per thread in sh.llp for a later fixed-order sum off this path. The
 // accumulator layout per source j (offset j M^2): diagonal i at i, the
 // off-diagonal pair (i < k) at M + 2 pair_index(M, i, k) (+1 imaginary).
 // NS sources (2 unless given); with lam != NULL the sums of every source
@@ -157,20 +158,28 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Each wave first sums its own 64 rows (no workgroup barrier: a wave starts
 // as soon as its own frames are done), in chunks of CH values: lane (h, c)
 // adds rows h, h + H, ... of column c (H = 64 / CH lanes per column, four
-// interleaved partial sums), then the H partials of a column. One workgroup
-// barrier, then wave 0 adds the per-wave sums (in wave order) and assembles
-// S: on return sh.S and sh.LL are complete for wave 0 only (the caller's
-// next workgroup barrier publishes them).
-// Sh provides red, wh, wp, fin, LL, S and the constants CH, NCH, NV, NW.
-template <int M, int NS = 2, typename Sh, typename T>
+// interleaved partial sums); unless there is one chunk with H <= 4, the H
+// partials of a column are then added per wave. One workgroup barrier, then wave 0 adds the
+// per-wave sums (in wave order) and writes S: on return sh.S (and sh.LL) are
+// complete for wave 0 only (the caller's next workgroup barrier publishes
+// them).
+// Sh provides red, wh, wp, LL (or llp), S and the constants CH, NCH,
+// NV, NW.
+template <int M, int NS = 2, bool DeferLL = false, typename Sh, typename T>
 __device__ __forceinline__ void wg_reduce_sums(Sh& sh, const T (&acc)[NS * M * M], double llacc, int nf, int tid,
                                                const double* lam, int lam_stride = 0) {
     constexpr int MM = M * M, NV = Sh::NV, CH = Sh::CH, NCH = Sh::NCH, NW = Sh::NW;
     constexpr int H = 64 / CH;
+    // one chunk with few partials per column: wave 0 adds them directly
+    constexpr bool kDirect = NCH == 1 && H <= 4;
     const int lane = tid & 63, w = tid >> 6;
+    if constexpr (DeferLL) {
+        sh.llp[tid] = llacc;
+    } else {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) llacc += __shfl_xor(llacc, off, 64);
-    if (lane == 0) sh.LL[w] = llacc;
+        for (int off = 32; off >= 1; off >>= 1) llacc += __shfl_xor(llacc, off, 64);
+        if (lane == 0) sh.LL[w] = llacc;
+    }
     T* __restrict__ red = sh.red + w * 64 * (CH + 1);
     const int c = lane % CH, h = lane / CH;
 #pragma unroll
@@ -188,24 +197,36 @@ __device__ __forceinline__ void wg_reduce_sums(Sh& sh, const T (&acc)[NS * M * M
             }
             sh.wh[w][h * CH + c] = (p[0] + p[1]) + (p[2] + p[3]);
         }
-        wave_lds_sync();
-        if (lane < CH && ch * CH + lane < NV) {
-            double sum = 0.0;
+        if constexpr (!kDirect) {
+            wave_lds_sync();
+            if (lane < CH && ch * CH + lane < NV) {
+                double sum = 0.0;
 #pragma unroll
-            for (int hh = 0; hh < H; ++hh) sum += sh.wh[w][hh * CH + lane];
-            sh.wp[w][ch * CH + lane] = sum;
+                for (int hh = 0; hh < H; ++hh) sum += sh.wh[w][hh * CH + lane];
+                sh.wp[w][ch * CH + lane] = sum;
+            }
+            wave_lds_sync();
         }
-        wave_lds_sync();
     }
     __syncthreads();
     if (w != 0) return;
-    for (int e = lane; e < NV; e += 64) {
+    // the workgroup total of accumulator e: per wave the H partials (one
+    // chunk) or the per-wave sum, added in wave order
+    auto total = [&](int e) {
         double sum = 0.0;
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) sum += sh.wp[ww][e];
-        sh.fin[e] = sum;
-    }
-    wave_lds_sync();
+        for (int ww = 0; ww < NW; ++ww) {
+            if constexpr (kDirect) {
+                double part = 0.0;
+#pragma unroll
+                for (int hh = 0; hh < H; ++hh) part += sh.wh[ww][hh * CH + e];
+                sum += part;
+            } else {
+                sum += sh.wp[ww][e];
+            }
+        }
+        return sum;
+    };
     for (int t = lane; t < NV; t += 64) {
         const int j = t / MM, ent = t % MM, i = ent / M, q = ent % M;
         double sc = 1.0 / (double)nf;
@@ -213,15 +234,13 @@ __device__ __forceinline__ void wg_reduce_sums(Sh& sh, const T (&acc)[NS * M * M
             const double* lj = lam + j * lam_stride;
             sc *= (i == q) ? lj[i] : lj[i] * lj[q];
         }
-        const double* f = sh.fin + j * MM;
         double2 val;
-        if (i == q) val = make_double2(f[i] * sc, 0.0);
-        else if (i < q) {
-            const int o = M + 2 * pair_index(M, i, q);
-            val = make_double2(f[o] * sc, f[o + 1] * sc);
+        if (i == q) {
+            val = make_double2(total(j * MM + i) * sc, 0.0);
         } else {
-            const int o = M + 2 * pair_index(M, q, i);
-            val = make_double2(f[o] * sc, -f[o + 1] * sc);
+            const int o = j * MM + M + 2 * pair_index(M, i < q ? i : q, i < q ? q : i);
+            const double re = total(o) * sc, im = total(o + 1) * sc;
+            val = make_double2(re, i < q ? im : -im);
         }
         sh.S[j][ent] = val;
     }
@@ -271,6 +290,59 @@ template <int M> struct GevdShape {
     static constexpr int LG = MP == 1 ? 0 : MP == 2 ? 1 : MP == 4 ? 2 : 3;
 };
 
+// sum_j log d_j of positive pivots: one log of the product unless it leaves
+// the range where the product is exact enough.
+template <int M>
+__device__ __forceinline__ double log_pivots(const double (&d)[M]) {
+    double prod = 1.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) prod *= d[j];
+    if (prod > 1e-300 && prod < 1e300) return ::log(prod);
+    double ld = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) ld += ::log(d[j]);
+    return ld;
+}
+
+struct PairRot {
+    double cc, th;
+    double2 g;
+    bool rot;
+};
+// Jacobi rotation of one pair (p, q), p < q, of a Hermitian matrix from
+// C_pp = a, C_qq = b, C_pq = h (formulas at gevd_wave): skipped (identity)
+// when |h|^2 <= eps2 |a b|. FastAngle: the angle in float (t = sign(d) /
+// (u + sqrt(u^2 + 1)), u = |d| / (2|h|)); the cosine/sine pair stays
+// consistent in double through the double rsqrt. Otherwise
+// t = sign(d) 2|h| / (|d| + sqrt(d^2 + 4|h|^2)), d = b - a (no overflow,
+// no division by |h|).
+template <bool FastAngle>
+__device__ __forceinline__ PairRot pair_rotation(double a, double b, double2 h, double eps2) {
+    PairRot r{1.0, 0.0, make_double2(0.0, 0.0), false};
+    const double hh = cabs2(h);
+    r.rot = hh > eps2 * fabs(a * b) && hh > 1e-300;
+    if (r.rot) {
+        const double rh = rsqrt_nr(hh);
+        const double habs = hh * rh;
+        const double d = b - a;
+        double t;
+        if constexpr (FastAngle) {
+            const float u = (float)fmin(fabs(d) * 0.5 * rh, 1e18);
+            const float tf = __builtin_amdgcn_rcpf(u + __builtin_amdgcn_sqrtf(fmaf(u, u, 1.0f)));
+            t = copysign((double)tf, d);
+        } else {
+            const double w2 = fma(d, d, 4.0 * hh);
+            const double root = w2 * rsqrt_nr1(w2);
+            t = copysign(2.0 * habs * rcp_nr1(fabs(d) + root), d);
+        }
+        r.cc = rsqrt_nr(fma(t, t, 1.0));
+        const double sn = t * r.cc * rh;
+        r.g = make_double2(sn * h.x, sn * h.y);
+        r.th = t * habs;
+    }
+    return r;
+}
+
 // Generalized eigendecomposition of the Hermitian-definite pencil (A, B),
 // folded into a basis update: Pnew = Pold Q with Q^H B Q = I and
 // Q^H A Q = diag(lam); *dlogdet = -log det B = log|det Q|^2. This is the
@@ -287,7 +359,9 @@ template <int M> struct GevdShape {
 // for the float bulk mode, where the angle's float accuracy is below the
 // per-bin arithmetic's. PnewT and lamT (optional) receive Pnew and lam in
 // the bulk precision Tb as well. Pnew may alias Pold (Pold is read before
-// any output is written).
+// any output is written). With piv (optional, M doubles) the Cholesky pivots
+// d_j (log det B = sum_j log d_j) are written there instead of computing
+// *dlogdet, so that the caller can take the logarithm off this wave.
 //
 // Method: B = L L^H by Cholesky (computed redundantly by every lane, so it is
 // uniform), W = L^-1; lane (i,k) of the MP x MP grid (M padded to a power of
@@ -305,7 +379,8 @@ template <int M> struct GevdShape {
 template <int M, bool FastAngle = false, typename Tb = double>
 __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold, GevdScratch& ws,
                          double2* Pnew, double* lam, double* dlogdet, double eps2,
-                         typename Vec2<Tb>::type* PnewT = nullptr, Tb* lamT = nullptr) {
+                         typename Vec2<Tb>::type* PnewT = nullptr, Tb* lamT = nullptr,
+                         double* piv = nullptr) {
     constexpr int MP = GevdShape<M>::MP;
     constexpr int LG = GevdShape<M>::LG;
     const int lane = threadIdx.x & 63;
@@ -315,14 +390,14 @@ __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold
 
     // ---- Cholesky B = L L^H and W = L^-1, uniform across lanes
     double2 L[M][M];
-    double pivprod = 1.0;
+    double pv[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         double d = B[j * M + j].x;
 #pragma unroll
         for (int q = 0; q < j; ++q) d -= cabs2(L[j][q]);
         if (!(d > 0.0) || !__builtin_isfinite(d)) return kFlagNotPD;
-        pivprod *= d;
+        pv[j] = d;
         const double inv = rsqrt_nr(d);
         L[j][j] = make_double2(d * inv, 0.0);
 #pragma unroll
@@ -333,13 +408,15 @@ __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold
             L[r][j] = cscale(inv, s);
         }
     }
-    double ld;
-    if (pivprod > 1e-300 && pivprod < 1e300) {
-        ld = ::log(pivprod);
-    } else {
-        ld = 0.0;
+    // log det B = sum_j log d_j; with piv the pivots d_j go to the caller
+    // instead (lane 0 writes them) and *dlogdet is left alone
+    double ld = 0.0;
+    if (piv) {
+        if (lane == 0)
 #pragma unroll
-        for (int j = 0; j < M; ++j) ld += 2.0 * ::log(L[j][j].x);
+            for (int j = 0; j < M; ++j) piv[j] = pv[j];
+    } else {
+        ld = log_pivots<M>(pv);
     }
     if (lane == 0) {
         double2 Wr[M][M];
@@ -414,53 +491,24 @@ __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold
                 ws.V[lane] = v;
             }
             wave_lds_sync();
-            double cc = 1.0, th = 0.0;
-            double2 g = make_double2(0.0, 0.0);
+            PairRot r{1.0, 0.0, make_double2(0.0, 0.0), false};
             double2 cik2 = c, ci2k = c, ci2k2 = c, vik2 = v;
-            bool rot = false;
             if (act) {
                 const int p = k < k2 ? k : k2, q = k ^ k2 ^ p;
-                const double a = ws.C[p * MP + p].x, b = ws.C[q * MP + q].x;
-                const double2 h = ws.C[p * MP + q];
+                r = pair_rotation<FastAngle>(ws.C[p * MP + p].x, ws.C[q * MP + q].x, ws.C[p * MP + q], eps2);
                 cik2 = ws.C[i * MP + k2];
                 ci2k = ws.C[i2 * MP + k];
                 ci2k2 = ws.C[i2 * MP + k2];
                 vik2 = ws.V[i * MP + k2];
-                const double hh = cabs2(h);
-                rot = hh > eps2 * fabs(a * b) && hh > 1e-300;
-                if (rot) {
-                    const double rh = rsqrt_nr(hh);          // 1/|h|, exact to rounding (|e| = 1)
-                    const double habs = hh * rh;
-                    const double d = b - a;
-                    double t;
-                    if constexpr (FastAngle) {
-                        // the angle in float: t = sign(d) / (u + sqrt(u^2 + 1)),
-                        // u = |d| / (2|h|); only (c, s) must be consistent in
-                        // double, which the double rsqrt below makes them
-                        const float u = (float)fmin(fabs(d) * 0.5 * rh, 1e18);
-                        const float tf = __builtin_amdgcn_rcpf(u + __builtin_amdgcn_sqrtf(fmaf(u, u, 1.0f)));
-                        t = copysign((double)tf, d);
-                    } else {
-                        // t = sign(tau) / (|tau| + sqrt(1 + tau^2)) written without the
-                        // division by |h|: t = sign(d) 2|h| / (|d| + sqrt(d^2 + 4|h|^2)),
-                        // d = C_qq - C_pp (no overflow, no branch).
-                        const double w2 = fma(d, d, 4.0 * hh);
-                        const double root = w2 * rsqrt_nr1(w2);
-                        t = copysign(2.0 * habs * rcp_nr1(fabs(d) + root), d);
-                    }
-                    cc = rsqrt_nr(fma(t, t, 1.0));             // c^2 + s^2 = 1 to rounding
-                    const double s = t * cc * rh;
-                    g = make_double2(s * h.x, s * h.y);
-                    th = t * habs;
-                }
-                if (i == 0) ws.prm[k] = make_double4(cc, g.x, g.y, th);
+                if (i == 0) ws.prm[k] = make_double4(r.cc, r.g.x, r.g.y, r.th);
             }
-            if (!__any(rot)) continue;   // no pair of this round rotates: C and V stay
+            if (!__any(r.rot)) continue;   // no pair of this round rotates: C and V stay
             wave_lds_sync();
             if (act) {
-                const double4 pr = ws.prm[i];
+                const double4 pr = ws.prm[i];   // the rotation of the pair containing i
                 // column factor G_{k2,k} and conjugated row factor conj(G_{i2,i})
-                const double2 gk = (k < k2) ? make_double2(-g.x, g.y) : g;
+                const double cc = r.cc, th = r.th;
+                const double2 gk = (k < k2) ? make_double2(-r.g.x, r.g.y) : r.g;
                 const double2 gi = (i < i2) ? make_double2(-pr.y, -pr.z) : make_double2(pr.y, -pr.z);
                 const double ci = pr.x;
                 double2 cn = cadd(cscale(ci, cadd(cscale(cc, c), cmul(gk, cik2))),
@@ -481,7 +529,7 @@ __device__ int gevd_wave(const double2* A, const double2* B, const double2* Pold
         if (PnewT) PnewT[i * M + k] = make_vec2<Tb>((Tb)v.x, (Tb)v.y);
         if (lamT && i == k) lamT[i] = (Tb)c.x;
     }
-    *dlogdet = -ld;
+    if (!piv) *dlogdet = -ld;
     return flag;
 }
 

@@ -50,11 +50,12 @@ template <int M, typename T, int NT_ = kEmThreads> struct EmShared {
     int flag;           // FCA flag bits of the problem
     int bad;            // a non-finite or non-positive power appeared in this pass
     double2 S[2][MM];   // S~1, S~2 (full Hermitian, FP64)
-    double fin[NV];
     T red[NT_ * (CH + 1)];
     double wh[NW][64];  // per-wave partial column sums
     double wp[NW][NV];  // per-wave sums
-    double LL[NW];
+    double llp[NT_];    // per-thread log-likelihood terms of the pass
+    double piv[2][M];   // Cholesky pivots of the last two updates (by parity)
+    int pend[2];        // that update succeeded; its log-determinant is pending
     GevdScratch ws;
 };
 
@@ -268,7 +269,9 @@ template <int M, int NT_> struct EmSharedMf {
     double2 S[2][MM];
     double fin[NV];
     double red2[G * CH];
-    double LL[NW];
+    double llp[NT_];
+    double piv[2][M];
+    int pend[2];
     double Gm[2][256];  // W_j W_j^T summed over the waves (FP64)
     union {
         float stg[NW][2 * kStgSrc];  // per wave: W_1 then W_2 (layout above)
@@ -340,17 +343,15 @@ __device__ __forceinline__ void em_bin_mf(const float (&yr)[M], const float (&yi
     wave_lds_sync();
 }
 
-// End-of-pass reduction for the MFMA scheme: per-wave log-likelihood, the
-// per-thread diagonal terms (two fixed-order stages) and the per-wave Gram
+// End-of-pass reduction for the MFMA scheme: the per-thread log-likelihood
+// terms stored for em_update, the per-thread diagonal terms (two fixed-order stages) and the per-wave Gram
 // blocks (summed over the waves in FP64, fixed order) into S~_j = sums / N.
 template <int M, int NT_>
 __device__ __forceinline__ void wg_reduce_mf(EmSharedMf<M, NT_>& sh, const float (&cd)[2 * M], const f32x4 (&am)[2],
                                              double llacc, int nf, int tid) {
     constexpr int MM = M * M, CH = 2 * M, G = NT_ / 32, NW = NT_ / 64;
     const int lane = tid & 63, w = tid >> 6;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) llacc += __shfl_xor(llacc, off, 64);
-    if (lane == 0) sh.LL[w] = llacc;
+    sh.llp[tid] = llacc;
     __syncthreads();  // every wave is done with its staging rows (shared with red, blk)
 #pragma unroll
     for (int c = 0; c < CH; ++c) sh.u.r.red[tid * (CH + 1) + c] = cd[c];
@@ -397,30 +398,26 @@ __device__ __forceinline__ void wg_reduce_mf(EmSharedMf<M, NT_>& sh, const float
     __syncthreads();
 }
 
-// After the reduction of a pass (S~_j in sh.S, per-wave log-likelihood in
-// sh.LL): record LL(theta^(it)), then the FP64 GEVD of (S~1, S~2) and the
-// basis update P <- P Q, Lambda <- Sigma (eqs. GEVDeff5, updatePeff,
-// updateLambdaeff) on wave 0. Returns true when the caller must stop
-// iterating: an evaluation-only pass, a problem frozen on entry, or a failure
-// that froze it now (it then keeps theta^(it), whose log-likelihood stands
-// for the later iterations).
+// After the reduction of a pass (S~_j in sh.S, per-thread log-likelihood
+// terms in sh.llp): on wave 0 the FP64 GEVD of (S~1, S~2) and the basis
+// update P <- P Q, Lambda <- Sigma (eqs. GEVDeff5, updatePeff,
+// updateLambdaeff), which leaves its Cholesky pivots for log|det P|^2; beside
+// it on wave 1, log|det P^(it)|^2 (the previous update's pivots) and
+// LL(theta^(it)). Returns true when the caller must stop iterating: an
+// evaluation-only pass, a problem frozen on entry, or a failure that froze it
+// now (it then keeps theta^(it), whose log-likelihood stands for the later
+// iterations). The last update's log-determinant stays pending
+// (em_settle_logdet).
 template <int M, typename Sh>
 __device__ __forceinline__ bool em_update(Sh& sh, int it, int iters, int it_base, bool frozen_at_entry, int nf,
                                           double* __restrict__ ll, int64_t ll_stride, int pid, double eps2,
                                           int tid) {
-    constexpr int MM = M * M, NW = Sh::NW;
+    constexpr int NW = Sh::NW;
     const int ll_count = iters > 0 ? iters : 1;
+    const bool last = (iters == 0) || frozen_at_entry;
+    double tot = 0.0;
     if (tid < 64) {
-        const bool last = (iters == 0) || frozen_at_entry;
-        double tot = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) tot += sh.LL[w];
-        tot += (double)nf * (-(double)M * kLogPi + sh.logdet);
-        if (last) {
-            if (tid == 0)
-                for (int l = it; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
-        } else {
-            if (tid == 0) ll[(int64_t)it * ll_stride + pid] = tot;
+        if (!last) {
             int flag = sh.bad ? kFlagNonFinite : 0;
             double dld = 0.0;
             // the eigendecomposition is this workgroup's critical path: give its
@@ -431,33 +428,57 @@ __device__ __forceinline__ bool em_update(Sh& sh, int it, int iters, int it_base
             __builtin_amdgcn_s_setprio(3);
             if (!flag)
                 flag = gevd_wave<M, sizeof(Tb) == 4, Tb>(sh.S[0], sh.S[1], sh.P, sh.ws, sh.P, sh.lam, &dld, eps2,
-                                                        sh.Pt, sh.lamT);
+                                                        sh.Pt, sh.lamT, sh.piv[it & 1]);
             __builtin_amdgcn_s_setprio(0);
-            if (flag & kFreezeMask) {
-                if (tid == 0)
-                    for (int l = it + 1; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
-                flag |= (it_base + it + 1) << kFlagIterShift;  // the failing iteration of the call
-            } else if (tid == 0) {
-                sh.logdet += dld;
+            if (flag & kFreezeMask) flag |= (it_base + it + 1) << kFlagIterShift;  // the failing iteration of the call
+            if (tid == 0) {
+                sh.pend[it & 1] = (flag & kFreezeMask) ? 0 : 1;
+                sh.flag |= flag;
             }
-            if (tid == 0) sh.flag |= flag;
+        }
+    } else if (tid < 128) {
+        double logdet = sh.logdet;
+        if (it > 0 && sh.pend[(it - 1) & 1]) logdet -= log_pivots<M>(sh.piv[(it - 1) & 1]);
+        double part = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) part += sh.llp[w * 64 + (tid - 64)];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
+        tot = part + (double)nf * (-(double)M * kLogPi + logdet);
+        if (tid == 64) {
+            sh.logdet = logdet;
+            if (last)
+                for (int l = it; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
+            else
+                ll[(int64_t)it * ll_stride + pid] = tot;
         }
     }
     __syncthreads();
-    return iters == 0 || frozen_at_entry || (sh.flag & kFreezeMask);
+    const bool frozen_now = !last && (sh.flag & kFreezeMask);
+    if (frozen_now && tid == 64)
+        for (int l = it + 1; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
+    return last || frozen_now;
+}
+
+// log|det P|^2 of the last update of a call (pending after em_update), by
+// thread 0 after the loop (whose last em_update ended with a barrier).
+// last_it: the last iteration that ran an update, or -1.
+template <int M, typename Sh>
+__device__ __forceinline__ void em_settle_logdet(Sh& sh, int last_it, int tid) {
+    if (tid == 0 && last_it >= 0 && sh.pend[last_it & 1]) sh.logdet -= log_pivots<M>(sh.piv[last_it & 1]);
 }
 
 
 // End of one pass over the frames (per-thread accumulators): FP64 reduction
-// of the sums and of the log-likelihood over the workgroup (fixed order),
-// S~_j = sums / N, then em_update.
+// of the sums over the workgroup (fixed order), S~_j = sums / N, the
+// log-likelihood terms stored per thread, then em_update.
 template <int M, typename T, int NT_>
 __device__ __forceinline__ bool em_finish(EmShared<M, T, NT_>& sh, const T (&acc)[2 * M * M], double llacc,
                                           bool bad, int it, int iters, int it_base, bool frozen_at_entry, int nf,
                                           double* __restrict__ ll, int64_t ll_stride, int pid, double eps2,
                                           int tid) {
     if (bad) sh.bad = 1;
-    wg_reduce_sums<M>(sh, acc, llacc, nf, tid, sh.lam);
+    wg_reduce_sums<M, 2, true>(sh, acc, llacc, nf, tid, sh.lam);
     return em_update<M>(sh, it, iters, it_base, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid);
 }
 
@@ -559,6 +580,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(M <= 4 ? 3 :
 
     // P and Lambda in the bulk precision: prepared here, then rewritten by
     // each basis update (published by its closing barrier)
+    int last_it = -1;
     for (int it = 0; it < passes; ++it) {
         T lm[M];
 #pragma unroll
@@ -581,6 +603,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(M <= 4 ? 3 :
             __builtin_amdgcn_sched_barrier(0);
             pa.bin(sh, yr[k], yi[k], v1[k], v2[k], lm, (k * NT + tid) < nf, llacc, v1n[k], v2n[k], bad, tid);
         }
+        last_it = (iters > 0 && !frozen_at_entry) ? it : -1;
         if (pa.finish(sh, llacc, bad, it, iters, it_base, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid)) break;
 #pragma unroll
         for (int k = 0; k < FPT; ++k) {
@@ -588,6 +611,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(M <= 4 ? 3 :
             v2[k] = v2n[k];
         }
     }
+    em_settle_logdet<M>(sh, last_it, tid);
 
     if (iters > 0 && !frozen_at_entry) {
 #pragma unroll
@@ -633,6 +657,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const bool write_v = iters > 0 && !frozen_at_entry;
     const T2* __restrict__ yb = y + pr.y_off;
     int cur = 0;
+    int last_it = -1;
 
     for (int it = 0; it < passes; ++it) {
         T lm[M];
@@ -673,9 +698,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
                 }
             }
         }
+        last_it = write_v ? it : -1;
         if (pa.finish(sh, llacc, bad, it, iters, it_base, frozen_at_entry, nf, ll, ll_stride, pid, eps2, tid)) break;
         cur ^= 1;
     }
+    em_settle_logdet<M>(sh, last_it, tid);
 
     if (write_v) {
         if (cur) {

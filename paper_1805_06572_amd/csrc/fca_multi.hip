@@ -301,7 +301,6 @@ template <int M, int J, typename T> struct MultiShared {
     double logdet;
     int flag, bad;
     double2 S[J][kMS];
-    double fin[NV];
     T red[kMThreads * (CH + 1)];
     double wh[NW][64];
     double wp[NW][NV];
