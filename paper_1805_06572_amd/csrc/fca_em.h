@@ -539,8 +539,20 @@ template <int M> struct PassAcc<M, float, true> {
 // One workgroup owns one (mixture, frequency) EM problem for all iterations of
 // a call; each thread keeps FPT frames of y and v in registers, so y(n,f) and
 // v_j(n,f) cross HBM once per call, not once per iteration.
+// Waves per SIMD requested for em_kernel: three workgroups per CU where the
+// per-thread frames fit in 168 registers (M <= 4, up to four frames per
+// thread), two otherwise (eight frames per thread spill at three). FP64 at
+// M = 4 with eight frames keeps the request of three, which the compiler
+// cannot meet: it then takes accumulation registers at one workgroup per CU,
+// where a request of two makes it spill to scratch instead.
+template <int M, typename T, int FPT>
+constexpr int em_waves_per_eu() {
+    if (M == 4 && sizeof(T) == 8 && FPT == 8) return 3;
+    return (M <= 4 && FPT <= 4) ? 3 : 2;
+}
+
 template <int M, typename T, int FPT, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(M <= 4 ? 3 : 2))) void em_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(em_waves_per_eu<M, T, FPT>()))) void em_kernel(
     const EmProblem* __restrict__ probs, const typename Vec2<T>::type* __restrict__ y,
     T* __restrict__ v, double2* __restrict__ Pg, double* __restrict__ lamg,
     double* __restrict__ logdetg, int* __restrict__ flagsg, double* __restrict__ ll,
