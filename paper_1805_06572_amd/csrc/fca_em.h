@@ -109,9 +109,10 @@ __device__ __forceinline__ void em_prepare(Sh& sh, int tid) {
 //   llacc += -sum_i log d_i - sum_i |y~_i|^2 / d_i   (log-likelihood of theta^(l))
 // `ok` masks padding frames (no contribution, powers unchanged).
 // em_bin_front: everything up to the new powers; leaves y~ (ytr, yti), e_i,
-// r_i, t1_i, t2_i and the new powers nv1, nv2 (also in nv1o, nv2o unless
-// padding).
-template <int M, typename T>
+// r_i, t1_i, t2_i (unless KeepT is false: then only their sums are formed,
+// one fused multiply-add per term) and the new powers nv1, nv2 (also in
+// nv1o, nv2o unless padding).
+template <int M, typename T, bool KeepT = true>
 __device__ __forceinline__ void em_bin_front(const T (&yr)[M], const T (&yi)[M], T a1, T a2, const T (&lm)[M],
                                              const typename Vec2<T>::type* Pt, bool ok, double& llacc, T& nv1o,
                                              T& nv2o, bool& bad, T (&ytr)[M], T (&yti)[M], T (&e)[M], T (&r)[M],
@@ -162,10 +163,15 @@ __device__ __forceinline__ void em_bin_front(const T (&yr)[M], const T (&yi)[M],
     for (int i = 0; i < M; ++i) {
         const T er = e[i] * r[i];
         const T a1l = a1 * lm[i];
-        t1[i] = r[i] * fma(a1l, er, a2);
-        t2[i] = r[i] * fma(a2, er, a1l);
-        s1 += t1[i];
-        s2 += t2[i];
+        if constexpr (KeepT) {
+            t1[i] = r[i] * fma(a1l, er, a2);
+            t2[i] = r[i] * fma(a2, er, a1l);
+            s1 += t1[i];
+            s2 += t2[i];
+        } else {
+            s1 = fma(r[i], fma(a1l, er, a2), s1);
+            s2 = fma(r[i], fma(a2, er, a1l), s2);
+        }
     }
     nv1 = a1 * s1 * (T(1) / T(M));
     nv2 = a2 * s2 * (T(1) / T(M));
@@ -273,7 +279,7 @@ template <int M, int NT_> struct EmSharedMf {
     double piv[2][M];
     int pend[2];
     double Gm[2][256];  // W_j W_j^T summed over the waves (FP64)
-    union {
+    union alignas(16) {  // the staging rows are read back as float4
         float stg[NW][2 * kStgSrc];  // per wave: W_1 then W_2 (layout above)
         struct {
             float red[NT_ * (CH + 1)];
@@ -303,7 +309,7 @@ __device__ __forceinline__ void em_bin_mf(const float (&yr)[M], const float (&yi
                                           float& nv1o, float& nv2o, bool& bad, float* __restrict__ stg,
                                           float (&cd)[2 * M], f32x4 (&am)[2], int lane) {
     float ytr[M], yti[M], e[M], r[M], t1[M], t2[M], nv1, nv2;
-    em_bin_front<M, float>(yr, yi, a1, a2, lm, Pt, ok, llacc, nv1o, nv2o, bad, ytr, yti, e, r, t1, t2, nv1, nv2);
+    em_bin_front<M, float, false>(yr, yi, a1, a2, lm, Pt, ok, llacc, nv1o, nv2o, bad, ytr, yti, e, r, t1, t2, nv1, nv2);
     const float w1 = ok ? __builtin_amdgcn_rsqf(nv1) : 0.0f;
     const float w2 = ok ? __builtin_amdgcn_rsqf(nv2) : 0.0f;
     const float iv1 = w1 * w1, iv2 = w2 * w2;
@@ -670,7 +676,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const T2* __restrict__ yb = y + pr.y_off;
     int cur = 0;
     int last_it = -1;
-
+    // the frames of one chunk: y and the powers of theta^(l). Lanes past the
+    // last frame load the last frame (the bins mask them by `ok`), so every
+    // load is unconditional: loads under a branch are waited for inside it,
+    // one after the other, while these stay in flight until first used.
+    auto load_chunk = [&](int base, const T* __restrict__ vsrc, T (&cyr)[FPT][M], T (&cyi)[FPT][M],
+                          T (&ca1)[FPT], T (&ca2)[FPT]) {
+#pragma unroll
+        for (int k = 0; k < FPT; ++k) {
+            const int n = min(base + k * NT + tid, nf - 1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const T2 val = yb[(int64_t)m * npad + n];
+                cyr[k][m] = val.x;
+                cyi[k][m] = val.y;
+            }
+            ca1[k] = vsrc[n];
+            ca2[k] = vsrc[pr.v2_off + n];
+        }
+    };
     for (int it = 0; it < passes; ++it) {
         T lm[M];
 #pragma unroll
@@ -683,21 +707,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         T* __restrict__ vout = v + (cur ? 0 : v_alt) + pr.v_off;
         for (int base = 0; base < nf; base += NT * FPT) {
             T yr[FPT][M], yi[FPT][M], a1[FPT], a2[FPT];
-#pragma unroll
-            for (int k = 0; k < FPT; ++k) {
-                const int n = base + k * NT + tid;
-                const bool ok = n < nf;
-#pragma unroll
-                for (int m = 0; m < M; ++m) {
-                    T2 val;
-                    if (ok) val = yb[(int64_t)m * npad + n];
-                    else { val.x = T(0); val.y = T(0); }
-                    yr[k][m] = val.x;
-                    yi[k][m] = val.y;
-                }
-                a1[k] = ok ? vin[n] : T(1);
-                a2[k] = ok ? vin[pr.v2_off + n] : T(1);
-            }
+            load_chunk(base, vin, yr, yi, a1, a2);
 #pragma unroll
             for (int k = 0; k < FPT; ++k) {
                 const int n = base + k * NT + tid;
