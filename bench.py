@@ -207,6 +207,36 @@ def base_record(args, value, ms_per_step, config):
 
 
 # ---------------------------------------------------------------------------- workloads
+def invariants(fca, R, gll_f):
+    """Run metrics of the method's invariants on the final parameters
+    R [2, F, M, M] (device, complex128) and the per-frequency log-likelihood
+    rows gll_f [iters, F]: the library's FP64 generalized eigendecomposition of
+    (R1, R2) must give P^H R2 P = I and P^H R1 P = diag(lambda) (the Appendix
+    theorem), and the EM log-likelihood never decreases (Section 2)."""
+    import numpy as np
+    import torch
+    R1, R2 = R[0].contiguous(), R[1].contiguous()
+    P, lam, flags = fca.fca_gevd(R1, R2)
+    PH = P.conj().transpose(-1, -2).contiguous()
+    eye = torch.eye(R1.shape[-1], dtype=torch.complex128, device=R1.device)
+    r2 = (torch.matmul(torch.matmul(PH, R2), P) - eye).abs().amax(dim=(-2, -1)).cpu().numpy()
+    d1 = torch.matmul(torch.matmul(PH, R1), P) - torch.diag_embed(lam.to(torch.complex128))
+    r1 = (d1.abs().amax(dim=(-2, -1)) / lam.abs().amax(dim=-1)).cpu().numpy()
+    # FP64 residuals grow with the conditioning of R2 (near-singular at the
+    # lowest frequencies, where the diffuse field is almost rank one)
+    w = np.linalg.eigvalsh(R2.cpu().numpy())
+    cond = w[:, -1] / np.maximum(w[:, 0], 1e-300)
+    dll = np.diff(gll_f, axis=0)
+    drops = dll < -1e-6 * np.abs(gll_f[1:])
+    q = lambda a: {"median": float(np.median(a)), "p99": float(np.quantile(a, 0.99)), "max": float(a.max())}
+    return {"gevd_PH_R2_P_minus_I": q(r2), "gevd_PH_R1_P_minus_Lambda_rel": q(r1),
+            "gevd_residual_over_cond_eps_max": float(np.max(np.maximum(r1, r2) / (cond * 2.2e-16))),
+            "cond_R2": q(cond),
+            "gevd_flagged": int((flags != 0).sum()),
+            "loglik_decreases": {"count": int(drops.sum()), "of": int(dll.size),
+                                 "rule": "LL(l+1) < LL(l) - 1e-6 |LL(l+1)| per frequency"}}
+
+
 def oracle_error(kappa, oflags, gflags, S, v, ll, gR, gv, gll_f):
     """GPU against the oracle, per frequency: relative 2-norm errors of v_j
     and R_j, and of the log-likelihood of every iterate summed over the
@@ -266,6 +296,7 @@ def run_array(args):
     # the outputs of the last timed step, before the conventional kernel reuses the buffers
     lls = run.ll.cpu().numpy()[0]
     gll_f = fca.fca_loglik_per_freq(run.ctx, L).cpu().numpy()[:, 0]
+    inv = invariants(fca, run.R.view(2, F, M, M), gll_f)
     gR = run.R.view(2, F, M, M).cpu().numpy()
     gv = run.v.view(2, F, N).cpu().numpy()
     flags = fca.fca_status_per_freq(run.ctx)[0]
@@ -292,6 +323,7 @@ def run_array(args):
                               "flagged_frequencies": int((conv_flags != 0).sum())}
     rec["loglik_first_last"] = [float(lls[0]), float(lls[-1])]
     rec["flagged_frequencies"] = int((flags != 0).sum())
+    rec["invariants"] = inv
     if not args.no_cpu_baseline:
         # the oracle on every frequency and frame of the same input and start:
         # the CPU baseline and the error of the GPU result

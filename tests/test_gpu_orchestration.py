@@ -184,6 +184,33 @@ def test_graph_with_inactive_mixture_and_stale_shape(fca):
         fca.fca_destroy(ref)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_resume_from_exported_parameters(fca, prec):
+    """Checkpoint and resume: 6 iterations, export (R, v), start a second
+    context from them with fca_set_start and run 4 more; the result equals
+    10 straight iterations. The resumed context rebuilds its basis from R
+    (another eigendecomposition of the same pencil), so the agreement is to
+    rounding, not bitwise: relative 1e-9 in FP64, 1e-4 in FP32 bulk."""
+    P = fca.FCA_FP64 if prec == "fp64" else fca.FCA_FP32_BULK
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    mxs, ys = batch(dtype=np.complex128 if prec == "fp64" else np.complex64)
+    straight = fca.fca_init_batch(ys, prec=P)
+    resumed = fca.fca_init_batch(ys, prec=P)
+    try:
+        ll, R, v = fca.fca_em_step(straight, 10, allow_flags=True)
+        _, R6, v6 = fca.fca_em_step(resumed, 6, allow_flags=True)
+        for k in range(len(ys)):
+            fca.fca_set_start(resumed, k, R6[k].clone(), v6[k].clone())
+        ll2, R2, v2 = fca.fca_em_step(resumed, 4, allow_flags=True)
+    finally:
+        fca.fca_destroy(straight)
+        fca.fca_destroy(resumed)
+    for k in range(len(ys)):
+        assert rel(v2[k].double().cpu().numpy(), v[k].double().cpu().numpy(), (-1,)).max() < tol
+        assert rel(R2[k].cpu().numpy(), R[k].cpu().numpy(), (-2, -1)).max() < tol
+        np.testing.assert_allclose(ll2[k].cpu().numpy(), ll[k, 6:].cpu().numpy(), rtol=tol)
+
+
 def test_invalid_arguments_are_rejected_and_leave_the_context_usable(fca):
     """Host-side argument checks of the ABI: FCA_E_ARG (or FCA_E_STATE) and
     no change to a live context."""
