@@ -462,6 +462,12 @@ def run_large(args):
     return rec
 
 
+def progress(msg: str):
+    """One line on stderr when a phase of a long run ends (the JSON result
+    line stays alone on stdout)."""
+    print(msg, file=sys.stderr, flush=True)
+
+
 def time_to_target(args, seed0: int = 3000, K: int | None = None, settings=None, widths=None):
     """Time to a target log-likelihood, on K held-out array mixtures (M = 4,
     F = 513, N = 1000, AR(1) log-powers, seeds seed0 .. seed0 + K - 1).
@@ -521,6 +527,7 @@ def time_to_target(args, seed0: int = 3000, K: int | None = None, settings=None,
 
     plain_its = [first_hit(h, thr[k]) for k, (_, h) in enumerate(plain)]
     plain_ms = sum(ms * (L if it is None else it) / L for (ms, _), it in zip(plain, plain_its))
+    progress(f"time to target: plain FP32 one mixture at a time, {plain_ms:.1f} ms")
     hit_rule, conv_rule = schedule.reached(thr), schedule.converged(1e-6)
 
     def stop(b, ll):
@@ -553,14 +560,17 @@ def time_to_target(args, seed0: int = 3000, K: int | None = None, settings=None,
                 "reached": len(got), "of": len(its)}
 
     bp_ms, _, bp_run, bp_hits, _ = batched(None)
+    progress(f"time to target: batched plain start, {bp_ms:.1f} ms")
     learned = []
     for H in widths:
         t0 = time.perf_counter()
         net, _ = learned_init.train(M=M, F=F, steps=args.train_steps, batch=8192, seed=0, hidden=H)
         train_s = time.perf_counter() - t0
+        progress(f"time to target: width {H} trained in {train_s:.1f} s")
         bce, bce_const = learned_init.evaluate(net, n=65536, M=M, F=F)
         ms, start_ms, run_its, hits, chosen = batched(net)
         net.close()
+        progress(f"time to target: width {H} learned start, {ms:.1f} ms")
         learned.append({"hidden": H, "ms": ms, "start_ms": start_ms,
                         "speedup_vs_plain_fp32_one_at_a_time": plain_ms / ms,
                         "speedup_vs_batched_plain": bp_ms / ms,
