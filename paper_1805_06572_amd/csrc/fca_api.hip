@@ -97,7 +97,10 @@ struct fca_ctx {
     MaskCovMix* mask_mix = nullptr;       // device table of fca_set_mask_covariances (B entries)
     MaskCovMix* mask_mix_host = nullptr;  // pinned staging of it
     EmProblem* table_act = nullptr;  // pinned host staging of probs_act (nprob entries)
-    hipEvent_t table_ev = nullptr;   // the last upload from table_act
+    int* inactive_host = nullptr;    // pinned host staging of inactive_dev (B entries)
+    hipEvent_t table_ev = nullptr;   // the last upload from table_act or inactive_host
+    int* inactive_dev = nullptr;     // indices of the inactive mixtures at the last table rebuild
+    int n_inactive = 0;
     EmProblem* probs_act = nullptr;
     std::vector<Group> groups_act;
     std::vector<char> active;
@@ -180,12 +183,13 @@ fca_status dev_alloc(fca_ctx* c, P** p, size_t bytes) {
 void free_ctx_memory(fca_ctx* c) {
     void* dev[] = {c->y, c->v, c->v_init, c->R_init, c->P, c->Pinv, c->lam, c->logdet, c->flags, c->ll,
                    c->ll_tot, c->fsum, c->R_stage, c->probs, c->x_off, c->probs_act, c->flag_sum,
-                   c->P0, c->lam0, c->logdet0, c->mask_mix};
+                   c->P0, c->lam0, c->logdet0, c->mask_mix, c->inactive_dev};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->ll_host) (void)hipHostFree(c->ll_host);
     if (c->flag_sum_host) (void)hipHostFree(c->flag_sum_host);
     if (c->table_act) (void)hipHostFree(c->table_act);
+    if (c->inactive_host) (void)hipHostFree(c->inactive_host);
     if (c->mask_mix_host) (void)hipHostFree(c->mask_mix_host);
     if (c->table_ev) (void)hipEventDestroy(c->table_ev);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -342,6 +346,7 @@ fca_status do_reset(fca_ctx* c) {
     std::fill(c->active.begin(), c->active.end(), 1);
     c->all_active = true;
     c->act_dirty = false;
+    c->n_inactive = 0;
     FCA_HIP(c, hipStreamSynchronize(c->stream));
     return FCA_OK;
 }
@@ -353,8 +358,9 @@ fca_status refresh_active(fca_ctx* c) {
     c->act_dirty = false;
     c->shape_version += 1;
     c->all_active = std::all_of(c->active.begin(), c->active.end(), [](char a) { return a != 0; });
+    c->n_inactive = 0;
     if (c->all_active) return FCA_OK;
-    FCA_HIP(c, hipEventSynchronize(c->table_ev));  // the previous upload has read the staging buffer
+    FCA_HIP(c, hipEventSynchronize(c->table_ev));  // the previous upload has read the staging buffers
     c->groups_act.clear();
     int n = 0;
     for (const Group& g : c->groups) {
@@ -371,11 +377,14 @@ fca_status refresh_active(fca_ctx* c) {
         }
         if (ga.count) c->groups_act.push_back(ga);
     }
-    if (n) {
+    if (n)
         FCA_HIP(c, hipMemcpyAsync(c->probs_act, c->table_act, (size_t)n * sizeof(EmProblem), hipMemcpyHostToDevice,
                                   c->stream));
-        FCA_HIP(c, hipEventRecord(c->table_ev, c->stream));
-    }
+    for (int b = 0; b < c->B; ++b)
+        if (!c->active[b]) c->inactive_host[c->n_inactive++] = b;
+    FCA_HIP(c, hipMemcpyAsync(c->inactive_dev, c->inactive_host, (size_t)c->n_inactive * sizeof(int),
+                              hipMemcpyHostToDevice, c->stream));
+    FCA_HIP(c, hipEventRecord(c->table_ev, c->stream));
     return FCA_OK;
 }
 
@@ -488,6 +497,7 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
     FCA_TRY(dev_alloc(c, &c->probs_act, (size_t)c->nprob * sizeof(EmProblem)));
     FCA_TRY(dev_alloc(c, &c->x_off, (size_t)c->nprob * 2 * sizeof(int64_t)));
     FCA_TRY(dev_alloc(c, &c->flag_sum, 5 * sizeof(int)));
+    FCA_TRY(dev_alloc(c, &c->inactive_dev, (size_t)B * sizeof(int)));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->ll_host), (size_t)kLChunk * B * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -506,6 +516,13 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
                       hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         c->table_act = nullptr;
+        set_err(c, "hipHostMalloc failed");
+        FCA_TRY(FCA_E_NOMEM);
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->inactive_host), (size_t)B * sizeof(int), hipHostMallocDefault) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        c->inactive_host = nullptr;
         set_err(c, "hipHostMalloc failed");
         FCA_TRY(FCA_E_NOMEM);
     }
@@ -1031,9 +1048,8 @@ fca_status enqueue_em_groups(fca_ctx* c, const std::vector<Group>& groups, const
 // column `done` (inactive mixtures: NaN rows).
 fca_status enqueue_ll_out(fca_ctx* c, int rows, int total, int done, double* loglik_dev, hipStream_t s) {
     FCA_HIP(c, launch_ll_reduce(c->ll, c->nprob, rows, c->B, c->F, c->ll_tot, s));
-    if (!c->all_active)  // all-ones words: a NaN double in every row of an inactive mixture
-        for (int b = 0; b < c->B; ++b)
-            if (!c->active[b]) FCA_HIP(c, launch_fill_u32(c->ll_tot + (size_t)b * rows, 0xFFFFFFFFu, 2 * rows, s));
+    if (!c->all_active && c->n_inactive)  // NaN in every row of an inactive mixture, one launch
+        FCA_HIP(c, launch_nan_rows(c->ll_tot, 0, 1, rows, rows, c->inactive_dev, c->n_inactive, s));
     if (loglik_dev)
         FCA_HIP(c, hipMemcpy2DAsync(loglik_dev + done, total * sizeof(double), c->ll_tot, rows * sizeof(double),
                                     rows * sizeof(double), c->B, hipMemcpyDeviceToDevice, s));
@@ -1484,18 +1500,32 @@ fca_status fca_loglik_per_freq(const fca_ctx* cc, int32_t rows, double* ll_out) 
     FCA_HIP(c, hipMemcpyAsync(ll_out, c->ll + (int64_t)(c->last_rows - rows) * c->nprob, n * sizeof(double),
                               hipMemcpyDefault, s));
     const bool dev = is_device_ptr(ll_out);
-    if (!dev) FCA_HIP(c, hipStreamSynchronize(s));
+    if (dev) {
+        // NaN rows of the mixtures inactive in that call, one launch (the
+        // list staged like the launch tables)
+        FCA_HIP(c, hipEventSynchronize(c->table_ev));
+        int ni = 0;
+        for (int b = 0; b < c->B; ++b)
+            if (!c->last_active[b]) c->inactive_host[ni++] = b;
+        if (ni) {
+            FCA_HIP(c, hipMemcpyAsync(c->inactive_dev, c->inactive_host, (size_t)ni * sizeof(int),
+                                      hipMemcpyHostToDevice, s));
+            FCA_HIP(c, launch_nan_rows(ll_out, c->nprob, rows, c->F, c->F, c->inactive_dev, ni, s));
+            // the same list as the last table rebuild's unless the activity
+            // changed since, which marks the tables for a rebuild anyway
+            FCA_HIP(c, hipEventRecord(c->table_ev, s));
+        }
+        FCA_HIP(c, hipStreamSynchronize(s));
+        return FCA_OK;
+    }
+    FCA_HIP(c, hipStreamSynchronize(s));
     for (int b = 0; b < c->B; ++b) {
         if (c->last_active[b]) continue;
         for (int r = 0; r < rows; ++r) {
             double* row = ll_out + (int64_t)r * c->nprob + (int64_t)b * c->F;
-            if (dev)  // all-ones words: NaN doubles
-                FCA_HIP(c, launch_fill_u32(row, 0xFFFFFFFFu, 2 * (int64_t)c->F, s));
-            else
-                for (int f = 0; f < c->F; ++f) row[f] = std::numeric_limits<double>::quiet_NaN();
+            for (int f = 0; f < c->F; ++f) row[f] = std::numeric_limits<double>::quiet_NaN();
         }
     }
-    if (dev) FCA_HIP(c, hipStreamSynchronize(s));
     return FCA_OK;
 }
 

@@ -122,6 +122,11 @@ int mlp_microphones(const fca_mlp* m);
 // Text returned by fca_last_error(NULL) (calls without a context).
 void set_global_error(const char* msg);
 
+// NaN in base[r row_stride + list[i] b_stride + e] for r < rows, e < len and
+// the `count` entries of the device index list (one launch).
+hipError_t launch_nan_rows(double* base, int64_t row_stride, int rows, int64_t b_stride, int len, const int* list,
+                           int count, hipStream_t s);
+
 // out[0] = OR of flags[0..count), out[1] / out[2] = first index flagged
 // kFlagNotPD / kFlagNonFinite, count if none (out: 3 device ints).
 hipError_t launch_flag_summary(const int* flags, int count, int* out, hipStream_t s);

@@ -145,6 +145,27 @@ __global__ __launch_bounds__(kFlagThreads) void flag_summary_kernel(const int* _
     }
 }
 
+__global__ void nan_rows_kernel(double* __restrict__ base, int64_t row_stride, int rows, int64_t b_stride, int len,
+                                const int* __restrict__ list, int count) {
+    const int64_t per = (int64_t)rows * len;
+    const int64_t total = per * count;
+    const double nan = __longlong_as_double(-1LL);   // all-ones bits
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i / per);
+        const int64_t rem = i - (int64_t)k * per;
+        const int r = (int)(rem / len), e = (int)(rem - (int64_t)r * len);
+        base[(int64_t)r * row_stride + (int64_t)list[k] * b_stride + e] = nan;
+    }
+}
+
+hipError_t launch_nan_rows(double* base, int64_t row_stride, int rows, int64_t b_stride, int len, const int* list,
+                           int count, hipStream_t s) {
+    if (count <= 0 || rows <= 0 || len <= 0) return hipSuccess;
+    nan_rows_kernel<<<grid_for((int64_t)count * rows * len, 256), 256, 0, s>>>(base, row_stride, rows, b_stride, len,
+                                                                               list, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_flag_summary(const int* flags, int count, int* out, hipStream_t s) {
     flag_summary_kernel<<<1, kFlagThreads, 0, s>>>(flags, count, out);
     return hipGetLastError();
