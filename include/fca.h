@@ -334,13 +334,16 @@ typedef struct {
  * receives the number of groups. */
 fca_status fca_launch_groups(const fca_ctx *c, fca_launch_group *out, int32_t cap, int32_t *count);
 
-/* Set the launch shape of launch group `group`: threads 0 or 256 (the
- * default), or 128 (groups of at most 1024 frames; each thread then keeps up
+/* Set the launch shape of launch group `group`: threads 0 or 256, or 128
+ * (groups of at most 1024 frames; each thread then keeps up
  * to 8 frames in registers); streamed != 0 re-reads the frames from memory
  * every pass instead of keeping them in registers (256 threads; the only
  * shape for groups beyond 2048 frames). Results differ only by rounding (a
  * different reduction order). FCA_E_ARG for a group index out of range or a
- * shape that cannot hold the group. */
+ * shape that cannot hold the group. A context starts every group at 256
+ * threads, except float-bulk groups of M <= 4 microphones, at most 1024
+ * frames and more problems than three per compute unit, which start at 128
+ * threads (more of their problems fit on a compute unit at once). */
 fca_status fca_set_launch_shape(fca_ctx *c, int32_t group, int32_t threads, int32_t streamed);
 
 /* Pick the launch shape of every group by measurement: each admissible shape

@@ -576,6 +576,29 @@ fca_status init_impl(const fca_problem* probs, int32_t B, fca_ctx** out) {
             g.max_n = std::max(g.max_n, mi.N);
         }
     }
+    // Default launch shape: 256 threads with the group's frames per thread.
+    // A float-bulk group at M <= 4 with more problems than 256-thread
+    // workgroups hold at once (three per CU) and at most 1024 frames starts at
+    // 128 threads (eight frames per thread) instead: those workgroups hold
+    // more problems per CU in registers (at M = 4 four rather than three;
+    // measured 7 % faster per iteration on 256 mixtures of 513 x 1000 bins).
+    // fca_set_launch_shape and fca_autotune override it.
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            cus = 0;
+        }
+        for (Group& g : c->groups) {
+            if (c->fp64 || g.M > 4 || g.fpt == 0 || g.max_n > 128 * kMaxFramesPerThread || cus <= 0 ||
+                g.count <= 3 * cus)
+                continue;
+            int f = 1;
+            while (f * 128 < g.max_n) f *= 2;
+            g.nt = 128;
+            g.run_fpt = f;
+        }
+    }
     c->table = table;
     FCA_TRY(hipcall(hipMemcpyAsync(c->probs, c->table.data(), c->table.size() * sizeof(EmProblem),
                                    hipMemcpyHostToDevice, s), "hipMemcpyAsync(problems)"));
