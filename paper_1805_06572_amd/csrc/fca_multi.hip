@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <new>
@@ -726,6 +727,30 @@ namespace {
 
 using fca::EmProblem;
 
+// Whether the Hermitian matrix with the upper triangle of A (M x M,
+// row-major) is positive definite: a Cholesky factorisation in double.
+bool hermitian_pd(const double2* A, int M) {
+    double Lr[4][4] = {}, Li[4][4] = {};
+    for (int j = 0; j < M; ++j) {
+        double d = A[j * M + j].x;
+        for (int q = 0; q < j; ++q) d -= Lr[j][q] * Lr[j][q] + Li[j][q] * Li[j][q];
+        if (!(d > 0.0) || !std::isfinite(d)) return false;
+        const double l = std::sqrt(d);
+        Lr[j][j] = l;
+        for (int r = j + 1; r < M; ++r) {
+            // A_rj = conj(A_jr); L_rj = (A_rj - sum_q L_rq conj(L_jq)) / L_jj
+            double sr = A[j * M + r].x, si = -A[j * M + r].y;
+            for (int q = 0; q < j; ++q) {
+                sr -= Lr[r][q] * Lr[j][q] + Li[r][q] * Li[j][q];
+                si -= Li[r][q] * Lr[j][q] - Lr[r][q] * Li[j][q];
+            }
+            Lr[r][j] = sr / l;
+            Li[r][j] = si / l;
+        }
+    }
+    return true;
+}
+
 void mfree(fca_mctx* c) {
     void* ptrs[] = {c->y, c->v, c->P, c->Pinv, c->lam, c->logdet, c->flags, c->ll, c->ll_tot, c->fsum, c->R0, c->probs,
                     c->flag_sum};
@@ -866,9 +891,22 @@ fca_status fca_multi_init(const fca_problem* p, int32_t J, const double* R0, con
                                (size_t)F * c->npad * c->rsz, hipMemcpyDeviceToDevice, s) != hipSuccess)
                 return fail(FCA_E_DEVICE, "plain start failed");
     }
-    // spatial covariances: given, or the plain start S_j = I + 0.5 (j-1)/(J-1) e1 e1^H
+    // spatial covariances: given (every R_j(f) checked positive definite by a
+    // Cholesky factorisation of the Hermitian matrix its upper triangle
+    // defines), or the plain start S_j = I + 0.5 (j-1)/(J-1) e1 e1^H
     if (R0) {
-        if (hipMemcpyAsync(c->R0, R0, (size_t)J * F * M * M * sizeof(double2), hipMemcpyDefault, s) != hipSuccess)
+        std::vector<double2> h((size_t)J * F * M * M);
+        if (hipMemcpy(h.data(), R0, h.size() * sizeof(double2), hipMemcpyDefault) != hipSuccess)
+            return fail(FCA_E_DEVICE, "copy of R0 failed");
+        for (int j = 0; j < J; ++j)
+            for (int f = 0; f < F; ++f)
+                if (!hermitian_pd(h.data() + ((size_t)j * F + f) * M * M, M)) {
+                    char what[96];
+                    snprintf(what, sizeof what, "R0 of source %d at frequency %d is not positive definite", j + 1, f);
+                    return fail(FCA_E_ARG, what);
+                }
+        if (hipMemcpyAsync(c->R0, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
             return fail(FCA_E_DEVICE, "copy of R0 failed");
     } else {
         std::vector<double2> h((size_t)J * F * M * M, make_double2(0.0, 0.0));

@@ -203,6 +203,11 @@ def test_argument_errors(fca):
     with pytest.raises(fca.FcaError) as e:
         fca.fca_multi_init(y, 3, R0=R0)
     assert e.value.status == fca.FCA_E_ARG and "positive definite" in str(e.value)
+    R0[2, 1] = np.eye(2)
+    R0[0, 1] = np.array([[1.0, 2.0], [2.0, 1.0]])   # R_1 of frequency 1 indefinite, positive diagonal
+    with pytest.raises(fca.FcaError) as e:
+        fca.fca_multi_init(y, 3, R0=R0)
+    assert e.value.status == fca.FCA_E_ARG and "source 1 at frequency 1" in str(e.value)
     p, keep, _ = fca._problem(y, np.stack([np.eye(2)] * 2 * 2).reshape(2, 2, 2, 2).astype(np.complex128), None,
                               fca.FCA_FP32_BULK, None)
     import ctypes
