@@ -27,7 +27,10 @@ Other workloads (--workload): "batched" = 64 mixtures with N uniform in
 F = 1025, N = 8000, 100 iterations (frames streamed); "time-to-target" =
 the time-to-target comparison alone; "ttt-tune" = the choice of the learned
 path's settings (mask sharpening, start-comparison iteration, stop-check
-chunks) on mixtures disjoint from the evaluation ones.
+chunks) on mixtures disjoint from the evaluation ones; "stft" = the STFT
+analysis and synthesis of a four-microphone recording of 1024 s at the paper's
+settings (samples/s, HBM roofline of both kernels); "multi" = the J-source
+EM (J = 3 and 4) on one array mixture M = 4, F = 513, N = 1000.
 """
 from __future__ import annotations
 
@@ -63,23 +66,28 @@ def bytes_per_update(M: int) -> int:
     return 8 * M + 16
 
 
-def kernel_source_hash() -> str:
+STFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stft1024_traffic.json")
+STFT_SOURCES = [os.path.join(ROOT, "paper_1805_06572_amd", "csrc", "fca_stft.hip")]
+
+
+def kernel_source_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """Measured HBM bytes per EM launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
-    scaled by a copy-kernel calibration), if taken on the current kernel."""
+def load_traffic(path=TRAFFIC_FILE, sources=None, key="bytes_per_launch"):
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    scaled by a copy-kernel calibration), if taken on the current kernel
+    sources."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if t.get("kernel_source_hash") != kernel_source_hash(sources):
         return None
-    return t.get("bytes_per_launch")
+    return t.get(key)
 
 
 def oracle_threads() -> int:
@@ -200,8 +208,8 @@ def roofline_entry(kernel_ms, bytes_alg, flop, traffic, kernel_name):
                           "frac_of_78_6_unpacked": tflops / FP32_UNPACKED_TFLOPS}}
 
 
-def base_record(args, value, ms_per_step, config):
-    return {"metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+def base_record(args, value, ms_per_step, config, metric=METRIC, unit="updates/s"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": config}
 
@@ -610,6 +618,152 @@ def run_time_to_target(args):
     return rec
 
 
+def hbm_entry(ms, nbytes, kernel, rule):
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "traffic": None, "kernel": kernel, "kernel_ms_per_launch": ms, "algorithmic_bytes_per_launch": nbytes,
+            "bytes_rule": rule}
+
+
+def event_ms(fn, reps):
+    """Mean duration of fn() over reps calls, HIP events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_stft(args):
+    """The STFT front and back end at the paper's analysis settings (16 kHz,
+    frames of 1024 samples, shift 512, square-root Hann window) on one
+    4-microphone recording of 1024 s (the [F, N, 4] layout the EM takes),
+    one call each way; error against the oracle on the first second of
+    channel 0 and the reconstruction error."""
+    import numpy as np
+    import torch
+    from paper_1805_06572_amd import fca
+    import oracle.stft as ostft
+    C, T, L = 4, 1024 * 16000, 1024
+    g = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.randn((C, T), generator=g, device="cuda", dtype=torch.float32)
+    X = fca.fca_stft(x, L)
+    F, N, _ = X.shape
+    ms_a = event_ms(lambda: fca.fca_stft(x, L), args.steps)
+    ms_s = event_ms(lambda: fca.fca_istft(X, T, L), args.steps)
+    xr = fca.fca_istft(X, T, L)
+    rec_err = float((xr - x).abs().max() / x.abs().max())
+    head = x[:1, :16000].double().cpu().numpy()
+    want = ostft.stft(head, L)                       # [F, 33, 1]
+    full = int((16000 - 1) // (L // 2)) - 1          # frames lying wholly in the first second
+    got = X[:, :full, :1].to(torch.complex128).cpu().numpy()
+    err = float(np.max(np.abs(got - want[:, :full])) / np.max(np.abs(want[:, :full])))
+    samples = C * T
+    b_a = 4 * C * T + 8 * F * N * C
+    rec = base_record(args, samples / (ms_a * 1e-3), ms_a + ms_s,
+                      {"workload": f"STFT analysis and overlap-add synthesis, {C} channels x {T} samples "
+                                   f"(a 4-microphone recording of 1024 s at 16 kHz), L = {L}, shift {L // 2}",
+                       "channels": C, "samples_per_channel": T, "frame": L, "frames": N, "bins": F},
+                      metric="STFT samples/s (analysis)", unit="samples/s")
+    rec["synthesis_samples_per_s"] = samples / (ms_s * 1e-3)
+    rec["roofline"] = hbm_entry(ms_a, b_a, "stft1024_kernel (16 transforms per workgroup)",
+                                "4 B per input sample read once + 8 B per output bin written")
+    rec["roofline"]["traffic"] = load_traffic(STFT_TRAFFIC_FILE, STFT_SOURCES, "stft1024_bytes_per_launch")
+    rec["roofline_synthesis"] = hbm_entry(ms_s, b_a, "istft1024_kernel (16 transforms per workgroup)",
+                                          "8 B per input bin read once + 4 B per output sample written")
+    rec["roofline_synthesis"]["traffic"] = load_traffic(STFT_TRAFFIC_FILE, STFT_SOURCES, "istft1024_bytes_per_launch")
+    rec["oracle_error"] = {"sample": f"channel 0, frames 0..{full - 1} (the first second)", "rel_err_max": err}
+    rec["reconstruction_rel_err_max"] = rec_err
+    return rec
+
+
+def multi_mixture(J, M, F, N, seed):
+    """J far-field sources on the 4-microphone array: R_j(f) = a_j a_j^H +
+    0.1 diffuse coherence (direction theta_j uniform in (0, pi)), v_j(n, f)
+    Gamma(0.5, 1), images drawn as sqrt(v) R^(1/2) z."""
+    import numpy as np
+    from paper_1805_06572_amd import synth
+    rng = np.random.default_rng(seed)
+    G = synth.diffuse_coherence(M, F)
+    y = np.zeros((F, N, M), np.complex128)
+    for j in range(J):
+        a = synth.steering_vectors(float(rng.uniform(0.0, np.pi)), M, F)
+        R = a[:, :, None] * np.conj(a[:, None, :]) + 0.1 * G
+        v = rng.gamma(0.5, 1.0, size=(F, N))
+        y += synth.draw_images(R[None], v[None], synth.cn(rng, (1, F, N, M)), "eig")[0]
+    return y
+
+
+CHECK_ITERS = 5
+
+
+def run_multi(args):
+    """The J-source EM (approximate joint diagonalisation) on one array-style
+    mixture of J sources, M = 4, F = 513, N = 1000, float bulk, `iters`
+    iterations per call, for J = 3 and 4; error against the FP64 oracle
+    (oracle/multi.py) on four frequencies after a few iterations."""
+    import numpy as np
+    import torch
+    from paper_1805_06572_amd import fca
+    from oracle import multi
+    M, F, N, L = 4, 513, 1000, args.iters
+    out = {}
+    for J in (3, 4):
+        y = multi_mixture(J, M, F, N, 40 + J)
+        yd = torch.from_numpy(y.astype(np.complex64)).cuda()
+        ctx = fca.fca_multi_init(yd, J, prec=fca.FCA_FP32_BULK)
+        try:
+            fca.fca_multi_em_step(ctx, 1, want_loglik=False, want_R=False, want_v=False, allow_flags=True)
+            ms, kms = [], []
+            for _ in range(args.steps):
+                ctx2 = fca.fca_multi_init(yd, J, prec=fca.FCA_FP32_BULK)
+                fca.fca_multi_timing(ctx2, True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ll, R_out, v_out = fca.fca_multi_em_step(ctx2, L, want_R=False, allow_flags=True)
+                ms.append((time.perf_counter() - t0) * 1e3)
+                k_ms, n_launch = fca.fca_multi_timing(ctx2, False)
+                kms.append(k_ms / n_launch)
+                if _ < args.steps - 1:
+                    fca.fca_multi_destroy(ctx2)
+            gll = ll.cpu().numpy()
+            fca.fca_multi_destroy(ctx2)
+            # error after a few iterations on two frequencies (the oracle is slow)
+            ctx2 = fca.fca_multi_init(yd, J, prec=fca.FCA_FP32_BULK)
+            _, _, v_few = fca.fca_multi_em_step(ctx2, CHECK_ITERS, want_R=False, allow_flags=True)
+            gv = v_few.double().cpu().numpy()
+            fca.fca_multi_destroy(ctx2)
+        finally:
+            fca.fca_multi_destroy(ctx)
+        idx = np.array([F // 8, 3 * F // 8, 5 * F // 8, 7 * F // 8])
+        yc = y.astype(np.complex64).astype(np.complex128)[idx]
+        S0, v0 = multi.default_start(yc, J)
+        _, vo, _, _, _ = multi.fast_em(yc, S0, v0, CHECK_ITERS)
+        ev = float(np.max(np.sqrt((np.abs(gv[:, idx] - vo) ** 2).sum(-1)) / np.sqrt((np.abs(vo) ** 2).sum(-1))))
+        t, tk = float(np.median(ms)), float(np.median(kms))
+        bts = (8 * M + 8 * J) * F * N * L
+        out[f"J{J}"] = {"ms_per_call": t, "updates_per_s": F * N * L / (t * 1e-3), "kernel_ms_per_launch": tk,
+                        "roofline": hbm_entry(tk, bts, "em_multi_kernel (one workgroup per frequency, all iterations; "
+                                              "HIP events on the context's stream)",
+                                              "(8 M + 8 J) B per bin and iteration (y read, J powers read and written)"),
+                        "oracle_error": {"sample": f"v after {CHECK_ITERS} iterations, bins {', '.join(str(int(i)) for i in idx)}",
+                                         "rel_err_max": ev},
+                        "loglik_first_last": [float(gll[0]), float(gll[-1])]}
+    rec = base_record(args, out["J3"]["updates_per_s"], out["J3"]["ms_per_call"],
+                      {"workload": f"J-source EM, one mixture M={M} F={F} N={N}, {L} iterations, float bulk, "
+                                   "plain start (J = 3 headline, J = 4 beside it)", "M": M, "F": F, "N": N,
+                       "iterations": L},
+                      metric="TF-bin EM updates/sec, J sources (approximate joint diagonalisation)")
+    rec["roofline"] = out["J3"]["roofline"]
+    rec["per_J"] = out
+    return rec
+
+
 def run_ttt_tune(args):
     """Settings of the learned path (mask sharpening, start-comparison
     iteration, stop-check chunks) by wall time to target on 64 mixtures of
@@ -639,7 +793,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="array",
-                    choices=["array", "batched", "large", "time-to-target", "ttt-tune"])
+                    choices=["array", "batched", "large", "time-to-target", "ttt-tune", "stft", "multi"])
     ap.add_argument("--no-ttt", dest="ttt", action="store_false",
                     help="array workload: skip the time-to-target comparison")
     ap.add_argument("--iters", type=int, default=None)
@@ -683,7 +837,8 @@ def main():
     import torch
     torch.cuda.set_device(0)
     runner = {"array": run_array, "batched": run_batched, "large": run_large,
-              "time-to-target": run_time_to_target, "ttt-tune": run_ttt_tune}[args.workload]
+              "time-to-target": run_time_to_target, "ttt-tune": run_ttt_tune, "stft": run_stft,
+              "multi": run_multi}[args.workload]
     print(json.dumps(runner(args)), flush=True)
 
 

@@ -314,6 +314,13 @@ fca_status fca_multi_em_step(fca_mctx *c, int32_t iters, double *loglik, double 
  * [J][F][N][M] complex (prec), x_j = P^-H D_j (sum_k D_k)^-1 P^H y with
  * D_j = v_j Lambda_j (eq. MMSE in the basis); they sum to y. Waits. */
 fca_status fca_multi_separate(fca_mctx *c, void *x_out);
+/* Kernel timing of the iterations, as fca_timing: enable != 0 makes later
+ * fca_multi_em_step calls record HIP events on the context's stream around
+ * each launch of the iteration kernel (and wait for them); on return
+ * *em_kernel_ms and *em_launches (either may be NULL) hold the totals since
+ * the previous call, which restart from zero. FCA_E_DEVICE if the events
+ * cannot be created. */
+fca_status fca_multi_timing(fca_mctx *c, int32_t enable, double *em_kernel_ms, int64_t *em_launches);
 const char *fca_multi_last_error(const fca_mctx *c);
 void fca_multi_destroy(fca_mctx *c);   /* NULL is accepted */
 

@@ -720,6 +720,10 @@ struct fca_mctx {
     double2* R0 = nullptr;      // [J][F][M][M]
     fca::EmProblem* probs = nullptr;
     int* flag_sum = nullptr;    // 5 ints
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // created by the first fca_multi_timing(enable != 0)
+    bool timing = false;
+    double em_ms = 0.0;
+    int64_t em_launches = 0;
     std::string err;
 };
 
@@ -943,8 +947,17 @@ fca_status fca_multi_em_step(fca_mctx* c, int32_t iters, double* loglik, double*
     do {
         const int chunk = iters == 0 ? 0 : std::min(kMRows, iters - done);
         const int rows = chunk > 0 ? chunk : 1;
+        if (c->timing) MHIP(c, hipEventRecord(c->ev0, s));
         MHIP(c, dispatch_mj<OpEm>(c->M, c->J, c->fp64, c->fpt, (const EmProblem*)c->probs, c->F, (const void*)c->y,
                                   c->v, c->P, c->lam, c->logdet, c->flags, c->ll, chunk, done, s));
+        if (c->timing) {
+            MHIP(c, hipEventRecord(c->ev1, s));
+            MHIP(c, hipEventSynchronize(c->ev1));
+            float ms = 0.f;
+            MHIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+            c->em_ms += ms;
+            ++c->em_launches;
+        }
         if (loglik) {
             MHIP(c, launch_ll_reduce(c->ll, c->F, rows, 1, c->F, c->ll_tot, s));
             MHIP(c, hipMemcpyAsync(loglik + done, c->ll_tot, rows * sizeof(double), hipMemcpyDefault, s));
@@ -981,12 +994,29 @@ fca_status fca_multi_separate(fca_mctx* c, void* x_out) {
     return FCA_OK;
 }
 
+fca_status fca_multi_timing(fca_mctx* c, int32_t enable, double* em_kernel_ms, int64_t* em_launches) {
+    using namespace fca;
+    if (!c) return FCA_E_ARG;
+    if (enable && !c->ev0) {
+        MHIP(c, hipEventCreate(&c->ev0));
+        MHIP(c, hipEventCreate(&c->ev1));
+    }
+    if (em_kernel_ms) *em_kernel_ms = c->em_ms;
+    if (em_launches) *em_launches = c->em_launches;
+    c->em_ms = 0.0;
+    c->em_launches = 0;
+    c->timing = enable != 0;
+    return FCA_OK;
+}
+
 const char* fca_multi_last_error(const fca_mctx* c) { return c ? c->err.c_str() : fca_last_error(nullptr); }
 
 void fca_multi_destroy(fca_mctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     mfree(c);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
 }
 

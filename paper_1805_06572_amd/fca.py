@@ -39,8 +39,8 @@ EXPORTED = ["fca_init", "fca_init_batch", "fca_reset", "fca_set_start", "fca_set
             "fca_mlp_get_params", "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward",
             "fca_mlp_adamw", "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
             "fca_set_mask_covariances", "fca_loglik_per_freq", "fca_em_solve_noalloc", "fca_stft", "fca_istft",
-            "fca_stft_frames", "fca_multi_init", "fca_multi_em_step", "fca_multi_separate", "fca_multi_last_error",
-            "fca_multi_destroy"]
+            "fca_stft_frames", "fca_multi_init", "fca_multi_em_step", "fca_multi_separate", "fca_multi_timing",
+            "fca_multi_last_error", "fca_multi_destroy"]
 
 
 class fca_problem(ctypes.Structure):
@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
         L.fca_multi_init.argtypes = [ctypes.POINTER(fca_problem), i32, vp, vp, ctypes.POINTER(vp)]
         L.fca_multi_em_step.argtypes = [vp, i32, vp, vp, vp]
         L.fca_multi_separate.argtypes = [vp, vp]
+        L.fca_multi_timing.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.fca_multi_last_error.argtypes = [vp]
         L.fca_multi_last_error.restype = ctypes.c_char_p
         L.fca_multi_destroy.argtypes = [vp]
@@ -125,7 +126,7 @@ def lib() -> ctypes.CDLL:
                      "fca_mlp_set_params", "fca_mlp_forward", "fca_mlp_backward", "fca_mlp_adamw",
                      "fca_mlp_init_powers", "fca_mlp_init_powers_batch", "fca_set_learned_starts",
                      "fca_set_mask_covariances", "fca_loglik_per_freq", "fca_em_solve_noalloc", "fca_stft",
-                     "fca_istft", "fca_multi_init", "fca_multi_em_step", "fca_multi_separate"):
+                     "fca_istft", "fca_multi_init", "fca_multi_em_step", "fca_multi_separate", "fca_multi_timing"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -435,6 +436,14 @@ def fca_multi_separate(ctx: MultiCtx) -> torch.Tensor:
     x = torch.empty((ctx.J, ctx.F, ctx.N, ctx.M), dtype=ctx.complex_dtype, device=ctx.device)
     _mcheck(lib().fca_multi_separate(ctx.handle, x.data_ptr()), ctx)
     return x
+
+
+def fca_multi_timing(ctx: MultiCtx, enable: bool):
+    """(ms, launches) of the iteration kernel since the previous call; enable
+    switches event timing of later fca_multi_em_step calls on or off."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _mcheck(lib().fca_multi_timing(ctx.handle, 1 if enable else 0, ctypes.byref(ms), ctypes.byref(n)), ctx)
+    return ms.value, n.value
 
 
 def fca_multi_last_error(ctx: MultiCtx = None) -> str:

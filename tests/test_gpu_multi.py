@@ -222,3 +222,20 @@ def test_argument_errors(fca):
     finally:
         fca.fca_multi_destroy(ctx)
     del keep
+
+
+def test_kernel_timing_counts_launches(fca):
+    """fca_multi_timing: 130 iterations are two launches of the iteration
+    kernel (at most 128 per launch), timed with events; the totals restart
+    after each call and nothing is recorded while timing is off."""
+    y = j_source_mixture(3, 2, 3, 64, seed=4)
+    ctx = fca.fca_multi_init(torch.from_numpy(y.astype(np.complex64)).to(DEV), 3)
+    try:
+        assert fca.fca_multi_timing(ctx, True) == (0.0, 0)
+        fca.fca_multi_em_step(ctx, 130, want_R=False, want_v=False, allow_flags=True)
+        ms, n = fca.fca_multi_timing(ctx, False)
+        assert n == 2 and ms > 0.0
+        fca.fca_multi_em_step(ctx, 5, want_R=False, want_v=False, allow_flags=True)
+        assert fca.fca_multi_timing(ctx, False) == (0.0, 0)
+    finally:
+        fca.fca_multi_destroy(ctx)

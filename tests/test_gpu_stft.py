@@ -36,6 +36,10 @@ def rel(a, b):
     ("fp64", 16, 3, 1), ("fp32", 16, 1, 7),          # shorter than a frame
     ("fp32", 256, 4, 999), ("fp64", 4096, 1, 9000),  # largest frame (FP64: 112 KB of LDS)
     ("fp32", 4096, 2, 4097),
+    # L = 1024 takes the register-resident path: workgroups of 16 (FP32) or 8 (FP64)
+    # transforms; synthesis overlaps them by M (M <= 8 or 4) or splits them (larger M)
+    ("fp32", 1024, 1, 700), ("fp32", 1024, 9, 3001), ("fp32", 1024, 4, 9 * 1024 + 17),
+    ("fp64", 1024, 5, 2500), ("fp64", 1024, 3, 100), ("fp32", 1024, 17, 1537),
 ])
 def test_stft_and_istft_match_oracle(fca, prec, L, M, T):
     rng = np.random.default_rng(L + M + T)
