@@ -393,8 +393,16 @@ constexpr double kMultiTolFp64 = 1e-15;
 constexpr double kMultiTolFp32 = 1e-8;
 
 // Problem table entries: y_off, v_off (source j at + j v2_off), n, npad, pid.
+// Register budget: three workgroups per CU in float bulk with up to four
+// frames per thread (513 frequencies then run as one wave of workgroups on
+// 256 CUs); no cap otherwise (FP64 needs two workgroups' LDS per CU anyway).
 template <int M, int J, typename T, int FPT>
-__global__ __launch_bounds__(kMThreads) void em_multi_kernel(
+constexpr int multi_waves_per_eu() {
+    return (sizeof(T) == 4 && FPT <= 4) ? 3 : 1;
+}
+
+template <int M, int J, typename T, int FPT>
+__global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu<M, J, T, FPT>()))) void em_multi_kernel(
     const EmProblem* __restrict__ probs, const typename Vec2<T>::type* __restrict__ y, T* __restrict__ v,
     double2* __restrict__ Pg, double* __restrict__ lamg, double* __restrict__ logdetg, int* __restrict__ flagsg,
     double* __restrict__ ll, int64_t ll_stride, int iters, int it_base) {
