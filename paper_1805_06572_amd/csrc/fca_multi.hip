@@ -206,15 +206,10 @@ __device__ int ajd_wave(const double2 (*S)[kMS], const double2* Pold, AjdScratch
             double cs = 1.0;
             double2 sn = make_double2(0.0, 0.0);
             bool rot = false;
-            double2 cik2[NC], ci2k[NC], ci2k2[NC];
-            double2 vik2 = v;
             if (act) {
                 double off = 0.0, dia = 0.0, g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int j = 0; j < NC; ++j) {
-                    cik2[j] = ws.C[j][i * MP + k2];
-                    ci2k[j] = ws.C[j][i2 * MP + k];
-                    ci2k2[j] = ws.C[j][i2 * MP + k2];
                     const double a = ws.C[j][p * MP + p].x, b = ws.C[j][q * MP + q].x;
                     const double2 h = ws.C[j][p * MP + q];
                     off += cabs2(h);
@@ -227,7 +222,6 @@ __device__ int ajd_wave(const double2 (*S)[kMS], const double2* Pold, AjdScratch
                     g[4] = fma(h1, h2, g[4]);
                     g[5] = fma(h2, h2, g[5]);
                 }
-                vik2 = ws.V[i * MP + k2];
                 double ex, ey, ez;
                 if (q < M && off > tol2 * dia && off > 1e-300 && dominant_eig3(g, ex, ey, ez)) {
                     cs = sqrt(0.5 * (1.0 + ex));
@@ -245,6 +239,16 @@ __device__ int ajd_wave(const double2 (*S)[kMS], const double2* Pold, AjdScratch
             any_sweep = true;
             wave_lds_sync();
             if (act) {
+                // the partner entries of this round (C and V as written at its start; the next
+                // writes come after these reads in this wave's order)
+                double2 cik2[NC], ci2k[NC], ci2k2[NC];
+#pragma unroll
+                for (int j = 0; j < NC; ++j) {
+                    cik2[j] = ws.C[j][i * MP + k2];
+                    ci2k[j] = ws.C[j][i2 * MP + k];
+                    ci2k2[j] = ws.C[j][i2 * MP + k2];
+                }
+                const double2 vik2 = ws.V[i * MP + k2];
                 // column factors of this lane's k (pair (k, k2)), row factors of i (pair (i, i2))
                 const double2 gam = make_double2(cs, 0.0);
                 const double2 del = (k < k2) ? sn : make_double2(-sn.x, sn.y);   // s or -conj(s)
@@ -393,12 +397,14 @@ constexpr double kMultiTolFp64 = 1e-15;
 constexpr double kMultiTolFp32 = 1e-8;
 
 // Problem table entries: y_off, v_off (source j at + j v2_off), n, npad, pid.
-// Register budget: three workgroups per CU in float bulk with up to four
-// frames per thread (513 frequencies then run as one wave of workgroups on
-// 256 CUs); no cap otherwise (FP64 needs two workgroups' LDS per CU anyway).
+// Register budget in float bulk with up to four frames per thread: three
+// workgroups per CU for J = 2 (513 frequencies then run as one wave of
+// workgroups on 256 CUs), two for J >= 3 (their J power sums would spill
+// heavily at three); no cap otherwise (FP64 needs two workgroups' LDS per CU
+// anyway).
 template <int M, int J, typename T, int FPT>
 constexpr int multi_waves_per_eu() {
-    return (sizeof(T) == 4 && FPT <= 4) ? 3 : 1;
+    return (sizeof(T) == 4 && FPT <= 4) ? (J >= 3 ? 2 : 3) : 1;
 }
 
 template <int M, int J, typename T, int FPT>
