@@ -48,10 +48,11 @@ constexpr int kAjdMaxSweeps = 16;
 
 // ---------------------------------------------------------------- dominant eigenvector of a 3x3
 // Unit eigenvector (x, y, z), x >= 0, of the largest eigenvalue of the
-// symmetric G = [[g0, g1, g2], [g1, g3, g4], [g2, g4, g5]] (trigonometric
-// form of the characteristic cubic, then the longest cross product of two
-// rows of G - lambda I). False when no direction dominates (G a multiple of
-// the identity, zero included, or a repeated largest eigenvalue).
+// symmetric G = [[g0, g1, g2], [g1, g3, g4], [g2, g4, g5]] (the largest
+// root of the characteristic cubic by monotone Newton steps, then the
+// longest cross product of two rows of G - lambda I). False when no
+// direction dominates (G a multiple of the identity, zero included, or a
+// repeated largest eigenvalue).
 __device__ bool dominant_eig3(const double (&g)[6], double& x, double& y, double& z) {
     const double m = (g[0] + g[3] + g[5]) * (1.0 / 3.0);
     const double a = g[0] - m, b = g[3] - m, c = g[5] - m;
@@ -59,12 +60,22 @@ __device__ bool dominant_eig3(const double (&g)[6], double& x, double& y, double
     const double p2 = a * a + b * b + c * c + 2.0 * off;
     const double scale = fabs(g[0]) + fabs(g[3]) + fabs(g[5]);
     if (!(p2 > 1e-28 * scale * scale) || !(scale > 1e-300)) return false;
-    const double p = sqrt(p2 * (1.0 / 6.0));
-    const double ip = 1.0 / p;
-    const double B0 = a * ip, B3 = b * ip, B5 = c * ip, B1 = g[1] * ip, B2 = g[2] * ip, B4 = g[4] * ip;
-    const double det = B0 * (B3 * B5 - B4 * B4) - B1 * (B1 * B5 - B4 * B2) + B2 * (B1 * B4 - B3 * B2);
-    const double r = fmin(fmax(0.5 * det, -1.0), 1.0);
-    const double lam = m + 2.0 * p * cos(acos(r) * (1.0 / 3.0));
+    // the largest eigenvalue by Newton's method on the characteristic polynomial of the
+    // shifted matrix B = G - m I, q(t) = det(t I - B) = t^3 - k1 t - k0 (trace 0), from an
+    // upper bound of its largest root (the largest Gershgorin row sum): right of that root
+    // q is increasing and convex, so the iterates decrease monotonically onto it
+    const double k1 = 0.5 * p2;                        // sum of the squared entries / 2
+    const double k0 = a * (b * c - g[4] * g[4]) - g[1] * (g[1] * c - g[4] * g[2]) + g[2] * (g[1] * g[4] - b * g[2]);
+    double t = fmax(fabs(a) + fabs(g[1]) + fabs(g[2]), fmax(fabs(g[1]) + fabs(b) + fabs(g[4]), fabs(g[2]) + fabs(g[4]) + fabs(c)));
+    for (int it = 0; it < 48; ++it) {
+        const double q = (t * t - k1) * t - k0;
+        const double dq = 3.0 * t * t - k1;
+        if (!(q > 0.0) || !(dq > 0.0)) break;
+        const double step = q / dq;
+        t -= step;
+        if (step <= 2e-16 * t) break;
+    }
+    const double lam = m + t;
     const double r0[3] = {g[0] - lam, g[1], g[2]}, r1[3] = {g[1], g[3] - lam, g[4]}, r2[3] = {g[2], g[4], g[5] - lam};
     double best[3] = {0.0, 0.0, 0.0}, bn = 0.0;
     auto consider = [&](const double (&u)[3], const double (&w)[3]) {
@@ -222,8 +233,18 @@ __device__ int ajd_wave(const double2 (*S)[kMS], const double2* Pold, AjdScratch
                     g[4] = fma(h1, h2, g[4]);
                     g[5] = fma(h2, h2, g[5]);
                 }
+                // A pair whose rotation is provably below tol is left alone without solving for it:
+                // with the residual (0, g1, g2) of e1 as an eigenvector of G and the gap g0 - mu to
+                // the rest of the spectrum (mu, the largest eigenvalue of G's lower 2 x 2 block,
+                // bounds the others by interlacing), the dominant eigenvector u makes an angle phi
+                // with e1 of sin phi <= |(g1, g2)| / (g0 - mu) (Davis-Kahan), and the rotation it
+                // gives has |s|^2 = (1 - u0) / 2 <= sin^2 phi / 2. Skipped when that bound is below
+                // tol^2 / 8: the eigenvector's own test would skip the pair too.
+                const double hb = 0.5 * (g[3] - g[5]);
+                const double gap = g[0] - (0.5 * (g[3] + g[5]) + sqrt(hb * hb + g[4] * g[4]));
+                const bool tiny = gap > 0.0 && g[1] * g[1] + g[2] * g[2] <= 0.25 * tol2 * gap * gap;
                 double ex, ey, ez;
-                if (q < M && off > tol2 * dia && off > 1e-300 && dominant_eig3(g, ex, ey, ez)) {
+                if (q < M && off > tol2 * dia && off > 1e-300 && !tiny && dominant_eig3(g, ex, ey, ez)) {
                     cs = sqrt(0.5 * (1.0 + ex));
                     const double is2c = 0.5 / cs;
                     sn = make_double2(ey * is2c, ez * is2c);
