@@ -71,7 +71,7 @@ __device__ bool dominant_eig3(const double (&g)[6], double& x, double& y, double
         const double q = (t * t - k1) * t - k0;
         const double dq = 3.0 * t * t - k1;
         if (!(q > 0.0) || !(dq > 0.0)) break;
-        const double step = q / dq;
+        const double step = q * rcp_nr(dq);            // the step's rounding does not move the root
         t -= step;
         if (step <= 2e-16 * t) break;
     }
@@ -245,8 +245,9 @@ __device__ int ajd_wave(const double2 (*S)[kMS], const double2* Pold, AjdScratch
                 const bool tiny = gap > 0.0 && g[1] * g[1] + g[2] * g[2] <= 0.25 * tol2 * gap * gap;
                 double ex, ey, ez;
                 if (q < M && off > tol2 * dia && off > 1e-300 && !tiny && dominant_eig3(g, ex, ey, ez)) {
-                    cs = sqrt(0.5 * (1.0 + ex));
-                    const double is2c = 0.5 / cs;
+                    const double hc = 0.5 * (1.0 + ex), rc = rsqrt_nr(hc);   // hc >= 1/2
+                    cs = hc * rc;
+                    const double is2c = 0.5 * rc;
                     sn = make_double2(ey * is2c, ez * is2c);
                     rot = cabs2(sn) > tol2;
                     if (!rot) {
