@@ -417,7 +417,11 @@ def run_large(args):
                    "ll_gain_after_1_iteration_where_chosen": float((ll_l - ll_p)[chosen].sum())}
     ms_step, em_ms = run.timed(args.steps, args.warmup)
     flags = fca.fca_status_per_freq(run.ctx)
-    run_R, run_v = run.R, run.v
+    run_R, run_v = run.R[: 2 * F * M * M].clone(), run.v[: 2 * F * N].clone()   # mixture 0
+    # in-run baseline: the conventional frame-wise EM on the same batch and start (its frames are
+    # streamed from memory every pass too), one step after one warm-up step
+    _, conv_ms = run.timed(1, 1, conventional=True, separate=False)
+    conv_flags = fca.fca_status_per_freq(run.ctx)
     run.close()
     updates = B * F * N * L
     rec = base_record(args, updates / (ms_step * 1e-3), ms_step,
@@ -430,6 +434,11 @@ def run_large(args):
     rec["roofline"] = roofline_entry(em_ms, bts, flop_per_update(M) * updates, None,
                                      "em_stream_kernel (frames re-read every iteration)")
     rec["flagged_frequencies"] = int((flags != 0).sum())
+    rec["in_run_baseline"] = {"kernel": "conv_stream_kernel (conventional frame-wise EM, same workload, frames "
+                                        "streamed)",
+                              "kernel_ms_per_step": conv_ms, "updates_per_s": updates / (conv_ms * 1e-3),
+                              "fastfca_kernel_speedup": conv_ms / em_ms,
+                              "flagged_frequencies": int((conv_flags != 0).sum())}
     if learned:
         rec["learned_start"] = learned
     # error against the FP64 oracle on a subsample: mixture 0, 8 evenly spaced

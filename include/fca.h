@@ -155,8 +155,9 @@ fca_status fca_em_step(fca_ctx *c, int32_t iters, double *loglik, double *R_out,
  * eigendecomposition), on the same context and with the same arguments,
  * outputs and failure semantics as fca_em_step. The paper states the two
  * algorithms produce identical iterates; this entry point is the in-run
- * baseline of that comparison. Requires N <= 2048 for every mixture
- * (FCA_E_ARG otherwise). */
+ * baseline of that comparison. Mixtures of more than 2048 frames re-read
+ * their frames from memory every pass (powers double-buffered, as in
+ * fca_em_step's streamed shape); the others keep them in registers. */
 fca_status fca_conv_em_step(fca_ctx *c, int32_t iters, double *loglik, double *R_out, void *v_out);
 
 /* MMSE source images with the current parameters (eq. MMSE; Algorithm 1,

@@ -996,16 +996,16 @@ hipError_t launch_em(int M, bool fp64, int nt, int fpt, const EmProblem* probs, 
 }
 
 hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y, void* v,
-                          double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride,
-                          int iters, int it_base, hipStream_t s) {
+                          int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll,
+                          int64_t ll_stride, int iters, int it_base, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     switch (M) {
 #define FCA_CONV_CASE(MM_)                                                                                         \
     case MM_:                                                                                                      \
-        return fp64 ? launch_conv_fpt<MM_, double>(fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride, \
-                                                    iters, it_base, s)                                             \
-                    : launch_conv_fpt<MM_, float>(fpt, probs, count, y, v, P, lam, logdet, flags, ll, ll_stride,   \
-                                                   iters, it_base, s);
+        return fp64 ? launch_conv_fpt<MM_, double>(fpt, probs, count, y, v, v_alt, P, lam, logdet, flags, ll,     \
+                                                    ll_stride, iters, it_base, s)                                  \
+                    : launch_conv_fpt<MM_, float>(fpt, probs, count, y, v, v_alt, P, lam, logdet, flags, ll,       \
+                                                   ll_stride, iters, it_base, s);
         FCA_CONV_CASE(1) FCA_CONV_CASE(2) FCA_CONV_CASE(3) FCA_CONV_CASE(4)
         FCA_CONV_CASE(5) FCA_CONV_CASE(6) FCA_CONV_CASE(7) FCA_CONV_CASE(8)
 #undef FCA_CONV_CASE
@@ -1054,8 +1054,8 @@ fca_status enqueue_em_groups(fca_ctx* c, const std::vector<Group>& groups, const
         hipStream_t gs = s;
         if (nside > 0 && i != big) gs = c->side[(k++) % nside];
         if (conventional)
-            FCA_HIP(c, launch_conv_em(g.M, c->fp64, g.fpt, probs + g.first, g.count, c->y, c->v, c->P, c->lam,
-                                      c->logdet, c->flags, c->ll, c->nprob, chunk, it_base, gs));
+            FCA_HIP(c, launch_conv_em(g.M, c->fp64, g.fpt, probs + g.first, g.count, c->y, c->v, c->v_alt, c->P,
+                                      c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, it_base, gs));
         else
             FCA_HIP(c, launch_em(g.M, c->fp64, g.nt, g.run_fpt, probs + g.first, g.count, c->y, c->v, c->v_alt,
                                  c->P, c->lam, c->logdet, c->flags, c->ll, c->nprob, chunk, it_base, gs));
@@ -1127,13 +1127,6 @@ fca_status em_step_impl(fca_ctx* c, int32_t iters, double* loglik, double* R_out
     }
     const std::vector<Group>& groups = c->all_active ? c->groups : c->groups_act;
     const EmProblem* probs = c->all_active ? c->probs : c->probs_act;
-    if (conventional) {
-        for (const Group& g : groups)
-            if (g.fpt == 0) {
-                set_err(c, "the conventional EM kernel keeps frames in registers: N <= %d", kMaxFrames);
-                return FCA_E_ARG;
-            }
-    }
     const hipStream_t s = c->stream;
     const bool ll_dev = loglik && is_device_ptr(loglik);
     int done = 0;

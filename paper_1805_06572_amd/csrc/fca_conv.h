@@ -366,14 +366,157 @@ __global__ __launch_bounds__(kEmThreads) void conv_em_kernel(
     }
 }
 
+// The same iteration for problems with more frames than fit in registers:
+// every pass re-reads y and the powers in chunks of kEmThreads frames (one
+// per thread). The powers are double-buffered (second buffer at v + v_alt)
+// as in em_stream_kernel: pass l reads theta^(l)'s powers from one buffer and
+// writes the new ones to the other, so a problem that freezes keeps its last
+// complete iterate; on exit the committed powers are in the first buffer.
+// A thread meets its frames in the order the resident kernel keeps them, so
+// the sums, and the results, equal that kernel's bit for bit.
 template <int M, typename T>
-hipError_t launch_conv_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v, double2* P,
-                                  double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride, int iters,
-                                  int it_base, hipStream_t s) {
+__global__ __launch_bounds__(kEmThreads) void conv_stream_kernel(
+    const EmProblem* __restrict__ probs, const typename Vec2<T>::type* __restrict__ y, T* __restrict__ v,
+    int64_t v_alt, double2* __restrict__ Pg, double* __restrict__ lamg, double* __restrict__ logdetg,
+    int* __restrict__ flagsg, double* __restrict__ ll, int64_t ll_stride, int iters, int it_base) {
+    using T2 = typename Vec2<T>::type;
+    constexpr int NT = kEmThreads;
+    constexpr int MM = M * M, NV = 2 * MM, NW = kEmThreads / 64;
+    __shared__ ConvShared<M, T> sh;
+    const EmProblem pr = probs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int nf = pr.n, npad = pr.npad, pid = pr.pid;
+    const int ll_count = iters > 0 ? iters : 1;
+
+    if (tid < MM) sh.Id[tid] = make_double2((tid % (M + 1)) == 0 ? 1.0 : 0.0, 0.0);
+    if (tid == 0) {
+        sh.flag = flagsg[pid];
+        sh.bad = 0;
+        double2 X[M][M];
+        invert<M>(Pg + (int64_t)pid * kMaxM * kMaxM, X);
+        const double* lm = lamg + (int64_t)pid * kMaxM;
+        for (int a = 0; a < M; ++a)
+            for (int b = 0; b < M; ++b) {
+                double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+                for (int k = 0; k < M; ++k) {
+                    const double2 t = cmulc(X[k][b], X[k][a]);
+                    s2 = cadd(s2, t);
+                    s1 = cadd(s1, cscale(lm[k], t));
+                }
+                if (a == b) { s1.y = 0.0; s2.y = 0.0; }
+                sh.S[0][a * M + b] = s1;
+                sh.S[1][a * M + b] = s2;
+            }
+    }
+    __syncthreads();
+    const T2* __restrict__ yb = y + pr.y_off;
+    const bool frozen_at_entry = (sh.flag & kFreezeMask) != 0;
+    const int passes = (iters > 0 && !frozen_at_entry) ? iters : 1;
+    const bool write_v = iters > 0 && !frozen_at_entry;
+    int cur = 0;
+    for (int it = 0; it < passes; ++it) {
+        if (tid == 0) {
+            double2 X1[M][M], X2[M][M];
+            const bool ok1 = invert<M>(sh.S[0], X1);
+            const bool ok2 = invert<M>(sh.S[1], X2);
+            if (!ok1 || !ok2) sh.bad = 1;
+            for (int a = 0; a < M; ++a)
+                for (int b = 0; b < M; ++b) {
+                    const int e = a * M + b;
+                    sh.Sold[0][e] = sh.S[0][e];
+                    sh.Sold[1][e] = sh.S[1][e];
+                    sh.St[0][e] = make_vec2<T>((T)sh.S[0][e].x, (T)sh.S[0][e].y);
+                    sh.St[1][e] = make_vec2<T>((T)sh.S[1][e].x, (T)sh.S[1][e].y);
+                    sh.Si[0][e] = make_vec2<T>((T)X1[a][b].x, (T)X1[a][b].y);
+                    sh.Si[1][e] = make_vec2<T>((T)X2[a][b].x, (T)X2[a][b].y);
+                }
+        }
+        __syncthreads();
+        T acc[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] = T(0);
+        double llacc = 0.0;
+        bool bad = false;
+        const T* __restrict__ vin = v + (cur ? v_alt : 0) + pr.v_off;
+        T* __restrict__ vout = v + (cur ? 0 : v_alt) + pr.v_off;
+        for (int base = 0; base < nf; base += NT) {
+            const int n = base + tid;
+            const bool ok = n < nf;
+            const int nc = ok ? n : nf - 1;   // lanes past the last frame load it and are masked
+            T yr[M], yi[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const T2 val = yb[(int64_t)m * npad + nc];
+                yr[m] = ok ? val.x : T(0);
+                yi[m] = ok ? val.y : T(0);
+            }
+            const T a1 = ok ? vin[nc] : T(1), a2 = ok ? vin[pr.v2_off + nc] : T(1);
+            T n1 = a1, n2 = a2;
+            conv_bin<M, T>(yr, yi, a1, a2, sh.St[0], sh.St[1], sh.Si[0], sh.Si[1], ok, acc, llacc, n1, n2, bad);
+            if (ok && write_v) {
+                vout[n] = n1;
+                vout[pr.v2_off + n] = n2;
+            }
+        }
+        if (bad) sh.bad = 1;
+        wg_reduce_sums<M>(sh, acc, llacc, nf, tid, nullptr);
+        if (tid == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < NW; ++w) tot += sh.LL[w];
+            tot += -(double)nf * (double)M * kLogPi;
+            const bool last = (iters == 0) || frozen_at_entry;
+            if (last) {
+                for (int l = it; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
+            } else {
+                ll[(int64_t)it * ll_stride + pid] = tot;
+                bool finite = true;
+                for (int e = 0; e < MM; ++e) finite = finite && cfinite(sh.S[0][e]) && cfinite(sh.S[1][e]);
+                if (sh.bad || !finite) {
+                    sh.flag |= kFlagNonFinite | ((it_base + it + 1) << kFlagIterShift);
+                    for (int e = 0; e < MM; ++e) {
+                        sh.S[0][e] = sh.Sold[0][e];
+                        sh.S[1][e] = sh.Sold[1][e];
+                    }
+                    for (int l = it + 1; l < ll_count; ++l) ll[(int64_t)l * ll_stride + pid] = tot;
+                }
+            }
+        }
+        __syncthreads();
+        if (iters == 0 || frozen_at_entry || (sh.flag & kFreezeMask)) break;
+        cur ^= 1;
+    }
+
+    if (write_v) {
+        if (cur) {
+            for (int n = tid; n < nf; n += NT) {
+                v[pr.v_off + n] = v[v_alt + pr.v_off + n];
+                v[pr.v_off + pr.v2_off + n] = v[v_alt + pr.v_off + pr.v2_off + n];
+            }
+        }
+        if (tid < 64) {
+            double dld = 0.0;
+            const int flag = gevd_wave<M>(sh.S[0], sh.S[1], sh.Id, sh.ws, sh.Pn, sh.lamN, &dld, 1e-30);
+            wave_lds_sync();
+            if (!(flag & kFreezeMask)) {
+                if (tid < MM) Pg[(int64_t)pid * kMaxM * kMaxM + tid] = sh.Pn[tid];
+                if (tid < M) lamg[(int64_t)pid * kMaxM + tid] = sh.lamN[tid];
+                if (tid == 0) logdetg[pid] = dld;
+            }
+            if (tid == 0) flagsg[pid] = sh.flag | (flag & kFreezeMask);
+        }
+    }
+}
+
+// fpt 0: the streamed kernel (powers double-buffered at v + v_alt).
+template <int M, typename T>
+hipError_t launch_conv_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v, int64_t v_alt,
+                           double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride,
+                           int iters, int it_base, hipStream_t s) {
     using T2 = typename Vec2<T>::type;
     const T2* yy = static_cast<const T2*>(y);
     T* vv = static_cast<T*>(v);
     switch (fpt) {
+        case 0: conv_stream_kernel<M, T><<<count, kEmThreads, 0, s>>>(probs, yy, vv, v_alt, P, lam, logdet, flags, ll, ll_stride, iters, it_base); break;
         case 1: conv_em_kernel<M, T, 1><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base); break;
         case 2: conv_em_kernel<M, T, 2><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base); break;
         case 4: conv_em_kernel<M, T, 4><<<count, kEmThreads, 0, s>>>(probs, yy, vv, P, lam, logdet, flags, ll, ll_stride, iters, it_base); break;

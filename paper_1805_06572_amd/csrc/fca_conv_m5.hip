@@ -2,6 +2,6 @@
 #include "fca_conv.h"
 
 namespace fca {
-template hipError_t launch_conv_fpt<5, float>(int fpt, const EmProblem* probs, int count, const void* y, void* v, double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride, int iters, int it_base, hipStream_t s);
-template hipError_t launch_conv_fpt<5, double>(int fpt, const EmProblem* probs, int count, const void* y, void* v, double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride, int iters, int it_base, hipStream_t s);
+template hipError_t launch_conv_fpt<5, float>(int fpt, const EmProblem* probs, int count, const void* y, void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride, int iters, int it_base, hipStream_t s);
+template hipError_t launch_conv_fpt<5, double>(int fpt, const EmProblem* probs, int count, const void* y, void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride, int iters, int it_base, hipStream_t s);
 }  // namespace fca

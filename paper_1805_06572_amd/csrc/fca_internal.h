@@ -74,12 +74,13 @@ hipError_t launch_em(int M, bool fp64, int nt, int fpt, const EmProblem* probs, 
 // fca_conv_lo.hip and fca_conv_m5.hip .. fca_conv_m8.hip, and the dispatch
 // on M and precision (fca_api.hip).
 template <int M, typename T>
-hipError_t launch_conv_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v, double2* P,
-                           double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride, int iters,
-                           int it_base, hipStream_t s);
+hipError_t launch_conv_fpt(int fpt, const EmProblem* probs, int count, const void* y, void* v, int64_t v_alt,
+                           double2* P, double* lam, double* logdet, int* flags, double* ll, int64_t ll_stride,
+                           int iters, int it_base, hipStream_t s);
 
+// fpt 0: frames streamed (the powers double-buffered at v + v_alt elements).
 hipError_t launch_conv_em(int M, bool fp64, int fpt, const EmProblem* probs, int count, const void* y,
-                          void* v, double2* P, double* lam, double* logdet, int* flags, double* ll,
+                          void* v, int64_t v_alt, double2* P, double* lam, double* logdet, int* flags, double* ll,
                           int64_t ll_stride, int iters, int it_base, hipStream_t s);
 
 // Support kernels (fca_kernels.hip).

@@ -606,15 +606,48 @@ def test_conventional_kernel_fp32_array_workload(fca, array_workload):
     assert err_v[:, gate].max() < 1e-4
 
 
-def test_conventional_kernel_rejects_streamed_mixtures(fca):
-    mx = synth.random_mixture(2, 2, 2100, 5)
+@pytest.mark.parametrize("M,F,N,iters", [(2, 3, 2100, 4), (3, 2, 2600, 3), (8, 1, 2049, 2)])
+def test_streamed_conventional_kernel_matches_oracle(fca, M, F, N, iters):
+    """More frames than the registers hold (N > 2048): the conventional
+    kernel re-reads the frames every pass (powers double-buffered), FP64
+    parity with the oracle as for the resident kernel."""
+    mx = synth.random_mixture(M, F, N, 400 + M)
+    S0, v0 = oracle.default_init(mx.y)
+    S, v, ll, flags = oracle.em(mx.y, S0, v0, iters, threads=8)
     ctx = fca.fca_init(torch.from_numpy(mx.y).to(DEV), prec=fca.FCA_FP64)
     try:
-        with pytest.raises(fca.FcaError) as ei:
-            fca.fca_conv_em_step(ctx, 1)
-        assert ei.value.status == fca.FCA_E_ARG
+        gll, gR, gv = fca.fca_conv_em_step(ctx, iters)
     finally:
         fca.fca_destroy(ctx)
+    assert per_freq_rel(gv[0].cpu().numpy(), v, (-1,)).max() < 1e-10
+    assert per_freq_rel(gR[0].cpu().numpy(), S, (-2, -1)).max() < 1e-10
+    np.testing.assert_allclose(gll.cpu().numpy()[0], ll[:iters].sum(1), rtol=1e-10)
+
+
+def test_streamed_kernels_interleave_in_a_batch(fca):
+    """A batch of one streamed (N = 2300) and one resident mixture: 2 FastFCA,
+    3 conventional (odd, so the streamed powers end in the second buffer and
+    are copied back) and 2 FastFCA iterations equal 7 oracle iterations of
+    each; float bulk on the same batch stays within the float tolerance."""
+    mxs = [synth.random_mixture(2, 3, 2300, 81), synth.random_mixture(2, 3, 500, 82)]
+    want = []
+    for mx in mxs:
+        S0, v0 = oracle.default_init(mx.y)
+        want.append(oracle.em(mx.y, S0, v0, 7, threads=8))
+    for prec, tol in ((fca.FCA_FP64, 1e-10), (fca.FCA_FP32_BULK, 1e-3)):
+        dt = np.complex128 if prec == fca.FCA_FP64 else np.complex64
+        ctx = fca.fca_init_batch([torch.from_numpy(mx.y.astype(dt)).to(DEV) for mx in mxs], prec=prec)
+        try:
+            l1, _, _ = fca.fca_em_step(ctx, 2, want_R=False, want_v=False)
+            l2, _, _ = fca.fca_conv_em_step(ctx, 3, want_R=False, want_v=False)
+            l3, gR, gv = fca.fca_em_step(ctx, 2)
+        finally:
+            fca.fca_destroy(ctx)
+        for b, (S, v, ll, _) in enumerate(want):
+            gll = np.r_[l1.cpu().numpy()[b], l2.cpu().numpy()[b], l3.cpu().numpy()[b]]
+            np.testing.assert_allclose(gll, ll[:7].sum(1), rtol=tol)
+            assert per_freq_rel(gv[b].cpu().numpy().astype(np.float64), v, (-1,)).max() < tol
+            assert per_freq_rel(gR[b].cpu().numpy(), S, (-2, -1)).max() < tol
 
 
 def test_loglik_per_freq_matches_oracle(fca):
