@@ -182,17 +182,17 @@ struct alignas(2 * sizeof(T)) Cx {
 // FP64 the 16 KiB would halve the resident workgroups, so they are read from
 // the constant table)
 template <typename T> struct Shape;
-// kPrefetch (analysis), kPrefetchSyn (synthesis): the next block's input is
-// loaded into registers while the current one is transformed (FP32; in FP64
-// the registers do not suffice). kWaves: waves per SIMD that the LDS lets
-// reside (two workgroups per CU), the register budget.
+// kPrefetchSyn: synthesis loads the next block's bins into registers while
+// the current one is transformed (FP32; in FP64 the registers do not
+// suffice; analysis measured faster without). kWaves: waves per SIMD that
+// the LDS lets reside (two workgroups per CU), the register budget.
 template <> struct Shape<float> {
     static constexpr int kQ = 16, kThreads = 256, kWaves = 2;
-    static constexpr bool kLdsTw = true, kPrefetch = false, kPrefetchSyn = true;
+    static constexpr bool kLdsTw = true, kPrefetchSyn = true;
 };
 template <> struct Shape<double> {
     static constexpr int kQ = 8, kThreads = 128, kWaves = 1;
-    static constexpr bool kLdsTw = false, kPrefetch = false, kPrefetchSyn = false;
+    static constexpr bool kLdsTw = false, kPrefetchSyn = false;
 };
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
@@ -364,13 +364,12 @@ __device__ __forceinline__ void copy_roots(Cx<T>* twl) {
         for (int k = threadIdx.x; k < 1024; k += Shape<T>::kThreads) twl[k] = kTab<T>.tw[k >> 5][k & 31];
 }
 
-// X[f][q] for blocks of kQ transforms q = n M + m (nq = N M), f <= 512. The
-// next block's samples are loaded while the current one is transformed.
+// X[f][q] for blocks of kQ transforms q = n M + m (nq = N M), f <= 512.
 template <typename T>
 __global__ __launch_bounds__(Shape<T>::kThreads) __attribute__((amdgpu_waves_per_eu(Shape<T>::kWaves))) void stft1024_kernel(const T* __restrict__ x, int64_t T_len, int M,
                                                                       int64_t nq, Cx<T>* __restrict__ X) {
     constexpr int kQ = Shape<T>::kQ, kThreads = Shape<T>::kThreads;
-    constexpr bool kLdsTw = Shape<T>::kLdsTw, kPrefetch = Shape<T>::kPrefetch;
+    constexpr bool kLdsTw = Shape<T>::kLdsTw;
     extern __shared__ __align__(16) unsigned char smem[];
     Cx<T>* lds = reinterpret_cast<Cx<T>*>(smem);
     Cx<T>* twl = lds + (kQ / 2) * kRegion;
@@ -379,84 +378,43 @@ __global__ __launch_bounds__(Shape<T>::kThreads) __attribute__((amdgpu_waves_per
     const int p = threadIdx.x >> 5, l = threadIdx.x & 31;
     const bool narrow = nq <= 0xffffffffLL;
     copy_roots<T, kLdsTw>(twl);
-    T win[kPrefetch ? 32 : 1];
-    if (kPrefetch) {
-#pragma unroll
-        for (int k = 0; k < 32; ++k) win[k] = kTab<T>.win[l + 32 * k];
-    }
-    // frame sources of the pair: real part transform q0 + 2p, imaginary part
-    // q0 + 2p + 1; inner: both frames exist and lie wholly inside the signal
-    struct Src {
-        const T* xa;
-        const T* xb;
-        int64_t sa, sb;
-        bool va, vb, inner;
-    };
-    auto source = [&](int64_t blk) {
-        const int64_t qa = blk * kQ + 2 * p, qb = qa + 1;
-        const int64_t ca = qa < nq ? qa : nq - 1, cb = qb < nq ? qb : nq - 1;
-        const int64_t na = div_small(ca, M, narrow), nb = div_small(cb, M, narrow);
-        const int64_t sa = na * kS - kS, sb = nb * kS - kS;
-        const bool inner = qb < nq && sa >= 0 && sa + kL <= T_len && sb >= 0 && sb + kL <= T_len;
-        return Src{x + (ca - na * M) * T_len, x + (cb - nb * M) * T_len, sa, sb, qa < nq, qb < nq, inner};
-    };
+    __syncthreads();                                   // roots in LDS
     // edge frames: loads from clamped indices, unconditionally; samples outside the signal count as zero
     auto clamp = [&](int64_t s1) { return s1 < 0 ? 0 : (s1 < T_len ? s1 : T_len - 1); };
-    T ra[kPrefetch ? 32 : 1], rb[kPrefetch ? 32 : 1];
-    auto issue = [&](const Src& sr) {
-        if (sr.inner) {
-            const T* pa = sr.xa + sr.sa + l;
-            const T* pb = sr.xb + sr.sb + l;
-#pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                ra[k] = pa[32 * k];
-                rb[k] = pb[32 * k];
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                ra[k] = sr.xa[clamp(sr.sa + l + 32 * k)];
-                rb[k] = sr.xb[clamp(sr.sb + l + 32 * k)];
-            }
-        }
-    };
-    int64_t blk = sh.begin;
-    Src cur = source(blk);
-    if (kPrefetch) issue(cur);
-    __syncthreads();                                   // roots in LDS
     const T half = (T)0.5;
     const int oi = threadIdx.x % kQ;                   // output transform of this thread (kThreads is a multiple of kQ)
     const bool odd = oi & 1;
     constexpr int kFStep = kThreads / kQ;
-    for (;;) {
+    for (int64_t blk = sh.begin; blk < sh.end; blk += sh.step) {
         const Tables<T>* tab = tables<T>();
+        // real part: transform q0 + 2p, imaginary part: q0 + 2p + 1
+        const int64_t qa = blk * kQ + 2 * p, qb = qa + 1;
+        const int64_t ca = qa < nq ? qa : nq - 1, cb = qb < nq ? qb : nq - 1;
+        const int64_t na = div_small(ca, M, narrow), nb = div_small(cb, M, narrow);
+        const T* xa = x + (ca - na * M) * T_len;
+        const T* xb = x + (cb - nb * M) * T_len;
+        const int64_t sa = na * kS - kS, sb = nb * kS - kS;
         Cx<T> d[32];
-        if (cur.inner) {
-            const T* pa = cur.xa + cur.sa + l;
-            const T* pb = cur.xb + cur.sb + l;
+        if (qb < nq && sa >= 0 && sa + kL <= T_len && sb >= 0 && sb + kL <= T_len) {   // both frames inside
+            const T* pa = xa + sa + l;
+            const T* pb = xb + sb + l;
 #pragma unroll
             for (int k = 0; k < 32; ++k) {
-                const T w = kPrefetch ? win[k] : tab->win[l + 32 * k];
-                d[k].x = w * (kPrefetch ? ra[k] : pa[32 * k]);
-                d[k].y = w * (kPrefetch ? rb[k] : pb[32 * k]);
+                const T w = tab->win[l + 32 * k];
+                d[k].x = w * pa[32 * k];
+                d[k].y = w * pb[32 * k];
             }
         } else {
+            const bool va = qa < nq, vb = qb < nq;
 #pragma unroll
             for (int k = 0; k < 32; ++k) {
-                const int64_t s1 = cur.sa + l + 32 * k, s2 = cur.sb + l + 32 * k;
-                const bool in1 = cur.va && s1 >= 0 && s1 < T_len, in2 = cur.vb && s2 >= 0 && s2 < T_len;
-                const T w = kPrefetch ? win[k] : tab->win[l + 32 * k];
-                const T y1 = kPrefetch ? ra[k] : cur.xa[clamp(s1)];
-                const T y2 = kPrefetch ? rb[k] : cur.xb[clamp(s2)];
+                const int64_t s1 = sa + l + 32 * k, s2 = sb + l + 32 * k;
+                const bool in1 = va && s1 >= 0 && s1 < T_len, in2 = vb && s2 >= 0 && s2 < T_len;
+                const T w = tab->win[l + 32 * k];
+                const T y1 = xa[clamp(s1)], y2 = xb[clamp(s2)];
                 d[k].x = in1 ? w * y1 : (T)0;
                 d[k].y = in2 ? w * y2 : (T)0;
             }
-        }
-        const int64_t nxt = blk + sh.step;
-        const bool more = nxt < sh.end;
-        if (more) {
-            cur = source(nxt);
-            if (kPrefetch) issue(cur);
         }
         Cx<T>* E = lds + p * kRegion;
         fft1024<false, kLdsTw, T>(d, E, twl, tab, l);
@@ -476,9 +434,7 @@ __global__ __launch_bounds__(Shape<T>::kThreads) __attribute__((amdgpu_waves_per
                 *out = Cx<T>{(p1 + p2) * half, (p3 - p4) * half};
             }
         }
-        if (!more) break;
         __syncthreads();                                 // the spectra are read out
-        blk = nxt;
     }
 }
 
