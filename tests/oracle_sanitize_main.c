@@ -1,7 +1,7 @@
 /* Drives every entry point of the C oracle (oracle/fca_oracle.c) on small
  * inputs under AddressSanitizer and UndefinedBehaviorSanitizer: a random
  * mixture, one microphone, one frame, a silent mixture, and invalid sizes.
- * Inputs come from a fixed linear congruential generator; the driver checks
+ * Inputs come from a fixed linear congruential generator; this program checks
  * return codes and that outputs are finite, not values (the values are
  * pinned by the other oracle tests). Built and run by
  * tests/test_oracle_sanitizers.py. */
