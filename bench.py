@@ -17,6 +17,7 @@ time. Prints one JSON line with
     FP64) on the frequencies whose true covariances have condition number
     <= 1e3, and by condition-number class on the others;
   - the conventional-EM kernel timed on the same workload (in-run baseline);
+  - the same workload in the FP64 mode (time per step and its oracle error);
   - the CPU oracle's own throughput on the host's cores;
   - time to target (unless --no-ttt): held-out mixtures with AR(1) powers,
     plain FastFCA FP32 one mixture at a time against batched runs with and
@@ -312,6 +313,14 @@ def run_array(args):
     _, conv_ms = run.timed(conv_steps, 1, conventional=True, separate=False)
     conv_flags = fca.fca_status_per_freq(run.ctx)[0]
     run.close()
+    # the same workload in FP64 arithmetic throughout (the precise mode), eager steps
+    run64 = Runner(fca, [y.to(torch.complex128)], L, fca.FCA_FP64)
+    ms64, em64 = run64.timed(conv_steps, 1)
+    gR64 = run64.R.view(2, F, M, M).cpu().numpy()
+    gv64 = run64.v.view(2, F, N).cpu().numpy()
+    gll64 = fca.fca_loglik_per_freq(run64.ctx, L).cpu().numpy()[:, 0]
+    flags64 = fca.fca_status_per_freq(run64.ctx)[0]
+    run64.close()
 
     updates = F * N * L
     rec = base_record(args, updates / (ms_step * 1e-3), ms_step,
@@ -329,6 +338,9 @@ def run_array(args):
                               "kernel_ms_per_step": conv_ms, "updates_per_s": updates / (conv_ms * 1e-3),
                               "fastfca_kernel_speedup": conv_ms / em_ms,
                               "flagged_frequencies": int((conv_flags != 0).sum())}
+    rec["fp64_variant"] = {"dtype": "f64", "ms_per_step": ms64, "updates_per_s": updates / (ms64 * 1e-3),
+                           "em_kernel_ms_per_launch": em64, "flagged_frequencies": int((flags64 != 0).sum()),
+                           "step": "reset + em_step(loglik, R, v) + separate, eager"}
     rec["loglik_first_last"] = [float(lls[0]), float(lls[-1])]
     rec["flagged_frequencies"] = int((flags != 0).sum())
     rec["invariants"] = inv
@@ -344,6 +356,8 @@ def run_array(args):
         S, v, ll, oflags = oracle.em(y64, S0, v0, L, threads=cores)
         cpu_s = time.perf_counter() - t0
         rec["oracle_error"] = oracle_error(synth.condition_numbers(mx.R), oflags, flags, S, v, ll, gR, gv, gll_f)
+        rec["fp64_variant"]["oracle_error"] = oracle_error(synth.condition_numbers(mx.R), oflags, flags64, S, v, ll,
+                                                           gR64, gv64, gll64)
         rec["cpu_baseline"] = {"value": updates / cpu_s, "unit": "updates/s", "cores": cores, "kind": "oracle",
                                "sample": f"{F}/{F} frequencies x {N} frames (1 mixture), {L} iterations of the "
                                          f"conventional FCA EM in FP64 ({cpu_s:.2f} s wall)"}
