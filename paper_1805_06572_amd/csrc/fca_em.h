@@ -550,10 +550,14 @@ template <int M> struct PassAcc<M, float, true> {
 // thread), two otherwise (eight frames per thread spill at three). FP64 at
 // M = 4 with eight frames keeps the request of three, which the compiler
 // cannot meet: it then takes accumulation registers at one workgroup per CU,
-// where a request of two makes it spill to scratch instead.
+// where a request of two makes it spill to scratch instead. FP64 at M = 4 with four
+// frames asks for two: 188 bytes of scratch per lane, but two workgroups per
+// CU instead of one (513 frequencies in two waves of workgroups instead of
+// three; 1.45 -> 1.19 ms per 50-iteration launch at M = 4, N = 1000).
 template <int M, typename T, int FPT>
 constexpr int em_waves_per_eu() {
     if (M == 4 && sizeof(T) == 8 && FPT == 8) return 3;
+    if (M == 4 && sizeof(T) == 8 && FPT == 4) return 2;
     return (M <= 4 && FPT <= 4) ? 3 : 2;
 }
 
