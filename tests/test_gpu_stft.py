@@ -40,6 +40,7 @@ def rel(a, b):
     # transforms; synthesis overlaps them by M (M <= 8 or 4) or splits them (larger M)
     ("fp32", 1024, 1, 700), ("fp32", 1024, 9, 3001), ("fp32", 1024, 4, 9 * 1024 + 17),
     ("fp64", 1024, 5, 2500), ("fp64", 1024, 3, 100), ("fp32", 1024, 17, 1537),
+    ("fp32", 1024, 2, 1), ("fp64", 1024, 1, 512), ("fp32", 1024, 3, 1024), ("fp64", 1024, 9, 1537),
 ])
 def test_stft_and_istft_match_oracle(fca, prec, L, M, T):
     rng = np.random.default_rng(L + M + T)
